@@ -1,0 +1,318 @@
+"""Benchmark of the masked differentiable rasterizer on one MI355X.
+
+Headline: masked forward+backward throughput (Mpixels/s of building-mask
+pixels) on the 1M-Gaussian, 1920x1080, SH-degree-3 workload with a ~40%
+rectangle-union mask.  One step = the whole hot path over that batch:
+tile-mask reduce, projection, depth sort, binning, tile sort, compositing
+with the depth epilogue, backward compositing and backward projection,
+driven by a fixed upstream gradient (N(0,1) on masked pixels).  Inputs are
+resident in HBM before the timed region.
+
+Also reported: per-stage times (HIP events on the launch stream, recorded
+inside the timed steps), the roofline of the dominant kernel, the FP64
+oracle timed on a bounded pixel sample on the host cores, and (unless
+--no-batched) the batched-versus-per-region speedup on the 16-sub-region x
+4-view workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import ctypes as C
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+# Algorithmic FP32 operations per blended (pixel, Gaussian) pair, counted
+# from the arithmetic of the method (see the kernel docs):
+#  forward: alpha (14) + transmittance update and 7-channel blend (18)
+#  backward: alpha (14) + transmittance recovery (4) + dL/dalpha and the
+#            7-channel feature gradients and suffix sums (58) + conic, mean
+#            and opacity gradients (22)
+FLOPS_PER_BLEND_FWD = 32
+FLOPS_PER_BLEND_BWD = 98
+
+
+class HipEvents:
+    """hipEvent_t handles created through the HIP runtime (timing only)."""
+
+    def __init__(self, n):
+        self.hip = C.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.hip.hipEventSynchronize.argtypes = [C.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [C.c_void_p]
+        self.ev = []
+        for _ in range(n):
+            e = C.c_void_p()
+            rc = self.hip.hipEventCreate(C.byref(e))
+            if rc != 0:
+                raise RuntimeError(f"hipEventCreate failed ({rc})")
+            self.ev.append(e.value)
+
+    def elapsed_ms(self, a, b):
+        self.hip.hipEventSynchronize(C.c_void_p(self.ev[b]))
+        out = C.c_float()
+        rc = self.hip.hipEventElapsedTime(C.byref(out), C.c_void_p(self.ev[a]), C.c_void_p(self.ev[b]))
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
+        return out.value
+
+    def close(self):
+        for e in self.ev:
+            self.hip.hipEventDestroy(C.c_void_p(e))
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_batch(scene, cfg, torch):
+    from paper_2501_01677_amd.raster import Batch, gaussians_to_device
+    sets = [gaussians_to_device(s) for s in scene.sets]
+    renders = []
+    for rd in scene.renders:
+        m = None if rd.mask is None else torch.from_numpy(np.ascontiguousarray(rd.mask)).cuda()
+        renders.append(dict(set=rd.set_index, camera=rd.camera, mask=m))
+    return Batch(sets, renders, cfg)
+
+
+def fill_gouts(batch, scene, seed, torch):
+    import scenes
+    for r, rd in enumerate(scene.renders):
+        g = scenes.grad_outputs(seed + r, rd, scale={"depth": 0.05})
+        for k, v in g.items():
+            batch.gout[r][k].copy_(torch.from_numpy(v).reshape(batch.gout[r][k].shape))
+
+
+def timed_steps(batch, steps, warmup, torch, events=True):
+    """Runs warmup + timed forward/backward steps; returns wall ms/step and
+    the mean per-stage times (ms) over the timed steps."""
+    from paper_2501_01677_amd import _abi as A
+    batch.forward()            # replans the pair capacity if needed
+    batch.fit_capacity(1.1)
+    for _ in range(warmup):
+        batch.forward(check_overflow=False)
+        batch.backward()
+    torch.cuda.synchronize()
+    ev = HipEvents(2 * A.NUM_STAGES * steps) if events else None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        e = None if ev is None else ev.ev[2 * A.NUM_STAGES * k:2 * A.NUM_STAGES * (k + 1)]
+        batch.forward(check_overflow=False, events=e)
+        batch.backward(events=e)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    st = batch.status()
+    if st.overflow:
+        raise RuntimeError("pair capacity overflow inside the timed region")
+    stage = {}
+    if ev is not None:
+        for s, name in enumerate(A.STAGES):
+            tot = 0.0
+            for k in range(steps):
+                base = 2 * A.NUM_STAGES * k
+                tot += ev.elapsed_ms(base + 2 * s, base + 2 * s + 1)
+            stage[name] = tot / steps
+        ev.close()
+    return wall, stage
+
+
+def roofline(stage, batch, scene, torch):
+    """Roofline entry of the dominant stage."""
+    dom = max(stage, key=stage.get)
+    t = stage[dom] * 1e-3
+    blends = float(sum(int(o["n_contrib"].sum().item()) for o in batch.out))
+    if dom in ("composite", "backward_composite"):
+        per = FLOPS_PER_BLEND_FWD if dom == "composite" else FLOPS_PER_BLEND_BWD
+        work = per * blends
+        ach = work / t / 1e12
+        return dom, dict(bound="alu", achieved=round(ach, 3), peak=FP32_VECTOR_PEAK_TFLOPS,
+                         unit="TFLOP/s", frac=round(ach / FP32_VECTOR_PEAK_TFLOPS, 4), traffic=None,
+                         kernel=dom, blends_per_launch=int(blends),
+                         flops_per_blend=per)
+    nbytes = algorithmic_bytes(dom, batch, scene)
+    ach = nbytes / t / 1e9
+    return dom, dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                     frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, kernel=dom)
+
+
+def algorithmic_bytes(stage, batch, scene):
+    n = sum(s.n for s in scene.sets)
+    P = sum(4 * (3 + 3 + 4 + 1 + 3 * (s.sh_degree + 1) ** 2) for s in scene.sets) / max(1, len(scene.sets))
+    nrec = int(batch.info.n_records)
+    if stage == "preprocess":
+        return n * P + nrec * (52 + 12)
+    if stage == "backward_preprocess":
+        return n * P + nrec * 52 + n * P
+    return float("nan")
+
+
+def cpu_baseline(scene, sample=4096, seed=7):
+    """The FP64 oracle (as it is) on a fixed sample of masked pixels:
+    forward at the sample plus the gradient of a loss on the sample."""
+    import torch
+    import scenes
+    from oracle import OracleConfig
+    from oracle import composite as oc
+    torch.set_num_threads(os.cpu_count() or 1)
+    cfg = OracleConfig()
+    rd = scene.renders[0]
+    gs = scene.sets[rd.set_index]
+    pix = scenes.sample_pixels(seed, rd, sample)
+    g = scenes.grad_outputs(seed + 1000, rd, scale={"depth": 0.05})
+    sel = np.zeros((rd.camera.height, rd.camera.width), bool)
+    sel[pix[:, 0], pix[:, 1]] = True
+    g = {k: (v * sel).astype(np.float32) for k, v in g.items()}
+    t0 = time.perf_counter()
+    oc.render(gs, rd.camera, rd.mask, cfg, pixels=pix)
+    oc.render_grad(gs, rd.camera, rd.mask, cfg, g, pixels=pix)
+    dt = time.perf_counter() - t0
+    return dict(value=round(len(pix) / dt / 1e6, 6), unit="Mpixels/s", cores=torch.get_num_threads(),
+                kind="oracle",
+                sample=f"{len(pix)} masked pixels (seed {seed}) of the same 1M-Gaussian 1080p workload, "
+                       f"FP64 forward + gradient, full per-Gaussian preprocessing included; {dt:.1f} s")
+
+
+def batched_speedup(torch, steps=5, scale=1.0):
+    """Batched persistent graph-captured step vs the per-sub-region loop on
+    16 sub-regions x 4 views at 1600x1200."""
+    import scenes
+    from paper_2501_01677_amd.raster import RenderConfig
+    sc = scenes.config4(scale=scale)
+    # per-region loop: one batch per sub-region, launched one after another
+    loops = []
+    for k, s in enumerate(sc.sets):
+        sub = scenes.Scene([s], [scenes.Render(0, rd.camera, rd.mask) for rd in sc.renders
+                                 if rd.set_index == k])
+        b = build_batch(sub, RenderConfig(tile=16), torch)
+        fill_gouts(b, sub, 4000 + k, torch)
+        b.forward()
+        b.fit_capacity(1.1)
+        loops.append(b)
+    for b in loops:
+        b.forward(check_overflow=False)
+        b.backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for b in loops:
+            b.forward(check_overflow=False)
+            b.backward()
+    torch.cuda.synchronize()
+    t_loop = (time.perf_counter() - t0) / steps
+    for b in loops:
+        del b.workspace
+    del loops
+    torch.cuda.empty_cache()
+    bb = build_batch(sc, RenderConfig(tile=16, persistent=True, queue_chunk=2), torch)
+    fill_gouts(bb, sc, 4000, torch)
+    bb.forward()
+    bb.fit_capacity(1.1)
+    bb.forward(check_overflow=False)
+    bb.backward()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            bb.forward(check_overflow=False)
+            bb.backward()
+    torch.cuda.current_stream().wait_stream(s)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / steps
+    if bb.status().overflow:
+        raise RuntimeError("overflow in the batched graph")
+    masked = sum(int(rd.mask.sum()) for rd in sc.renders)
+    return dict(workload="16 sub-regions x 4 views, 1600x1200, %d Gaussians" % sum(s.n for s in sc.sets),
+                loop_ms=round(t_loop * 1e3, 3), batched_graph_ms=round(t_graph * 1e3, 3),
+                speedup=round(t_loop / t_graph, 3),
+                batched_mpix_s=round(masked / t_graph / 1e6, 1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-scale", type=float, default=1.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        sys.exit(2)
+    import torch
+    import scenes
+    from paper_2501_01677_amd.raster import RenderConfig
+    torch.cuda.set_device(0)
+    log("[bench] generating the 1M-Gaussian 1080p workload")
+    sc = scenes.config2()
+    cfg = RenderConfig(tile=args.tile)
+    batch = build_batch(sc, cfg, torch)
+    fill_gouts(batch, sc, 2 + 1000, torch)
+    log("[bench] timing forward+backward")
+    ms_wall, stage = timed_steps(batch, args.steps, args.warmup, torch)
+    masked = int(sc.renders[0].mask.sum())
+    value = masked / (ms_wall * 1e-3) / 1e6
+    dom, roof = roofline(stage, batch, sc, torch)
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+    line = {
+        "metric": "masked fwd+bwd Mpixels/s (1M Gaussians, 1080p); batched vs per-region speedup",
+        "value": round(value, 2),
+        "unit": "Mpixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_wall, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1M Gaussians SH3, 1920x1080, 40% rectangle-union building mask, "
+                               "fwd+bwd with fixed dL/dout",
+                   "masked_pixels": masked, "tile": args.tile, "pairs": int(batch.status().pairs_needed)},
+        "stages_ms": {k: round(v, 4) for k, v in stage.items()},
+        "roofline": roof,
+    }
+    del batch
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        log("[bench] batched vs per-region loop")
+        try:
+            line["batched"] = batched_speedup(torch, steps=3, scale=args.batched_scale)
+        except Exception as e:  # report, do not hide the headline
+            line["batched"] = {"error": repr(e)}
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline(sc)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,278 @@
+/*
+ * pgsag.h -- C ABI of a masked, tile-based, differentiable 3D Gaussian
+ * splatting rasterizer for AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the per-sub-region rendering step of PG-SAG
+ * (arXiv 2501.01677): Gaussians with position, anisotropic covariance,
+ * spherical-harmonics colour and opacity are projected to 2D Gaussians,
+ * assigned to image tiles, depth sorted and alpha blended (Sec. 3.1, Eq. 1);
+ * the camera-frame Gaussian normals (Eq. 2) and plane distances (Eq. 3) are
+ * blended the same way and turned into an unbiased depth by intersecting
+ * every pixel ray with the blended plane (Eq. 4).  Only pixels inside the
+ * building mask are rendered (Sec. 1, Sec. 4.1, Sec. 5.3), and many
+ * sub-regions and views are rendered in one batch (Sec. 4.1, Sec. 4.4).
+ * The backward pass returns gradients of a scalar loss with respect to the
+ * raw Gaussian parameters (differentiable rendering, Sec. 3.1).
+ *
+ * Conventions
+ *  - All floating point is FP32, counts are int32, masks uint8 (0 / non-0).
+ *  - Every array is planar (structure of arrays), row-major images [H][W].
+ *  - World to camera: x_c = R x_w + t, R row-major; the camera looks along
+ *    +z, image x to the right, image y down.  Pixel (u, v) samples the image
+ *    plane at (u + 0.5, v + 0.5).  Intrinsics fx, fy, cx, cy.
+ *  - Raw parameters of a Gaussian set of n Gaussians:
+ *      means [3][n], log_scales [3][n] (natural log of the axis scales),
+ *      quats [4][n] as (w, x, y, z), any non-zero norm (normalised inside),
+ *      opacity_logits [n] (opacity = sigmoid(logit)),
+ *      sh [(deg+1)^2][3][n]  (real orthonormal SH with the Condon-Shortley
+ *      phase, coefficient index l*l + l + m; colour = sum + 0.5, clamped at
+ *      0, evaluated on the world-frame direction camera centre -> mean).
+ *  - Outputs per render, for masked pixels (0 elsewhere):
+ *      rgb [3][H][W] (Eq. 1 plus background times final transmittance),
+ *      normal [3][H][W] (Eq. 2, camera frame, not normalised),
+ *      dist [H][W] (Eq. 3, blended signed plane distance n_c . t_c),
+ *      depth [H][W] (Eq. 4: dist / (normal . K^-1 p~), 0 unless the
+ *                    denominator is below -1e-6),
+ *      alpha [H][W] (1 - final transmittance),
+ *      n_contrib [H][W] (number of blended Gaussians, the g_i of Eq. 9).
+ *  - Constants (see pgsag_config): fragments with alpha < alpha_min are
+ *    skipped; blending stops before a fragment would take the transmittance
+ *    below t_min; alpha = min(alpha_max, o * exp(-q/2)); +dilation px^2 on
+ *    the projected covariance diagonal; Gaussians with FP32 camera depth
+ *    <= z_near or logit < logit_min are culled; the depth order key is the
+ *    FP32 camera depth ((R20*x + R21*y) + R22*z) + t2 with every operation
+ *    rounded separately, ties by Gaussian index.
+ *
+ * Ownership: the caller owns every buffer -- parameters, outputs,
+ * gradients, the workspace and the device copy of the descriptor.  The
+ * library never allocates or frees device memory and keeps no global
+ * mutable state except the thread-local error string.  Work is enqueued on
+ * the caller's HIP stream (passed as void*, a hipStream_t; NULL = the null
+ * stream); no call synchronises except pgsag_read_status.  pgsag_forward
+ * and pgsag_backward are capturable into a HIP graph.
+ *
+ * Errors: every call returns a pgsag_status_code; on failure
+ * pgsag_last_error() (thread-local, valid until the next call on the same
+ * thread) describes it.  A pair-capacity overflow is detected on the
+ * device: emission stops at the capacity, the status word records the
+ * pairs that were needed and the outputs of that forward are invalid; read
+ * it with pgsag_read_status and plan again with a larger capacity.
+ */
+#ifndef PGSAG_H
+#define PGSAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PGSAG_ABI_VERSION 1
+#define PGSAG_NUM_STAGES 8
+
+typedef enum pgsag_status_code {
+  PGSAG_OK = 0,
+  PGSAG_INVALID_ARGUMENT = 1,    /* null required pointer, bad size, bad tile */
+  PGSAG_WORKSPACE_TOO_SMALL = 2, /* workspace or descriptor buffer too small */
+  PGSAG_UNSUPPORTED = 3,         /* valid but not implemented combination */
+  PGSAG_HIP_ERROR = 4            /* a HIP launch or copy failed */
+} pgsag_status_code;
+
+/* Stages timed when an event array is passed to forward/backward
+ * (events[2*s] recorded before stage s, events[2*s+1] after it). */
+typedef enum pgsag_stage {
+  PGSAG_STAGE_TILE_MASK = 0,  /* per-tile masked-pixel counts, active-tile SAT */
+  PGSAG_STAGE_PREPROCESS = 1, /* projection, SH colour, normal, support rect */
+  PGSAG_STAGE_DEPTH_SORT = 2, /* compaction + radix sort of visible records */
+  PGSAG_STAGE_EMIT = 3,       /* pair-count scan + (tile, record) emission */
+  PGSAG_STAGE_TILE_SORT = 4,  /* stable radix sort of pairs by tile, ranges, queue */
+  PGSAG_STAGE_COMPOSITE = 5,  /* forward compositing + depth epilogue */
+  PGSAG_STAGE_BACKWARD_COMPOSITE = 6, /* backward compositing (2D gradients) */
+  PGSAG_STAGE_BACKWARD_PREPROCESS = 7 /* chain rule to raw parameters */
+} pgsag_stage;
+
+typedef struct pgsag_camera {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float R[9]; /* world -> camera rotation, row-major */
+  float t[3]; /* x_c = R x_w + t */
+} pgsag_camera;
+
+typedef struct pgsag_gaussians {
+  int64_t n;         /* number of Gaussians, >= 0 */
+  int32_t sh_degree; /* 0..3 */
+  int32_t reserved;
+  const float *means, *log_scales, *quats, *opacity_logits, *sh; /* device */
+} pgsag_gaussians;
+
+/* Gradients with respect to the raw parameters of one set, same layouts as
+ * pgsag_gaussians; overwritten (not accumulated) by pgsag_backward, summed
+ * over every render of the set.  Any pointer may be NULL (not wanted). */
+typedef struct pgsag_grads {
+  float *means, *log_scales, *quats, *opacity_logits, *sh;
+} pgsag_grads;
+
+/* Device output planes of one render; NULL = not wanted, except alpha-free
+ * operation: the backward needs nothing here, but the depth gradient needs
+ * normal and dist, which must then be non-NULL. */
+typedef struct pgsag_outputs {
+  float *rgb, *normal, *dist, *depth, *alpha;
+  int32_t *n_contrib;
+} pgsag_outputs;
+
+/* Device dL/d(output) planes, same layouts as pgsag_outputs; NULL = zero.
+ * Values at unmasked pixels are ignored. */
+typedef struct pgsag_grad_outputs {
+  const float *rgb, *normal, *dist, *depth, *alpha;
+} pgsag_grad_outputs;
+
+typedef struct pgsag_render {
+  int32_t set; /* index of the Gaussian set this render draws */
+  int32_t reserved;
+  pgsag_camera cam;
+  const uint8_t *mask; /* device [H][W], non-zero = building pixel; NULL = all */
+  pgsag_outputs out;
+  pgsag_grad_outputs gout;
+} pgsag_render;
+
+typedef struct pgsag_config {
+  int32_t tile;        /* 8, 16 or 32 (pixels per tile side) */
+  int32_t persistent;  /* 1: persistent workgroups pulling an LPT tile queue */
+  int32_t queue_chunk; /* tiles fetched per queue pop (1..64) */
+  int32_t workgroups_per_cu; /* persistent grid = 256 CUs x this (1..16) */
+  float alpha_min;  /* 1/255 */
+  float t_min;      /* 1e-4 */
+  float alpha_max;  /* 0.99 */
+  float dilation;   /* 0.3 */
+  float z_near;     /* 0.2 */
+  float fov_clamp;  /* 1.3 */
+  float logit_min;  /* float32(-ln 254) */
+  float depth_guard; /* 1e-6 */
+  float bg[3];      /* 0, 0, 0 */
+  int32_t reserved;
+} pgsag_config;
+
+typedef struct pgsag_plan_info {
+  uint64_t workspace_bytes; /* device workspace the batch needs */
+  uint64_t desc_bytes;      /* size of the packed descriptor */
+  uint64_t n_records;       /* sum over renders of the set size */
+  uint64_t n_tiles;         /* sum over renders of tiles_x * tiles_y */
+  uint64_t n_pixels;        /* sum over renders of W * H */
+  uint64_t pair_capacity;   /* (tile, Gaussian) pairs the workspace holds */
+  int32_t tile_bits;        /* bits of the global tile id */
+  int32_t reserved;
+} pgsag_plan_info;
+
+/* Byte offsets of the workspace regions (for inspection by tests). */
+typedef struct pgsag_layout {
+  uint64_t status;     /* uint64 pairs_needed, uint32 overflow, uint32 n_visible */
+  uint64_t tile_count; /* uint32 [n_tiles] masked pixels per tile */
+  uint64_t sat;        /* uint32 active-tile summed-area tables */
+  uint64_t ranges;     /* uint32 [n_tiles][2] [start, end) into the pairs */
+  uint64_t queue;      /* uint32 [n_tiles] tile work queue (LPT order) */
+  uint64_t records;    /* float [n_records][16] projected records */
+  uint64_t depth_key;  /* uint32 [n_records] FP32 depth key bits */
+  uint64_t rect;       /* uint16 [n_records][4] tile rect x0, y0, x1, y1 */
+  uint64_t n_active;   /* uint32 [n_records] active tiles in the rect */
+  uint64_t pair_tile;  /* uint32 [capacity] sorted pair tile ids */
+  uint64_t pair_record; /* uint32 [capacity] sorted pair record ids */
+  uint64_t pixel_T;    /* float [n_pixels] final transmittance */
+  uint64_t pixel_last; /* int32 [n_pixels] last blended pair index, -1 none */
+  uint64_t grad2d;     /* float [n_records][16] 2D gradients */
+  uint64_t end;
+} pgsag_layout;
+
+typedef struct pgsag_status {
+  uint64_t pairs_needed; /* pairs the last forward/binning emitted or needed */
+  uint32_t overflow;     /* 1 if pairs_needed > capacity (outputs invalid) */
+  uint32_t n_visible;    /* records with at least one active tile */
+} pgsag_status;
+
+/* PGSAG_ABI_VERSION of the loaded library. */
+int pgsag_version(void);
+
+/* Thread-local description of the last failure on this thread. */
+const char *pgsag_last_error(void);
+
+/* Fills *cfg with the defaults listed in pgsag_config. */
+void pgsag_default_config(pgsag_config *cfg);
+
+/* Sizes the workspace and descriptor of a batch (host only, no device
+ * work).  sets[n_sets] and renders[n_renders] are read for their sizes;
+ * pair_capacity is the maximum number of (tile, Gaussian) pairs (1..2^32-1).
+ * Returns INVALID_ARGUMENT for n_sets < 1, n_renders < 1, a render whose set
+ * index is out of range, width/height < 1 or > 65535*tile, sh_degree
+ * outside 0..3, tile not in {8,16,32}, n < 0, or totals beyond 2^32-1. */
+int pgsag_plan(const pgsag_config *cfg, const pgsag_gaussians *sets, int32_t n_sets,
+               const pgsag_render *renders, int32_t n_renders, uint64_t pair_capacity,
+               pgsag_plan_info *out);
+
+/* Packs the batch into host_desc[desc_bytes] (host memory).  The caller
+ * copies these bytes to a device buffer (dev_desc) before forward/backward;
+ * device pointers inside stay valid for as long as the caller keeps the
+ * buffers alive, so a captured graph may replay with the same descriptor.
+ * set_grads may be NULL (no backward).  Same validation as pgsag_plan, plus
+ * non-NULL parameter pointers for n > 0 and depth gradients requiring the
+ * normal and dist outputs. */
+int pgsag_pack(const pgsag_config *cfg, const pgsag_gaussians *sets,
+               const pgsag_grads *set_grads, int32_t n_sets, const pgsag_render *renders,
+               int32_t n_renders, uint64_t pair_capacity, void *host_desc,
+               size_t desc_bytes);
+
+/* Workspace byte offsets of a packed batch. */
+int pgsag_layout_of(const void *host_desc, pgsag_layout *out);
+
+/* Forward pass (Sec. 3.1, Eq. 1-4) of every render of the batch: tile-mask
+ * reduce, projection, depth sort, tile binning, tile sort, compositing and
+ * the depth epilogue.  host_desc: the packed bytes (host); dev_desc: their
+ * device copy; workspace: device buffer of at least workspace_bytes, left
+ * untouched by the caller until pgsag_backward; stream: hipStream_t or NULL;
+ * events: NULL or 2*PGSAG_NUM_STAGES hipEvent_t recorded around the stages. */
+int pgsag_forward(const void *host_desc, const void *dev_desc, void *workspace,
+                  size_t workspace_bytes, void *stream, void **events);
+
+/* Backward pass: gradients of L = sum over renders, masked pixels and
+ * channels of gout * output with respect to the raw parameters of every set
+ * (overwritten, summed over the set's renders).  Must follow the forward of
+ * the same batch on the same workspace; recomputes the per-pixel blending
+ * state from the saved final transmittance and last index instead of storing
+ * per-fragment alphas. */
+int pgsag_backward(const void *host_desc, const void *dev_desc, void *workspace,
+                   size_t workspace_bytes, void *stream, void **events);
+
+/* Tile binning alone (the integer stages of Sec. 3.1: tile assignment and
+ * sorting): reads per-record tile rects, depth keys and validity that the
+ * caller has written into the workspace (layout: rect, depth_key, and
+ * n_active != 0 meaning valid), recounts active tiles from the masks,
+ * compacts, depth sorts, emits pairs, tile sorts and builds the ranges.
+ * For testing the binning against a reference on chosen inputs. */
+int pgsag_binning(const void *host_desc, const void *dev_desc, void *workspace,
+                  size_t workspace_bytes, void *stream);
+
+/* Copies the status word to *out and synchronises the stream. */
+int pgsag_read_status(const void *host_desc, const void *workspace, pgsag_status *out,
+                      void *stream);
+
+/* Fused Adam update over n floats (device pointers, any alignment of 4
+ * bytes): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * step >= 1.  (The paper does not name its optimiser; this is the one the
+ * 3DGS family uses.) */
+int pgsag_adam_step(float *params, const float *grads, float *m, float *v, int64_t n,
+                    float lr, float b1, float b2, float eps, int32_t step, void *stream);
+
+/* Balance-load statistics of the last forward (Sec. 4.3, Eq. 9): per
+ * render, over tiles with at least one masked pixel, the mean and the
+ * population variance of the per-tile pair counts, and over masked pixels
+ * the mean and population standard deviation of n_contrib / w where
+ * w = pixel_weight (device [H][W] per render, NULL = 1).  out: device float
+ * [n_renders][4] = {tile mean, tile variance, pixel mean, pixel std}. */
+int pgsag_load_stats(const void *host_desc, const void *dev_desc, const void *workspace,
+                     const float *const *pixel_weight, float *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PGSAG_H */

@@ -219,7 +219,7 @@ def render(gs, cam, mask, cfg, mode="culled", pixels=None, cell=16, prep=None):
     res = dict(pix=pix, rgb=np.zeros((Pn, 3)), normal=np.zeros((Pn, 3)), dist=np.zeros(Pn),
                depth=np.zeros(Pn), alpha=np.zeros(Pn), n_contrib=np.zeros(Pn, np.int64),
                allow=np.zeros((Pn, 8)), unsafe=np.zeros(Pn, bool),
-               depth_unreliable=np.zeros(Pn, bool), T=np.ones(Pn))
+               depth_unreliable=np.zeros(Pn, bool), T=np.ones(Pn), den=np.zeros(Pn))
     with torch.no_grad():
         g_all = _geo(proj, dec)
         for rows, cand in _groups(pix, proj, cam, cfg, mode, cell):
@@ -235,6 +235,7 @@ def render(gs, cam, mask, cfg, mode="culled", pixels=None, cell=16, prep=None):
             res["alpha"][rows] = alpha.numpy()
             res["T"][rows] = T.numpy()
             res["n_contrib"][rows] = n.numpy()
+            res["den"][rows] = den.numpy()
             res["allow"][rows] = allow.numpy()
             nr = torch.linalg.norm(nrm, dim=1) * torch.linalg.norm(r, dim=1)
             near_guard = (den + cfg.depth_guard).abs() <= 1e-3 * nr + 1e-12

@@ -1,0 +1,164 @@
+// Internal definitions shared by the kernels and the host side of libpgsag:
+// the packed descriptor (what the device reads), workspace layout, and small
+// device helpers.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pgsag.h"
+
+namespace pgsag {
+
+constexpr uint32_t kMagic = 0x50475341u;  // "PGSA"
+constexpr int kRec = 16;                  // floats per projected record
+constexpr int kG2 = 16;                   // floats per 2D-gradient slot
+constexpr int kScanItems = 16;            // items per thread in scans / sorts
+constexpr int kScanBlock = 256;           // threads per scan / sort block
+constexpr int kScanChunk = kScanItems * kScanBlock;  // 4096 elements per block
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+
+// Record layout (floats): projected Gaussian for one (render, Gaussian).
+enum RecField {
+  R_MX = 0, R_MY = 1,              // 2D mean (pixels)
+  R_CA = 2, R_CB = 3, R_CC = 4,    // conic: q = a dx^2 + 2 b dx dy + c dy^2
+  R_O = 5,                         // opacity
+  R_R = 6, R_G = 7, R_B = 8,       // colour
+  R_NX = 9, R_NY = 10, R_NZ = 11,  // camera-frame normal
+  R_D = 12,                        // plane distance
+  R_RX = 13, R_RY = 14,            // support half-widths (pixels, with margin)
+  R_PAD = 15
+};
+
+// 2D-gradient slot layout (floats).
+enum G2Field {
+  G_MX = 0, G_MY = 1, G_CA = 2, G_CB = 3, G_CC = 4, G_O = 5,
+  G_R = 6, G_G = 7, G_B = 8, G_NX = 9, G_NY = 10, G_NZ = 11, G_D = 12
+};
+
+struct DevCamera {
+  int32_t W, H;
+  float fx, fy, cx, cy;
+  float R[9];
+  float t[3];
+  float centre[3];  // camera centre in world coordinates, -R^T t
+  float limx, limy; // lateral clamp of the projection Jacobian
+};
+
+struct DevSet {
+  const float *means, *log_scales, *quats, *logits, *sh;
+  float *g_means, *g_log_scales, *g_quats, *g_logits, *g_sh;
+  int64_t n;
+  int32_t sh_degree;
+  int32_t n_renders;
+  uint64_t gauss_offset;  // prefix of n over sets
+  int32_t renders[64];    // render indices drawing this set (n_renders <= 64)
+};
+
+struct DevRender {
+  DevCamera cam;
+  int32_t set, tiles_x, tiles_y, reserved;
+  const uint8_t *mask;
+  float *o_rgb, *o_normal, *o_dist, *o_depth, *o_alpha;
+  int32_t *o_ncontrib;
+  const float *g_rgb, *g_normal, *g_dist, *g_depth, *g_alpha;
+  uint64_t record_offset;  // first record of this render
+  uint64_t pixel_offset;   // first per-pixel state slot
+  uint32_t tile_offset;    // first global tile id
+  uint32_t sat_offset;     // first SAT entry ((tiles_y+1)*(tiles_x+1) entries)
+  uint32_t row_offset;     // first global tile row
+  uint32_t reserved2;
+};
+
+struct Layout {
+  uint64_t status, tile_count, sat, ranges, queue, rec, depth_key, rect, nact;
+  uint64_t vis_key[2], vis_val[2], pair_off;
+  uint64_t pair_key[2], pair_val[2];
+  uint64_t sorted_key, sorted_val;  // the pair buffers holding the tile-sorted result
+  uint64_t pix_T, pix_last, g2;
+  uint64_t scan_sums, hist, bucket, stats;
+  uint64_t end;
+};
+
+// Status word layout (uint32 view of ws + layout.status).
+enum StatusField {
+  S_PAIRS_LO = 0, S_PAIRS_HI = 1, S_OVERFLOW = 2, S_NVIS = 3,
+  S_QUEUE_FWD = 4, S_QUEUE_BWD = 5, S_NPAIRS = 6, S_NQUEUE = 7,
+  S_WORDS = 64
+};
+
+struct Header {
+  uint32_t magic, abi;
+  int32_t n_sets, n_renders;
+  pgsag_config cfg;
+  uint64_t n_gauss, n_records, n_tiles, n_pixels, pair_capacity;
+  uint32_t sat_total, tile_bits, n_tile_rows, max_sh_degree;
+  uint64_t sets_off, renders_off, tile_starts_off, rec_starts_off, row_starts_off;
+  uint64_t desc_bytes, ws_bytes;
+  int32_t any_grads, reserved;
+  Layout ws;
+};
+
+__host__ __device__ inline const Header *header(const void *d) {
+  return reinterpret_cast<const Header *>(d);
+}
+__host__ __device__ inline const DevSet *sets_of(const void *d) {
+  return reinterpret_cast<const DevSet *>(static_cast<const char *>(d) + header(d)->sets_off);
+}
+__host__ __device__ inline const DevRender *renders_of(const void *d) {
+  return reinterpret_cast<const DevRender *>(static_cast<const char *>(d) + header(d)->renders_off);
+}
+// uint32 [n_renders + 1] prefix arrays used for binary searches
+__host__ __device__ inline const uint32_t *tile_starts_of(const void *d) {
+  return reinterpret_cast<const uint32_t *>(static_cast<const char *>(d) + header(d)->tile_starts_off);
+}
+__host__ __device__ inline const uint32_t *row_starts_of(const void *d) {
+  return reinterpret_cast<const uint32_t *>(static_cast<const char *>(d) + header(d)->row_starts_off);
+}
+__host__ __device__ inline const uint64_t *rec_starts_of(const void *d) {
+  return reinterpret_cast<const uint64_t *>(static_cast<const char *>(d) + header(d)->rec_starts_off);
+}
+
+template <typename T>
+__host__ __device__ inline T *ws_ptr(void *ws, uint64_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+template <typename T>
+__host__ __device__ inline const T *ws_ptr(const void *ws, uint64_t off) {
+  return reinterpret_cast<const T *>(static_cast<const char *>(ws) + off);
+}
+
+// Largest i in [0, n) with a[i] <= x (a ascending, a[0] == 0).
+template <typename T>
+__device__ inline int upper_index(const T *a, int n, T x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (a[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------- launches
+// Host-side launch helpers, defined in the kernel translation units.
+void launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t s);
+void launch_tile_mask(const void *d_desc, const Header &h, void *ws, hipStream_t s);
+void launch_preprocess(const void *d_desc, const Header &h, void *ws, hipStream_t s);
+void launch_recount(const void *d_desc, const Header &h, void *ws, hipStream_t s);
+void launch_depth_sort(const void *d_desc, const Header &h, void *ws, hipStream_t s);
+void launch_emit(const void *d_desc, const Header &h, void *ws, hipStream_t s);
+void launch_tile_sort(const void *d_desc, const Header &h, void *ws, hipStream_t s);
+void launch_composite(const void *d_desc, const Header &h, void *ws, hipStream_t s);
+void launch_backward_composite(const void *d_desc, const Header &h, void *ws, hipStream_t s);
+void launch_backward_preprocess(const void *d_desc, const Header &h, void *ws, hipStream_t s);
+void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
+                 float b2, float eps, int32_t step, hipStream_t s);
+void launch_load_stats(const void *d_desc, const Header &h, const void *ws, int r,
+                       const float *pixel_weight, float *out, hipStream_t s);
+
+// Scratch sizes the binning stages need (elements of uint32).
+uint64_t scan_scratch_words(uint64_t max_n);
+uint64_t radix_hist_words(uint64_t max_n);
+
+}  // namespace pgsag

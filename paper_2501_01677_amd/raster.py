@@ -1,0 +1,317 @@
+"""Python boundary of libpgsag: a batch of masked renders over caller-owned
+torch buffers, and the autograd function around it.
+
+PyTorch provides device memory and the stream; every step of the forward
+and backward pass runs in the library's HIP kernels.  A ``Batch`` owns the
+output planes, the upstream-gradient planes, the parameter-gradient arrays,
+the workspace and the device copy of the packed descriptor; the Gaussian
+parameters and masks stay owned by the caller and must outlive the batch.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+OUTPUTS = (("rgb", 3), ("normal", 3), ("dist", 1), ("depth", 1), ("alpha", 1), ("n_contrib", 1))
+GRAD_OUTPUTS = ("rgb", "normal", "dist", "depth", "alpha")
+PARAMS = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+@dataclass
+class RenderConfig:
+    tile: int = 16
+    persistent: bool = False
+    queue_chunk: int = 1
+    workgroups_per_cu: int = 4
+    alpha_min: float = 1.0 / 255.0
+    t_min: float = 1e-4
+    alpha_max: float = 0.99
+    dilation: float = 0.3
+    z_near: float = 0.2
+    fov_clamp: float = 1.3
+    logit_min: float = float(np.float32(-math.log(254.0)))
+    depth_guard: float = 1e-6
+    bg: tuple = (0.0, 0.0, 0.0)
+
+    def to_c(self) -> A.Config:
+        c = A.Config()
+        c.tile, c.persistent, c.queue_chunk = self.tile, int(self.persistent), self.queue_chunk
+        c.workgroups_per_cu = self.workgroups_per_cu
+        for k in ("alpha_min", "t_min", "alpha_max", "dilation", "z_near", "fov_clamp", "logit_min",
+                  "depth_guard"):
+            setattr(c, k, getattr(self, k))
+        c.bg = (C.c_float * 3)(*self.bg)
+        return c
+
+
+class CapacityError(RuntimeError):
+    pass
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def make_camera(cam) -> A.Camera:
+    c = A.Camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.R = (C.c_float * 9)(*np.asarray(cam.R, np.float32).reshape(-1).tolist())
+    c.t = (C.c_float * 3)(*np.asarray(cam.t, np.float32).reshape(-1).tolist())
+    return c
+
+
+def gaussians_to_device(gs, device="cuda"):
+    """scenes.GaussianSet (numpy) -> dict of contiguous float32 device tensors."""
+    d = {k: torch.from_numpy(np.ascontiguousarray(v)).to(device) for k, v in gs.arrays().items()}
+    d["sh_degree"] = gs.sh_degree
+    return d
+
+
+class Batch:
+    """A batch of renders of one or more Gaussian sets (one launch per stage).
+
+    sets:    list of dicts with device tensors means [3,n], log_scales [3,n],
+             quats [4,n], opacity_logits [n], sh [K,3,n] and int sh_degree.
+    renders: list of dicts with set (int), camera (width, height, fx, fy, cx,
+             cy, R, t attributes) and mask (device uint8 [H,W] or None).
+    """
+
+    def __init__(self, sets, renders, cfg: RenderConfig | None = None, pair_capacity=None,
+                 want_grads=True, outputs=tuple(n for n, _ in OUTPUTS), grad_outputs=GRAD_OUTPUTS,
+                 device="cuda"):
+        self.lib = A.lib()
+        self.cfg = cfg or RenderConfig()
+        self.sets = sets
+        self.renders = renders
+        self.device = device
+        self.want_grads = want_grads
+        self.out = []
+        self.gout = []
+        for rd in renders:
+            cam = rd["camera"]
+            H, W = int(cam.height), int(cam.width)
+            o = {}
+            for name, c in OUTPUTS:
+                if name in outputs:
+                    dt = torch.int32 if name == "n_contrib" else torch.float32
+                    o[name] = torch.empty((c, H, W) if c > 1 else (H, W), dtype=dt, device=device)
+            self.out.append(o)
+            g = {}
+            if want_grads:
+                for name, c in OUTPUTS:
+                    if name in grad_outputs:
+                        g[name] = torch.zeros((c, H, W) if c > 1 else (H, W), dtype=torch.float32,
+                                              device=device)
+            self.gout.append(g)
+        self.grads = []
+        if want_grads:
+            for s in sets:
+                self.grads.append({k: torch.zeros_like(s[k]) for k in PARAMS})
+        n_rec = sum(int(sets[rd["set"]]["means"].shape[1]) for rd in renders)
+        if pair_capacity is None:
+            pair_capacity = max(1 << 16, 8 * n_rec)
+        self._pack(int(min(pair_capacity, (1 << 31) - 1)))
+
+    # ------------------------------------------------------------ packing
+    def _c_arrays(self):
+        gs = (A.Gaussians * len(self.sets))()
+        gr = (A.Grads * len(self.sets))()
+        for i, s in enumerate(self.sets):
+            gs[i].n = int(s["means"].shape[1])
+            gs[i].sh_degree = int(s["sh_degree"])
+            for k in PARAMS:
+                t = s[k]
+                assert t.dtype == torch.float32 and t.is_contiguous(), k
+                setattr(gs[i], k, _p(t))
+            if self.want_grads:
+                for k in PARAMS:
+                    setattr(gr[i], k, _p(self.grads[i][k]))
+        rs = (A.Render * len(self.renders))()
+        for i, rd in enumerate(self.renders):
+            rs[i].set = int(rd["set"])
+            rs[i].cam = make_camera(rd["camera"])
+            m = rd.get("mask")
+            if m is not None:
+                assert m.dtype == torch.uint8 and m.is_contiguous()
+            rs[i].mask = _p(m)
+            for name, _ in OUTPUTS:
+                setattr(rs[i].out, name, _p(self.out[i].get(name)))
+            for name in GRAD_OUTPUTS:
+                setattr(rs[i].gout, name, _p(self.gout[i].get(name)))
+        return gs, gr, rs
+
+    def _pack(self, capacity):
+        cfg = self.cfg.to_c()
+        gs, gr, rs = self._c_arrays()
+        info = A.PlanInfo()
+        A.check(self.lib.pgsag_plan(C.byref(cfg), gs, len(self.sets), rs, len(self.renders), capacity,
+                                    C.byref(info)), "pgsag_plan")
+        self.info = info
+        self.host_desc = (C.c_uint8 * info.desc_bytes)()
+        A.check(self.lib.pgsag_pack(C.byref(cfg), gs, gr if self.want_grads else None, len(self.sets), rs,
+                                    len(self.renders), capacity, self.host_desc, info.desc_bytes),
+                "pgsag_pack")
+        self.workspace = torch.empty(int(info.workspace_bytes), dtype=torch.uint8, device=self.device)
+        host = torch.frombuffer(bytearray(bytes(self.host_desc)), dtype=torch.uint8)
+        self.dev_desc = host.to(self.device)
+        lay = A.Layout()
+        A.check(self.lib.pgsag_layout_of(self.host_desc, C.byref(lay)), "pgsag_layout_of")
+        self.layout = lay
+        self.capacity = capacity
+
+    def repack(self):
+        """Re-reads parameter / buffer pointers (after replacing tensors)."""
+        self._pack(self.capacity)
+
+    # ------------------------------------------------------------- passes
+    def _events(self, events):
+        if events is None:
+            return None
+        arr = (C.c_void_p * len(events))(*[C.c_void_p(e) for e in events])
+        return arr
+
+    def forward(self, stream=None, events=None, check_overflow=True):
+        """Renders every view.  With check_overflow the status word is read
+        (a stream synchronisation) and the batch replans and reruns once if
+        the pair capacity was too small."""
+        for _ in range(3):
+            A.check(self.lib.pgsag_forward(self.host_desc, _p(self.dev_desc), _p(self.workspace),
+                                           int(self.info.workspace_bytes), _stream(stream),
+                                           self._events(events)), "pgsag_forward")
+            if not check_overflow:
+                return self.out
+            st = self.status(stream)
+            if not st.overflow:
+                return self.out
+            self._pack(int(min((1 << 31) - 1, max(st.pairs_needed * 5 // 4, 1024))))
+        raise CapacityError("pair capacity overflow persists after replanning")
+
+    def fit_capacity(self, slack=1.25, stream=None):
+        """Replans the pair capacity to slack x what the last forward needed."""
+        st = self.status(stream)
+        want = int(min((1 << 31) - 1, max(1024, st.pairs_needed * slack)))
+        if want != self.capacity:
+            self._pack(want)
+        return st
+
+    def backward(self, gouts=None, stream=None, events=None):
+        """Gradients of sum(gout * out) with respect to the raw parameters.
+        ``gouts``: list (per render) of dicts name -> tensor, copied into the
+        batch's gradient planes (missing names keep their current values)."""
+        if not self.want_grads:
+            raise RuntimeError("batch was built without gradients")
+        if gouts is not None:
+            for i, g in enumerate(gouts):
+                for name, t in g.items():
+                    if t is None:
+                        self.gout[i][name].zero_()
+                    else:
+                        self.gout[i][name].copy_(t.reshape(self.gout[i][name].shape))
+        A.check(self.lib.pgsag_backward(self.host_desc, _p(self.dev_desc), _p(self.workspace),
+                                        int(self.info.workspace_bytes), _stream(stream),
+                                        self._events(events)), "pgsag_backward")
+        return self.grads
+
+    def binning(self, stream=None):
+        A.check(self.lib.pgsag_binning(self.host_desc, _p(self.dev_desc), _p(self.workspace),
+                                       int(self.info.workspace_bytes), _stream(stream)), "pgsag_binning")
+
+    def status(self, stream=None):
+        st = A.Status()
+        A.check(self.lib.pgsag_read_status(self.host_desc, _p(self.workspace), C.byref(st),
+                                           _stream(stream)), "pgsag_read_status")
+        return st
+
+    def load_stats(self, weights=None, stream=None):
+        out = torch.empty((len(self.renders), 4), dtype=torch.float32, device=self.device)
+        warr = None
+        if weights is not None:
+            warr = (C.c_void_p * len(self.renders))(*[None if w is None else w.data_ptr() for w in weights])
+        A.check(self.lib.pgsag_load_stats(self.host_desc, _p(self.dev_desc), _p(self.workspace), warr,
+                                          _p(out), _stream(stream)), "pgsag_load_stats")
+        return out
+
+    # ------------------------------------------------------ workspace views
+    def view(self, name, dtype, count, cols=None):
+        off = getattr(self.layout, name)
+        itemsize = torch.tensor([], dtype=dtype).element_size()
+        n = count * (cols or 1)
+        t = self.workspace[off:off + n * itemsize].view(dtype)
+        return t.view(count, cols) if cols else t
+
+
+def adam_step(params, grads, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    """Fused Adam update in place over matching float32 device tensors."""
+    L = A.lib()
+    for t in (params, grads, m, v):
+        assert t.dtype == torch.float32 and t.is_contiguous() and t.numel() == params.numel()
+    A.check(L.pgsag_adam_step(_p(params), _p(grads), _p(m), _p(v), params.numel(), lr, b1, b2, eps, step,
+                              _stream(stream)), "pgsag_adam_step")
+
+
+class _RasterizeFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, batch, *flat):
+        batch.forward()
+        ctx.batch = batch
+        outs = []
+        for o in batch.out:
+            for name in GRAD_OUTPUTS:
+                outs.append(o[name].clone())
+            outs.append(o["n_contrib"].clone())
+        ctx.mark_non_differentiable(*outs[len(GRAD_OUTPUTS)::len(GRAD_OUTPUTS) + 1])
+        return tuple(outs)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        batch = ctx.batch
+        per = len(GRAD_OUTPUTS) + 1
+        gouts = []
+        for i in range(len(batch.renders)):
+            g = {}
+            for j, name in enumerate(GRAD_OUTPUTS):
+                gi = grads[i * per + j]
+                g[name] = None if gi is None else gi.contiguous()
+            gouts.append(g)
+        batch.backward(gouts)
+        res = [None]
+        for s in batch.grads:
+            res += [s[k].clone() for k in PARAMS]
+        return tuple(res)
+
+
+class MaskedRasterizer:
+    """Differentiable masked rendering of fixed Gaussian sets and views.
+
+    ``rasterizer()`` returns, per render, a dict of rgb [3,H,W], normal
+    [3,H,W], dist, depth, alpha [H,W] (differentiable) and n_contrib (int32).
+    Gradients flow to the parameter tensors of ``sets`` (which should have
+    requires_grad set by the caller)."""
+
+    def __init__(self, sets, renders, cfg: RenderConfig | None = None, pair_capacity=None):
+        self.batch = Batch(sets, renders, cfg, pair_capacity, want_grads=True)
+
+    def __call__(self):
+        flat = []
+        for s in self.batch.sets:
+            flat += [s[k] for k in PARAMS]
+        outs = _RasterizeFn.apply(self.batch, *flat)
+        per = len(GRAD_OUTPUTS) + 1
+        res = []
+        for i in range(len(self.batch.renders)):
+            d = {name: outs[i * per + j] for j, name in enumerate(GRAD_OUTPUTS)}
+            d["n_contrib"] = outs[i * per + len(GRAD_OUTPUTS)]
+            res.append(d)
+        return res

@@ -1,0 +1,138 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+the header declares, the ctypes mirror matches the C struct layouts, and the
+host-only planning calls validate their arguments."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2501_01677_amd import _abi as A
+from paper_2501_01677_amd.raster import RenderConfig, make_camera
+import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pgsag.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(pgsag_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = A.lib()
+    decl = declared_functions()
+    assert len(decl) >= 12
+    for name in decl:
+        assert hasattr(L, name), name
+    assert set(decl) == set(A.SYMBOLS)
+    assert L.pgsag_version() == A.ABI_VERSION
+
+
+STRUCTS = {
+    "pgsag_camera": (A.Camera, ["width", "fx", "R", "t"]),
+    "pgsag_gaussians": (A.Gaussians, ["n", "sh_degree", "means", "sh"]),
+    "pgsag_grads": (A.Grads, ["means", "sh"]),
+    "pgsag_outputs": (A.Outputs, ["rgb", "alpha", "n_contrib"]),
+    "pgsag_grad_outputs": (A.GradOutputs, ["rgb", "alpha"]),
+    "pgsag_render": (A.Render, ["set", "cam", "mask", "out", "gout"]),
+    "pgsag_config": (A.Config, ["tile", "alpha_min", "logit_min", "depth_guard", "bg"]),
+    "pgsag_plan_info": (A.PlanInfo, ["workspace_bytes", "pair_capacity", "tile_bits"]),
+    "pgsag_layout": (A.Layout, ["status", "records", "grad2d", "end"]),
+    "pgsag_status": (A.Status, ["pairs_needed", "overflow", "n_visible"]),
+}
+
+
+def test_ctypes_layouts_match_the_header():
+    lines = ['#include "pgsag.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void) {"]
+    for sname, (_, fields) in STRUCTS.items():
+        lines.append(f'  printf("{sname} %zu\\n", sizeof({sname}));')
+        for f in fields:
+            lines.append(f'  printf("{sname}.{f} %zu\\n", offsetof({sname}, {f}));')
+    lines += ["  return 0;", "}"]
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(src, "w").write("\n".join(lines))
+        subprocess.check_call(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), src, "-o", exe])
+        out = subprocess.check_output([exe], text=True)
+    got = dict(line.split() for line in out.strip().splitlines())
+    for sname, (cls, fields) in STRUCTS.items():
+        assert int(got[sname]) == C.sizeof(cls), sname
+        for f in fields:
+            assert int(got[f"{sname}.{f}"]) == getattr(cls, f).offset, (sname, f)
+
+
+def _c_batch(n=100, W=70, H=50, tile=16, sets=1, renders=1):
+    gs = (A.Gaussians * sets)()
+    for i in range(sets):
+        gs[i].n = n
+        gs[i].sh_degree = 1
+        for k in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+            setattr(gs[i], k, C.c_void_p(0x1000))
+    rs = (A.Render * renders)()
+    for i in range(renders):
+        rs[i].set = i % sets
+        rs[i].cam = make_camera(scenes.pinhole(W, H, 60.0, 60.0))
+    cfg = RenderConfig(tile=tile).to_c()
+    return cfg, gs, rs
+
+
+def test_plan_sizes_and_validation():
+    L = A.lib()
+    cfg, gs, rs = _c_batch()
+    info = A.PlanInfo()
+    assert L.pgsag_plan(C.byref(cfg), gs, 1, rs, 1, 5000, C.byref(info)) == A.OK
+    assert info.n_tiles == 5 * 4 and info.n_pixels == 70 * 50 and info.n_records == 100
+    assert info.tile_bits == 5 and info.workspace_bytes > 100 * 64
+    # invalid tile size
+    cfg.tile = 12
+    assert L.pgsag_plan(C.byref(cfg), gs, 1, rs, 1, 5000, C.byref(info)) == A.INVALID_ARGUMENT
+    assert b"tile" in L.pgsag_last_error()
+    cfg.tile = 16
+    # bad SH degree, bad set index, zero capacity, bad image
+    gs[0].sh_degree = 4
+    assert L.pgsag_plan(C.byref(cfg), gs, 1, rs, 1, 5000, C.byref(info)) == A.INVALID_ARGUMENT
+    gs[0].sh_degree = 1
+    rs[0].set = 3
+    assert L.pgsag_plan(C.byref(cfg), gs, 1, rs, 1, 5000, C.byref(info)) == A.INVALID_ARGUMENT
+    rs[0].set = 0
+    assert L.pgsag_plan(C.byref(cfg), gs, 1, rs, 1, 0, C.byref(info)) == A.INVALID_ARGUMENT
+    rs[0].cam.width = 0
+    assert L.pgsag_plan(C.byref(cfg), gs, 1, rs, 1, 5000, C.byref(info)) == A.INVALID_ARGUMENT
+
+
+def test_pack_and_layout_on_host():
+    L = A.lib()
+    cfg, gs, rs = _c_batch(n=1000, sets=2, renders=5)
+    info = A.PlanInfo()
+    assert L.pgsag_plan(C.byref(cfg), gs, 2, rs, 5, 1 << 20, C.byref(info)) == A.OK
+    small = (C.c_uint8 * 16)()
+    assert L.pgsag_pack(C.byref(cfg), gs, None, 2, rs, 5, 1 << 20, small, 16) == A.WORKSPACE_TOO_SMALL
+    buf = (C.c_uint8 * info.desc_bytes)()
+    assert L.pgsag_pack(C.byref(cfg), gs, None, 2, rs, 5, 1 << 20, buf, info.desc_bytes) == A.OK
+    lay = A.Layout()
+    assert L.pgsag_layout_of(buf, C.byref(lay)) == A.OK
+    offs = [getattr(lay, f) for f, _ in A.Layout._fields_]
+    assert all(o % 256 == 0 for o in offs)
+    assert lay.end == info.workspace_bytes
+    assert lay.records < lay.grad2d < lay.end
+    # a depth gradient without the normal/dist outputs is rejected
+    rs[0].gout.depth = C.c_void_p(0x2000)
+    assert L.pgsag_pack(C.byref(cfg), gs, None, 2, rs, 5, 1 << 20, buf, info.desc_bytes) == A.INVALID_ARGUMENT
+    # garbage descriptors are rejected before any device work
+    junk = (C.c_uint8 * 4096)()
+    assert L.pgsag_layout_of(junk, C.byref(lay)) == A.INVALID_ARGUMENT
+    assert L.pgsag_forward(junk, None, None, 0, None, None) == A.INVALID_ARGUMENT
+
+
+def test_adam_rejects_bad_arguments_without_touching_memory():
+    L = A.lib()
+    assert L.pgsag_adam_step(None, None, None, None, -1, 1e-3, 0.9, 0.999, 1e-8, 1, None) == A.INVALID_ARGUMENT
+    assert L.pgsag_adam_step(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 1, None) == A.INVALID_ARGUMENT
+    p = C.c_void_p(0x1000)
+    assert L.pgsag_adam_step(p, p, p, p, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == A.INVALID_ARGUMENT
