@@ -82,7 +82,7 @@ typedef enum pgsag_status_code {
 /* Stages timed when an event array is passed to forward/backward
  * (events[2*s] recorded before stage s, events[2*s+1] after it). */
 typedef enum pgsag_stage {
-  PGSAG_STAGE_TILE_MASK = 0,  /* per-tile masked-pixel counts, active-tile SAT */
+  PGSAG_STAGE_TILE_MASK = 0,  /* per-tile masked-pixel counts, active-tile row prefix */
   PGSAG_STAGE_PREPROCESS = 1, /* projection, SH colour, normal, support rect */
   PGSAG_STAGE_DEPTH_SORT = 2, /* compaction + radix sort of visible records */
   PGSAG_STAGE_EMIT = 3,       /* pair-count scan + (tile, record) emission */
@@ -168,7 +168,7 @@ typedef struct pgsag_plan_info {
 typedef struct pgsag_layout {
   uint64_t status;     /* uint64 pairs_needed, uint32 overflow, uint32 n_visible */
   uint64_t tile_count; /* uint32 [n_tiles] masked pixels per tile */
-  uint64_t sat;        /* uint32 active-tile summed-area tables */
+  uint64_t sat;        /* uint32 per-tile-row prefix counts of active tiles */
   uint64_t ranges;     /* uint32 [n_tiles][2] [start, end) into the pairs */
   uint64_t queue;      /* uint32 [n_tiles] tile work queue (LPT order) */
   uint64_t records;    /* float [n_records][16] projected records */

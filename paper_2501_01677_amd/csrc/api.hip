@@ -129,7 +129,9 @@ Layout make_layout(const Sizes &z, uint64_t cap, int n_renders) {
 }
 
 struct DescLayout {
-  uint64_t sets_off, renders_off, tile_starts_off, row_starts_off, rec_starts_off, bytes;
+  uint64_t sets_off, renders_off, tile_starts_off, row_starts_off, rec_starts_off;
+  uint64_t deg_ids_off[4], deg_starts_off[4];
+  uint64_t bytes;
 };
 
 DescLayout desc_layout(int n_sets, int n_renders) {
@@ -145,6 +147,12 @@ DescLayout desc_layout(int n_sets, int n_renders) {
   off = align_up(off + 4ull * (n_renders + 1), 64);
   d.rec_starts_off = off;
   off = align_up(off + 8ull * (n_renders + 1), 64);
+  for (int k = 0; k < 4; ++k) {
+    d.deg_ids_off[k] = off;
+    off = align_up(off + 4ull * n_sets, 64);
+    d.deg_starts_off[k] = off;
+    off = align_up(off + 4ull * (n_sets + 1), 64);
+  }
   d.bytes = off;
   return d;
 }
@@ -268,6 +276,24 @@ int pgsag_pack(const pgsag_config *cfg, const pgsag_gaussians *sets, const pgsag
   h->ws = make_layout(z, pair_capacity, n_renders);
   h->ws_bytes = h->ws.end;
   h->any_grads = set_grads != nullptr;
+  for (int k = 0; k < 4; ++k) {
+    h->deg_ids_off[k] = d.deg_ids_off[k];
+    h->deg_starts_off[k] = d.deg_starts_off[k];
+    int32_t *ids = reinterpret_cast<int32_t *>(base + d.deg_ids_off[k]);
+    uint32_t *starts = reinterpret_cast<uint32_t *>(base + d.deg_starts_off[k]);
+    uint32_t blocks = 0;
+    int cnt = 0;
+    for (int s2 = 0; s2 < n_sets; ++s2) {
+      if (sets[s2].sh_degree != k || sets[s2].n == 0) continue;
+      ids[cnt] = s2;
+      starts[cnt] = blocks;
+      blocks += (uint32_t)((sets[s2].n + 255) / 256);
+      ++cnt;
+    }
+    starts[cnt] = blocks;
+    h->deg_count[k] = cnt;
+    h->deg_blocks[k] = blocks;
+  }
 
   DevSet *ds = reinterpret_cast<DevSet *>(base + d.sets_off);
   uint64_t goff = 0;

@@ -3,9 +3,9 @@
 //
 // Pipeline (all counts stay on the device; grids are sized from host bounds
 // and blocks past the device count exit or contribute nothing):
-//   tile_mask     masked pixels per tile (one workgroup per tile row)
-//   sat           per-render summed-area table of active tiles, so a support
-//                 rectangle's active-tile count is four loads
+//   tile_mask     masked pixels per tile and, per tile row, the prefix count
+//                 of active tiles (one workgroup per tile row), so a support
+//                 rectangle's active-tile count is two loads per tile row
 //   compact       stable compaction of records with >= 1 active tile into
 //                 (depth key, record) lists
 //   radix sort    stable LSD sort of that list by the FP32 depth key
@@ -29,100 +29,6 @@ __global__ void fill_u32_kernel(uint32_t *p, uint32_t value, uint64_t n) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) p[i] = value;
-}
-
-// ------------------------------------------------------------ tile mask
-
-// One workgroup per global tile row: counts masked (or, without a mask,
-// in-image) pixels of each tile of that row.
-__global__ void __launch_bounds__(256) tile_mask_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
-  const Header &h = *header(desc);
-  const uint32_t row = blockIdx.x;
-  const int r = upper_index(row_starts_of(desc), h.n_renders, row);
-  const DevRender &rd = renders_of(desc)[r];
-  const int ty = (int)(row - row_starts_of(desc)[r]);
-  const int tile = h.cfg.tile;
-  const int W = rd.cam.W, H = rd.cam.H;
-  __shared__ uint32_t cnt[65536 / 8 + 1];  // tiles_x <= W / 8 + 1 for W <= 65535
-  for (int x = threadIdx.x; x < rd.tiles_x; x += blockDim.x) cnt[x] = 0;
-  __syncthreads();
-  const int y0 = ty * tile, y1 = min(H, y0 + tile);
-  if (rd.mask == nullptr) {
-    for (int x = threadIdx.x; x < rd.tiles_x; x += blockDim.x) {
-      const int w = min(W, (x + 1) * tile) - x * tile;
-      cnt[x] = (uint32_t)(w * (y1 - y0));
-    }
-  } else {
-    for (int y = y0; y < y1; ++y) {
-      const uint8_t *m = rd.mask + (uint64_t)y * W;
-      for (int x = threadIdx.x; x < W; x += blockDim.x) {
-        if (m[x]) atomicAdd(&cnt[x / tile], 1u);
-      }
-    }
-  }
-  __syncthreads();
-  uint32_t *tc = ws_ptr<uint32_t>(ws, h.ws.tile_count) + rd.tile_offset + (uint64_t)ty * rd.tiles_x;
-  for (int x = threadIdx.x; x < rd.tiles_x; x += blockDim.x) tc[x] = cnt[x];
-}
-
-// Row pass of the active-tile summed-area table: one thread per
-// (render, tile row); writes sat[y+1][x+1] = sum_{x' <= x} active(y, x').
-__global__ void sat_rows_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
-  const Header &h = *header(desc);
-  const uint32_t row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= h.n_tile_rows) return;
-  const int r = upper_index(row_starts_of(desc), h.n_renders, row);
-  const DevRender &rd = renders_of(desc)[r];
-  const int ty = (int)(row - row_starts_of(desc)[r]);
-  const uint32_t *tc = ws_ptr<uint32_t>(ws, h.ws.tile_count) + rd.tile_offset + (uint64_t)ty * rd.tiles_x;
-  uint32_t *st = ws_ptr<uint32_t>(ws, h.ws.sat) + rd.sat_offset;
-  const uint32_t pitch = rd.tiles_x + 1;
-  uint32_t acc = 0;
-  st[(ty + 1) * pitch] = 0;
-  if (ty == 0)
-    for (int x = 0; x <= rd.tiles_x; ++x) st[x] = 0;
-  for (int x = 0; x < rd.tiles_x; ++x) {
-    acc += tc[x] > 0 ? 1u : 0u;
-    st[(ty + 1) * pitch + x + 1] = acc;
-  }
-}
-
-// Column pass: one thread per (render, column) accumulates down the rows.
-__global__ void sat_cols_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
-  const Header &h = *header(desc);
-  const int r = blockIdx.y;
-  const DevRender &rd = renders_of(desc)[r];
-  const int x = blockIdx.x * blockDim.x + threadIdx.x + 1;
-  if (x > rd.tiles_x) return;
-  uint32_t *st = ws_ptr<uint32_t>(ws, h.ws.sat) + rd.sat_offset;
-  const uint32_t pitch = rd.tiles_x + 1;
-  uint32_t acc = 0;
-  for (int y = 1; y <= rd.tiles_y; ++y) {
-    acc += st[y * pitch + x];
-    st[y * pitch + x] = acc;
-  }
-}
-
-// Active tiles inside caller-provided rects (binning-only entry point).
-__global__ void recount_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
-  const Header &h = *header(desc);
-  const uint64_t rec = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (rec >= h.n_records) return;
-  const int r = upper_index(rec_starts_of(desc), h.n_renders, rec);
-  const DevRender &rd = renders_of(desc)[r];
-  uint32_t *nact = ws_ptr<uint32_t>(ws, h.ws.nact);
-  if (nact[rec] == 0) return;
-  const uint2 rr = ws_ptr<uint2>(ws, h.ws.rect)[rec];
-  uint32_t x0 = rr.x & 0xffffu, y0 = rr.x >> 16, x1 = rr.y & 0xffffu, y1 = rr.y >> 16;
-  x1 = min(x1, (uint32_t)rd.tiles_x);
-  y1 = min(y1, (uint32_t)rd.tiles_y);
-  uint32_t count = 0;
-  if (x0 < x1 && y0 < y1) {
-    const uint32_t *st = ws_ptr<uint32_t>(ws, h.ws.sat) + rd.sat_offset;
-    const uint32_t pitch = rd.tiles_x + 1;
-    count = st[y1 * pitch + x1] - st[y0 * pitch + x1] - st[y1 * pitch + x0] + st[y0 * pitch + x0];
-  }
-  nact[rec] = count;
 }
 
 // -------------------------------------------------------------- scans
@@ -155,6 +61,96 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *total) {
   __syncthreads();
   *total = tot;
   return off + inc - v;
+}
+
+// ------------------------------------------------------------ tile mask
+
+// Non-zero bytes of a 32-bit word.
+__device__ inline uint32_t nonzero_bytes(uint32_t w) {
+  uint32_t t = (w | (w >> 4)) & 0x0f0f0f0fu;
+  t |= t >> 2;
+  t = (t | (t >> 1)) & 0x01010101u;
+  return __popc(t);
+}
+
+// Non-zero bytes of m[x0, x1).
+__device__ inline uint32_t count_span(const uint8_t *m, int x0, int x1) {
+  uint32_t c = 0;
+  int x = x0;
+  while (x < x1 && ((uintptr_t)(m + x) & 3u)) c += m[x++] != 0;
+  for (; x + 4 <= x1; x += 4) c += nonzero_bytes(*reinterpret_cast<const uint32_t *>(m + x));
+  while (x < x1) c += m[x++] != 0;
+  return c;
+}
+
+// One workgroup per global tile row: masked (or, without a mask, in-image)
+// pixels of every tile of the row, and the row prefix of active flags
+// rowsat[ty][x] = number of active tiles among tiles 0..x-1 of row ty.
+__global__ void __launch_bounds__(256) tile_mask_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+  const Header &h = *header(desc);
+  const uint32_t row = blockIdx.x;
+  const int r = upper_index(row_starts_of(desc), h.n_renders, row);
+  const DevRender &rd = renders_of(desc)[r];
+  const int ty = (int)(row - row_starts_of(desc)[r]);
+  const int tile = h.cfg.tile;
+  const int W = rd.cam.W, H = rd.cam.H;
+  const int tx_n = rd.tiles_x;
+  __shared__ uint32_t cnt[65536 / 8 + 1];  // tiles_x <= 8192 for W <= 65535, tile >= 8
+  for (int x = threadIdx.x; x < tx_n; x += blockDim.x) cnt[x] = 0;
+  __syncthreads();
+  const int y0 = ty * tile, y1 = min(H, y0 + tile);
+  const int rows = y1 - y0;
+  if (rd.mask == nullptr) {
+    for (int x = threadIdx.x; x < tx_n; x += blockDim.x)
+      cnt[x] = (uint32_t)((min(W, (x + 1) * tile) - x * tile) * rows);
+  } else {
+    // one work item per (tile, pixel row): count a tile-wide span
+    for (int it = threadIdx.x; it < tx_n * rows; it += blockDim.x) {
+      const int x = it % tx_n, y = y0 + it / tx_n;
+      const int a = x * tile, b = min(W, a + tile);
+      const uint32_t c = count_span(rd.mask + (uint64_t)y * W, a, b);
+      if (c) atomicAdd(&cnt[x], c);
+    }
+  }
+  __syncthreads();
+  uint32_t *tc = ws_ptr<uint32_t>(ws, h.ws.tile_count) + rd.tile_offset + (uint64_t)ty * tx_n;
+  uint32_t *rs = ws_ptr<uint32_t>(ws, h.ws.sat) + rd.sat_offset + (uint64_t)ty * (tx_n + 1);
+  if (threadIdx.x == 0) rs[0] = 0;
+  uint32_t running = 0;
+  for (int base = 0; base < tx_n; base += blockDim.x) {
+    const int x = base + threadIdx.x;
+    uint32_t v = 0;
+    if (x < tx_n) {
+      tc[x] = cnt[x];
+      v = cnt[x] > 0 ? 1u : 0u;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(v, &tot);
+    if (x < tx_n) rs[x + 1] = running + ex + v;
+    running += tot;
+  }
+}
+
+// Active tiles inside caller-provided rects (binning-only entry point).
+__global__ void recount_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+  const Header &h = *header(desc);
+  const uint64_t rec = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (rec >= h.n_records) return;
+  const int r = upper_index(rec_starts_of(desc), h.n_renders, rec);
+  const DevRender &rd = renders_of(desc)[r];
+  uint32_t *nact = ws_ptr<uint32_t>(ws, h.ws.nact);
+  if (nact[rec] == 0) return;
+  const uint2 rr = ws_ptr<uint2>(ws, h.ws.rect)[rec];
+  uint32_t x0 = rr.x & 0xffffu, y0 = rr.x >> 16, x1 = rr.y & 0xffffu, y1 = rr.y >> 16;
+  x1 = min(x1, (uint32_t)rd.tiles_x);
+  y1 = min(y1, (uint32_t)rd.tiles_y);
+  uint32_t count = 0;
+  if (x0 < x1 && y0 < y1) {
+    const uint32_t *st = ws_ptr<uint32_t>(ws, h.ws.sat) + rd.sat_offset;
+    const uint32_t pitch = rd.tiles_x + 1;
+    for (uint32_t y = y0; y < y1; ++y) count += st[y * pitch + x1] - st[y * pitch + x0];
+  }
+  nact[rec] = count;
 }
 
 __device__ inline uint64_t bounded_count(const uint32_t *n_dev, uint64_t n_bound) {
@@ -492,12 +488,6 @@ void launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t s) {
 
 void launch_tile_mask(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
   hipLaunchKernelGGL(tile_mask_kernel, dim3(h.n_tile_rows), dim3(256), 0, s, d_desc, ws);
-  hipLaunchKernelGGL(sat_rows_kernel, dim3(blocks_for(h.n_tile_rows, 64)), dim3(64), 0, s, d_desc, ws);
-  // columns: max tiles_x over renders bounds the x grid
-  const DevRender *rd = renders_of(&h);  // host copy of the descriptor
-  int maxtx = 1;
-  for (int r = 0; r < h.n_renders; ++r) maxtx = rd[r].tiles_x > maxtx ? rd[r].tiles_x : maxtx;
-  hipLaunchKernelGGL(sat_cols_kernel, dim3(blocks_for(maxtx, 64), h.n_renders), dim3(64), 0, s, d_desc, ws);
 }
 
 void launch_recount(const void *d_desc, const Header &h, void *ws, hipStream_t s) {

@@ -2,19 +2,28 @@
 // and its backward pass.
 //
 // Shape: one workgroup per tile of T x T pixels, one lane per pixel (each
-// pixel is a GPU thread, Sec. 4.3); a wave covers an 8 x 8 sub-block.  The
+// pixel is a GPU thread, Sec. 4.3); a wave covers an 8 x 8 pixel block.  The
 // tile's depth-ordered list of projected records is staged through LDS in
-// batches of T*T records (one coalesced 64-byte record load per lane).
-// Before touching a record a wave compares the record's support box with
-// its 8 x 8 pixel block and skips it as a whole if they do not meet; lanes
-// whose pixel is unmasked or whose transmittance has stopped idle, and the
-// workgroup leaves the tile when no lane is alive (__syncthreads_count).
+// batches (one coalesced 64-byte record load per lane).  After each batch
+// load every wave builds its own list of the records that can reach the
+// alpha cut-off somewhere in its block -- an exact minimum of the record's
+// quadratic form over the block's pixel centres -- compacted with ballots.
+// A list entry carries the record's exponent expanded around the block
+// origin, so that a lane evaluates
+//     e = log2(o) - q/2 * log2(e)  as  F + D lx + E ly + A lx^2 + B lx ly + C ly^2
+// with five FMAs from its constant (lx, ly) offsets, compares e with
+// log2(alpha_min) and calls exp2 only when the fragment passes.  Lanes whose
+// pixel is unmasked or whose transmittance has stopped idle; the workgroup
+// leaves the tile when no lane is alive (__syncthreads_count).
 //
 // The backward pass walks the same list back to front from the tile's
 // largest last-blended index, recovering each pixel's transmittance before a
 // fragment as T_i = T_{i+1} / (1 - alpha_i) from the saved final T, keeps the
 // suffix sums of the blended features, and reduces the 13 per-fragment 2D
-// gradients across the wave before one float atomic per value per wave.
+// gradients across the wave (VALU lane exchanges only) before one float
+// atomic per value per wave (13 lanes of one instruction, one cache line).
+// It builds its lists with the same code as the forward pass, so it takes
+// the forward's decisions.
 //
 // In persistent mode a grid of (CUs x occupancy) workgroups pulls chunks of
 // tiles from an LPT-ordered queue with an atomic counter; every workgroup
@@ -24,42 +33,110 @@
 namespace pgsag {
 namespace {
 
-constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
 
-// Records staged per LDS batch: one per lane, at most 512 (32 KB).
+// Records staged per LDS batch (64 for 8x8 tiles, else 128: keeps several
+// workgroups resident per CU).
 template <int T>
-constexpr int batch_of() { return T * T < 512 ? T * T : 512; }
+constexpr int batch_of() { return T == 8 ? 64 : 128; }
 
-// alpha of a record at pixel centre (px, py); the same instruction sequence
-// is used by the forward and backward kernels so they take identical
-// skip decisions.
-__device__ __forceinline__ float eval_alpha(float px, float py, const float4 &r0, float cc, float o,
-                                            float amax, float &dx, float &dy, float &G, float &raw) {
-#pragma clang fp contract(off)
-  dx = px - r0.x;
-  dy = py - r0.y;
-  const float dxy = dx * dy;
-  const float dxx = dx * dx;
-  const float dyy = dy * dy;
-  const float b2 = 2.f * r0.w;
-  const float cross = b2 * dxy;
-  const float q = __builtin_fmaf(cc, dyy, __builtin_fmaf(r0.z, dxx, cross));
-  const float arg = (-0.5f * kLog2e) * q;
-  G = __builtin_amdgcn_exp2f(arg);
-  raw = o * G;
-  return fminf(amax, raw);
+struct Entry {   // one record in one wave's list (16 bytes)
+  float F, D, E;
+  uint32_t k;    // slot of the record in the batch
+};
+
+// Minimum of a x^2 + 2 b x y + c y^2 (a, c > 0, ac > b^2) over the box
+// [x0, x1] x [y0, y1]: zero when the box holds the origin, otherwise the
+// smallest of the four edge minima.
+__device__ __forceinline__ float qmin_box(float a, float b, float c, float x0, float x1, float y0, float y1) {
+  if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return 0.f;
+  const float ia = 1.f / a, ic = 1.f / c;
+  float best = 3.0e38f;
+  {
+    const float y = y0, x = fminf(fmaxf(-b * y * ia, x0), x1);
+    best = fminf(best, a * x * x + 2.f * b * x * y + c * y * y);
+  }
+  {
+    const float y = y1, x = fminf(fmaxf(-b * y * ia, x0), x1);
+    best = fminf(best, a * x * x + 2.f * b * x * y + c * y * y);
+  }
+  {
+    const float x = x0, y = fminf(fmaxf(-b * x * ic, y0), y1);
+    best = fminf(best, a * x * x + 2.f * b * x * y + c * y * y);
+  }
+  {
+    const float x = x1, y = fminf(fmaxf(-b * x * ic, y0), y1);
+    best = fminf(best, a * x * x + 2.f * b * x * y + c * y * y);
+  }
+  return best;
 }
 
-__device__ __forceinline__ bool wave_culls(const float4 &r0, const float4 &r3, float wx0, float wx1, float wy0,
-                                           float wy1) {
-  return (r0.x + r3.y < wx0) || (r0.x - r3.y > wx1) || (r0.y + r3.z < wy0) || (r0.y - r3.z > wy1);
+// Builds this wave's list for batch slots [0, cnt): records whose exponent
+// can reach log2(alpha_min) (with a small margin) at one of the block's
+// pixel centres, with their exponent expansion around the block origin
+// (ox, oy).  Returns the list length (uniform across the wave).
+__device__ __forceinline__ int build_list(const float4 (*srec)[4], int cnt, float ox, float oy, float l2min,
+                                          Entry *list) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int len = 0;
+  for (int base = 0; base < cnt; base += 64) {
+    const int k = base + lane;
+    bool pass = false;
+    float F = 0.f, D = 0.f, E = 0.f;
+    if (k < cnt) {
+      const float4 r0 = srec[k][0];
+      const float4 r1 = srec[k][1];
+      const float4 r3 = srec[k][3];
+      const float a = r0.z, b = r0.w, c = r1.x, l2o = r3.w;
+      const float dx0 = ox - r0.x, dy0 = oy - r0.y;
+      const float qm = qmin_box(a, b, c, dx0, dx0 + 7.f, dy0, dy0 + 7.f);
+      pass = l2o - kHalfLog2e * qm >= l2min - 1e-3f;
+      if (pass) {
+        const float q0 = a * dx0 * dx0 + 2.f * b * dx0 * dy0 + c * dy0 * dy0;
+        F = l2o - kHalfLog2e * q0;
+        D = -2.f * kHalfLog2e * (a * dx0 + b * dy0);
+        E = -2.f * kHalfLog2e * (b * dx0 + c * dy0);
+      }
+    }
+    const uint64_t m = __ballot(pass);
+    if (pass) {
+      Entry e;
+      e.F = F;
+      e.D = D;
+      e.E = E;
+      e.k = (uint32_t)k;
+      list[len + __popcll(m & lt)] = e;
+    }
+    len += __popcll(m);
+  }
+  __builtin_amdgcn_wave_barrier();
+  return len;
+}
+
+// Exponent of an entry at this lane: F + D lx + E ly + A lx^2 + B lx ly + C ly^2
+// with (A, B, C) = -log2(e)/2 (a, 2b, c).  One instruction sequence shared by
+// the forward and backward kernels.
+struct LaneOffsets {
+  float lx, ly, lxx, lxy, lyy;
+};
+
+__device__ __forceinline__ float lane_exponent(const Entry &e, const float4 &abc, const LaneOffsets &L) {
+#pragma clang fp contract(off)
+  float v = __builtin_fmaf(e.E, L.ly, e.F);
+  v = __builtin_fmaf(e.D, L.lx, v);
+  v = __builtin_fmaf(abc.z, L.lyy, v);
+  v = __builtin_fmaf(abc.y, L.lxy, v);
+  v = __builtin_fmaf(abc.x, L.lxx, v);
+  return v;
 }
 
 struct TileGeom {
   const DevRender *rd;
-  int px, py;       // pixel of this lane
+  int px, py;   // pixel of this lane
   bool inside;
-  float wx0, wx1, wy0, wy1;  // pixel-centre box of this lane's wave
+  float ox, oy; // pixel centre of the wave's block origin
+  LaneOffsets L;
 };
 
 template <int T>
@@ -70,21 +147,46 @@ __device__ __forceinline__ void tile_geom(const void *desc, const Header &h, uin
   const uint32_t local = tile - rd.tile_offset;
   const int tx = (int)(local % (uint32_t)rd.tiles_x), ty = (int)(local / (uint32_t)rd.tiles_x);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  constexpr int SB = T / 8;  // 8x8 sub-blocks per tile side
+  constexpr int SB = T / 8;  // 8x8 blocks per tile side
   const int sbx = wave % SB, sby = wave / SB;
   const int bx = tx * T + sbx * 8, by = ty * T + sby * 8;
-  g.px = bx + (lane & 7);
-  g.py = by + (lane >> 3);
+  const int lx = lane & 7, ly = lane >> 3;
+  g.px = bx + lx;
+  g.py = by + ly;
   g.inside = g.px < rd.cam.W && g.py < rd.cam.H;
-  g.wx0 = bx + 0.5f;
-  g.wx1 = bx + 7.5f;
-  g.wy0 = by + 0.5f;
-  g.wy1 = by + 7.5f;
+  g.ox = bx + 0.5f;
+  g.oy = by + 0.5f;
+  g.L.lx = (float)lx;
+  g.L.ly = (float)ly;
+  g.L.lxx = (float)(lx * lx);
+  g.L.lxy = (float)(lx * ly);
+  g.L.lyy = (float)(ly * ly);
+}
+
+// Stages batch records [j0, j1) into LDS: the raw 64-byte records and the
+// per-record exponent coefficients (A, B, C).
+template <int NT>
+__device__ __forceinline__ void stage_batch(const float4 *__restrict__ rec4, const uint32_t *__restrict__ vals,
+                                            uint32_t j0, uint32_t j1, float4 (*srec)[4], float4 *sabc,
+                                            uint32_t *sid) {
+  const uint32_t j = j0 + threadIdx.x;
+  if (threadIdx.x < NT && j < j1) {
+    const uint32_t rid = vals[j];
+    const float4 *src = rec4 + (uint64_t)rid * 4;
+    const float4 r0 = src[0], r1 = src[1];
+    srec[threadIdx.x][0] = r0;
+    srec[threadIdx.x][1] = r1;
+    srec[threadIdx.x][2] = src[2];
+    srec[threadIdx.x][3] = src[3];
+    sabc[threadIdx.x] = make_float4(-kHalfLog2e * r0.z, -2.f * kHalfLog2e * r0.w, -kHalfLog2e * r1.x, 0.f);
+    if (sid) sid[threadIdx.x] = rid;
+  }
 }
 
 template <int T>
 __device__ void forward_tile(const void *__restrict__ desc, const Header &h, void *__restrict__ ws, uint32_t tile,
-                             float4 (*srec)[4], const uint32_t *__restrict__ vals) {
+                             float4 (*srec)[4], float4 *sabc, Entry (*lists)[batch_of<T>()],
+                             const uint32_t *__restrict__ vals) {
   constexpr int NT = batch_of<T>();
   TileGeom g;
   tile_geom<T>(desc, h, tile, g);
@@ -94,61 +196,53 @@ __device__ void forward_tile(const void *__restrict__ desc, const Header &h, voi
   const bool masked = g.inside && (rd.mask == nullptr || rd.mask[pix] != 0);
   const uint2 rg = ws_ptr<uint2>(ws, h.ws.ranges)[tile];
   const float4 *rec4 = ws_ptr<float4>(ws, h.ws.rec);
-  const float amin = h.cfg.alpha_min, amax = h.cfg.alpha_max, tmin = h.cfg.t_min;
-  const float fx = g.px + 0.5f, fy = g.py + 0.5f;
+  const float amax = h.cfg.alpha_max, tmin = h.cfg.t_min;
+  const float l2min = __log2f(h.cfg.alpha_min);
+  Entry *list = lists[threadIdx.x >> 6];
   bool done = !masked;
   float Tr = 1.f;
   float F[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   int32_t n = 0, last = -1;
   for (uint32_t b = rg.x; b < rg.y; b += NT) {
     if (__syncthreads_count(!done) == 0) break;
-    const uint32_t j = b + threadIdx.x;
-    if (threadIdx.x < NT && j < rg.y) {
-      const uint64_t rid = vals[j];
-      const float4 *src = rec4 + rid * 4;
-      srec[threadIdx.x][0] = src[0];
-      srec[threadIdx.x][1] = src[1];
-      srec[threadIdx.x][2] = src[2];
-      srec[threadIdx.x][3] = src[3];
-    }
+    const uint32_t b1 = min(rg.y, b + NT);
+    stage_batch<NT>(rec4, vals, b, b1, srec, sabc, nullptr);
     __syncthreads();
-    const int cnt = (int)min((uint32_t)NT, rg.y - b);
-    if (__ballot(!done) != 0ull) {
-      for (int k = 0; k < cnt; ++k) {
-        const float4 r0 = srec[k][0];
-        const float4 r3 = srec[k][3];
-        if (wave_culls(r0, r3, g.wx0, g.wx1, g.wy0, g.wy1)) continue;
-        if (!done) {
-          const float4 r1 = srec[k][1];
-          float dx, dy, G, raw;
-          const float a = eval_alpha(fx, fy, r0, r1.x, r1.y, amax, dx, dy, G, raw);
-          if (a >= amin) {
-            const float Tn = Tr * (1.f - a);
-            if (Tn < tmin) {
-              done = true;
-            } else {
-              const float4 r2 = srec[k][2];
-              const float w = a * Tr;
-              F[0] = fmaf(w, r1.z, F[0]);
-              F[1] = fmaf(w, r1.w, F[1]);
-              F[2] = fmaf(w, r2.x, F[2]);
-              F[3] = fmaf(w, r2.y, F[3]);
-              F[4] = fmaf(w, r2.z, F[4]);
-              F[5] = fmaf(w, r2.w, F[5]);
-              F[6] = fmaf(w, r3.x, F[6]);
-              Tr = Tn;
-              ++n;
-              last = (int32_t)(b + k);
-            }
+    if (__ballot(!done) == 0ull) continue;
+    const int len = build_list(srec, (int)(b1 - b), g.ox, g.oy, l2min, list);
+    for (int t = 0; t < len; ++t) {
+      const Entry e = list[t];
+      if (!done) {
+        const float ex = lane_exponent(e, sabc[e.k], g.L);
+        if (ex >= l2min) {
+          const float a = fminf(amax, __builtin_amdgcn_exp2f(ex));
+          const float Tn = Tr * (1.f - a);
+          if (Tn < tmin) {
+            done = true;
+          } else {
+            const float4 r1 = srec[e.k][1], r2 = srec[e.k][2];
+            const float d = srec[e.k][3].x;
+            const float w = a * Tr;
+            F[0] = fmaf(w, r1.z, F[0]);
+            F[1] = fmaf(w, r1.w, F[1]);
+            F[2] = fmaf(w, r2.x, F[2]);
+            F[3] = fmaf(w, r2.y, F[3]);
+            F[4] = fmaf(w, r2.z, F[4]);
+            F[5] = fmaf(w, r2.w, F[5]);
+            F[6] = fmaf(w, d, F[6]);
+            Tr = Tn;
+            ++n;
+            last = (int32_t)(b + e.k);
           }
         }
-        if ((k & 7) == 7 && __ballot(!done) == 0ull) break;
       }
+      if ((t & 7) == 7 && __ballot(!done) == 0ull) break;
     }
   }
   if (!g.inside) return;
   const uint64_t HW = (uint64_t)rd.cam.H * W;
   float rgb0 = 0.f, rgb1 = 0.f, rgb2 = 0.f, alpha = 0.f, depth = 0.f;
+  const float fx = g.px + 0.5f, fy = g.py + 0.5f;
   if (masked) {
     rgb0 = F[0] + Tr * h.cfg.bg[0];
     rgb1 = F[1] + Tr * h.cfg.bg[1];
@@ -178,48 +272,51 @@ __device__ void forward_tile(const void *__restrict__ desc, const Header &h, voi
   ws_ptr<int32_t>(ws, h.ws.pix_last)[rd.pixel_offset + pix] = masked ? last : -1;
 }
 
-// Sum of v[0..15] over the 64 lanes of a wave by recursive halving: after
-// the call lane L holds the total of value (L >> 2) & 15.
-__device__ __forceinline__ float wave_reduce16(float v[16]) {
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), CTRL, 0xf, 0xf, false));
+}
+
+// Sum of v[0..15] over the 64 lanes of a wave by recursive halving, using
+// only VALU lane exchanges: permlane32/16 swaps for lane distance 32 and 16,
+// DPP row rotate by 8, half-row mirror and quad permutations below that.
+// Each step keeps half of the values per lane and adds the partner lane's
+// copy of them.  Afterwards lane L holds the total of value (L >> 2) & 15.
+__device__ __forceinline__ float wave_reduce16(const float v[16]) {
   const int lane = threadIdx.x & 63;
   float w8[8], w4[4], w2[2];
-  {
-    const bool hi = lane & 32;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const float mine = hi ? v[8 + s] : v[s];
-      const float send = hi ? v[s] : v[8 + s];
-      w8[s] = mine + __shfl_xor(send, 32, 64);
-    }
+  for (int s = 0; s < 8; ++s) {
+    // lanes 0..31 keep v[s], lanes 32..63 keep v[8 + s]
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[s]), __float_as_uint(v[8 + s]), false, false);
+    w8[s] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    // lanes with bit 4 clear keep w8[s], the others w8[4 + s]
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w8[s]), __float_as_uint(w8[4 + s]), false, false);
+    w4[s] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
   {
-    const bool hi = lane & 16;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const float mine = hi ? w8[4 + s] : w8[s];
-      const float send = hi ? w8[s] : w8[4 + s];
-      w4[s] = mine + __shfl_xor(send, 16, 64);
-    }
-  }
-  {
-    const bool hi = lane & 8;
+    const bool hi = lane & 8;  // partner: lane ^ 8 (row rotate by 8)
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const float mine = hi ? w4[2 + s] : w4[s];
       const float send = hi ? w4[s] : w4[2 + s];
-      w2[s] = mine + __shfl_xor(send, 8, 64);
+      w2[s] = mine + dpp<0x128>(send);
     }
   }
-  const bool hi = lane & 4;
-  float x = (hi ? w2[1] : w2[0]) + __shfl_xor(hi ? w2[0] : w2[1], 4, 64);
-  x += __shfl_xor(x, 2, 64);
-  x += __shfl_xor(x, 1, 64);
+  const bool hi = lane & 4;  // partner: mirrored lane in the same 8-lane half row
+  float x = (hi ? w2[1] : w2[0]) + dpp<0x141>(hi ? w2[0] : w2[1]);
+  x += dpp<0x4e>(x);  // quad permutation: lane ^ 2
+  x += dpp<0xb1>(x);  // quad permutation: lane ^ 1
   return x;
 }
 
 template <int T>
 __device__ void backward_tile(const void *__restrict__ desc, const Header &h, void *__restrict__ ws, uint32_t tile,
-                              float4 (*srec)[4], uint32_t *sid, int *smax, const uint32_t *__restrict__ vals) {
+                              float4 (*srec)[4], float4 *sabc, uint32_t *sid, Entry (*lists)[batch_of<T>()],
+                              int *smax, const uint32_t *__restrict__ vals) {
   constexpr int NT = batch_of<T>();
   TileGeom g;
   tile_geom<T>(desc, h, tile, g);
@@ -231,8 +328,10 @@ __device__ void backward_tile(const void *__restrict__ desc, const Header &h, vo
   const uint2 rg = ws_ptr<uint2>(ws, h.ws.ranges)[tile];
   const float4 *rec4 = ws_ptr<float4>(ws, h.ws.rec);
   float *g2 = ws_ptr<float>(ws, h.ws.g2);
-  const float amin = h.cfg.alpha_min, amax = h.cfg.alpha_max;
+  const float amax = h.cfg.alpha_max;
+  const float l2min = __log2f(h.cfg.alpha_min);
   const float fx = g.px + 0.5f, fy = g.py + 0.5f;
+  Entry *list = lists[threadIdx.x >> 6];
 
   int32_t last = -1;
   float Tr = 1.f, Tf = 1.f;
@@ -285,64 +384,60 @@ __device__ void backward_tile(const void *__restrict__ desc, const Header &h, vo
   const int lane = threadIdx.x & 63;
   for (int64_t bend = end; bend > (int64_t)rg.x; bend -= NT) {
     const uint32_t bstart = (uint32_t)max((int64_t)rg.x, bend - NT);
-    __syncthreads();
-    const uint32_t j = bstart + threadIdx.x;
-    if (threadIdx.x < NT && j < (uint32_t)bend) {
-      const uint32_t rid = vals[j];
-      const float4 *src = rec4 + (uint64_t)rid * 4;
-      srec[threadIdx.x][0] = src[0];
-      srec[threadIdx.x][1] = src[1];
-      srec[threadIdx.x][2] = src[2];
-      srec[threadIdx.x][3] = src[3];
-      sid[threadIdx.x] = rid;
-    }
-    __syncthreads();
     const int cnt = (int)((uint32_t)bend - bstart);
-    if (__ballot(last >= (int32_t)bstart) == 0ull) continue;
-    for (int k = cnt - 1; k >= 0; --k) {
-      const float4 r0 = srec[k][0];
-      const float4 r3 = srec[k][3];
-      if (wave_culls(r0, r3, g.wx0, g.wx1, g.wy0, g.wy1)) continue;
-      const int32_t idx = (int32_t)(bstart + k);
-      float v[16];
+    __syncthreads();
+    stage_batch<NT>(rec4, vals, bstart, (uint32_t)bend, srec, sabc, sid);
+    __syncthreads();
+    if (__ballot(last >= (int32_t)bstart) != 0ull) {
+      const int len = build_list(srec, cnt, g.ox, g.oy, l2min, list);
+      for (int t = len - 1; t >= 0; --t) {
+        const Entry e = list[t];
+        const int32_t idx = (int32_t)(bstart + e.k);
+        float v[16];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) v[c] = 0.f;
-      bool contrib = false;
-      if (idx <= last) {
-        const float4 r1 = srec[k][1];
-        float dx, dy, G, raw;
-        const float a = eval_alpha(fx, fy, r0, r1.x, r1.y, amax, dx, dy, G, raw);
-        if (a >= amin) {
-          contrib = true;
-          const float4 r2 = srec[k][2];
-          const float f[7] = {r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
-          const float om = 1.f - a;
-          const float iom = 1.f / om;
-          const float Tp = Tr * iom;
-          const float w = a * Tp;
-          float dLda = ga * Tf * iom;
+        for (int c = 0; c < 16; ++c) v[c] = 0.f;
+        bool contrib = false;
+        if (idx <= last) {
+          const float ex = lane_exponent(e, sabc[e.k], g.L);
+          if (ex >= l2min) {
+            contrib = true;
+            const float raw = __builtin_amdgcn_exp2f(ex);
+            const float a = fminf(amax, raw);
+            const float4 r0 = srec[e.k][0], r1 = srec[e.k][1], r2 = srec[e.k][2];
+            const float d = srec[e.k][3].x;
+            const float f[7] = {r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, d};
+            const float om = 1.f - a;
+            const float iom = 1.f / om;
+            const float Tp = Tr * iom;
+            const float w = a * Tp;
+            float dLda = ga * Tf * iom;
 #pragma unroll
-          for (int c = 0; c < 7; ++c) {
-            dLda += gch[c] * (Tp * f[c] - S[c] * iom);
-            v[6 + c] = w * gch[c];
-            S[c] = fmaf(w, f[c], S[c]);
-          }
-          Tr = Tp;
-          if (raw <= amax) {
-            v[G_O] = dLda * G;
-            const float dLdq = -0.5f * a * dLda;
-            v[G_MX] = -2.f * dLdq * (r0.z * dx + r0.w * dy);
-            v[G_MY] = -2.f * dLdq * (r0.w * dx + r1.x * dy);
-            v[G_CA] = dLdq * dx * dx;
-            v[G_CB] = 2.f * dLdq * dx * dy;
-            v[G_CC] = dLdq * dy * dy;
+            for (int c = 0; c < 7; ++c) {
+              dLda += gch[c] * (Tp * f[c] - S[c] * iom);
+              v[6 + c] = w * gch[c];
+              S[c] = fmaf(w, f[c], S[c]);
+            }
+            Tr = Tp;
+            if (raw <= amax) {
+              // alpha = o G with G = exp(-q/2): dalpha/do = G = alpha / o,
+              // dalpha/dq = -alpha / 2
+              const float dx = fx - r0.x, dy = fy - r0.y;
+              v[G_O] = dLda * (a / r1.y);
+              const float dLdq = -0.5f * a * dLda;
+              v[G_MX] = -2.f * dLdq * (r0.z * dx + r0.w * dy);
+              v[G_MY] = -2.f * dLdq * (r0.w * dx + r1.x * dy);
+              v[G_CA] = dLdq * dx * dx;
+              v[G_CB] = 2.f * dLdq * dx * dy;
+              v[G_CC] = dLdq * dy * dy;
+            }
           }
         }
+        if (__ballot(contrib) == 0ull) continue;
+        const float tot = wave_reduce16(v);
+        const int which = (lane >> 2) & 15;
+        if ((lane & 3) == 0 && which < 13 && tot != 0.f)
+          unsafeAtomicAdd(g2 + (uint64_t)sid[e.k] * kG2 + which, tot);
       }
-      if (__ballot(contrib) == 0ull) continue;
-      const float tot = wave_reduce16(v);
-      const int which = (lane >> 2) & 15;
-      if ((lane & 3) == 0 && which < 13) unsafeAtomicAdd(g2 + (uint64_t)sid[k] * kG2 + which, tot);
     }
   }
 }
@@ -350,11 +445,14 @@ __device__ void backward_tile(const void *__restrict__ desc, const Header &h, vo
 template <int T>
 __global__ void __launch_bounds__(T *T) forward_kernel(const void *__restrict__ desc, void *__restrict__ ws,
                                                         const uint32_t *__restrict__ vals) {
-  __shared__ float4 srec[batch_of<T>()][4];
+  constexpr int NT = batch_of<T>();
+  __shared__ float4 srec[NT][4];
+  __shared__ float4 sabc[NT];
+  __shared__ Entry lists[T * T / 64][NT];
   __shared__ uint32_t s_item;
   const Header &h = *header(desc);
   if (!h.cfg.persistent) {
-    forward_tile<T>(desc, h, ws, blockIdx.x, srec, vals);
+    forward_tile<T>(desc, h, ws, blockIdx.x, srec, sabc, lists, vals);
     return;
   }
   uint32_t *ctr = ws_ptr<uint32_t>(ws, h.ws.status) + S_QUEUE_FWD;
@@ -370,7 +468,7 @@ __global__ void __launch_bounds__(T *T) forward_kernel(const void *__restrict__ 
     const uint32_t stop = min(ntiles, base + chunk);
     for (uint32_t it = base; it < stop; ++it) {
       __syncthreads();
-      forward_tile<T>(desc, h, ws, queue[it], srec, vals);
+      forward_tile<T>(desc, h, ws, queue[it], srec, sabc, lists, vals);
     }
   }
 }
@@ -378,13 +476,16 @@ __global__ void __launch_bounds__(T *T) forward_kernel(const void *__restrict__ 
 template <int T>
 __global__ void __launch_bounds__(T *T) backward_kernel(const void *__restrict__ desc, void *__restrict__ ws,
                                                          const uint32_t *__restrict__ vals) {
-  __shared__ float4 srec[batch_of<T>()][4];
-  __shared__ uint32_t sid[batch_of<T>()];
+  constexpr int NT = batch_of<T>();
+  __shared__ float4 srec[NT][4];
+  __shared__ float4 sabc[NT];
+  __shared__ uint32_t sid[NT];
+  __shared__ Entry lists[T * T / 64][NT];
   __shared__ int smax;
   __shared__ uint32_t s_item;
   const Header &h = *header(desc);
   if (!h.cfg.persistent) {
-    backward_tile<T>(desc, h, ws, blockIdx.x, srec, sid, &smax, vals);
+    backward_tile<T>(desc, h, ws, blockIdx.x, srec, sabc, sid, lists, &smax, vals);
     return;
   }
   uint32_t *ctr = ws_ptr<uint32_t>(ws, h.ws.status) + S_QUEUE_BWD;
@@ -400,7 +501,7 @@ __global__ void __launch_bounds__(T *T) backward_kernel(const void *__restrict__
     const uint32_t stop = min(ntiles, base + chunk);
     for (uint32_t it = base; it < stop; ++it) {
       __syncthreads();
-      backward_tile<T>(desc, h, ws, queue[it], srec, sid, &smax, vals);
+      backward_tile<T>(desc, h, ws, queue[it], srec, sabc, sid, lists, &smax, vals);
     }
   }
 }

@@ -28,7 +28,7 @@ enum RecField {
   R_NX = 9, R_NY = 10, R_NZ = 11,  // camera-frame normal
   R_D = 12,                        // plane distance
   R_RX = 13, R_RY = 14,            // support half-widths (pixels, with margin)
-  R_PAD = 15
+  R_LOG2O = 15                     // log2(opacity)
 };
 
 // 2D-gradient slot layout (floats).
@@ -66,7 +66,7 @@ struct DevRender {
   uint64_t record_offset;  // first record of this render
   uint64_t pixel_offset;   // first per-pixel state slot
   uint32_t tile_offset;    // first global tile id
-  uint32_t sat_offset;     // first SAT entry ((tiles_y+1)*(tiles_x+1) entries)
+  uint32_t sat_offset;     // first row-prefix entry (tiles_y rows of tiles_x+1)
   uint32_t row_offset;     // first global tile row
   uint32_t reserved2;
 };
@@ -97,6 +97,12 @@ struct Header {
   uint64_t sets_off, renders_off, tile_starts_off, rec_starts_off, row_starts_off;
   uint64_t desc_bytes, ws_bytes;
   int32_t any_grads, reserved;
+  // Sets grouped by SH degree for the degree-specialised projection kernels:
+  // deg_ids[d] -> int32 [deg_count[d]] set indices, deg_starts[d] -> uint32
+  // [deg_count[d] + 1] prefix of 256-thread blocks.
+  uint64_t deg_ids_off[4], deg_starts_off[4];
+  int32_t deg_count[4];
+  uint32_t deg_blocks[4];
   Layout ws;
 };
 
@@ -127,6 +133,13 @@ __host__ __device__ inline T *ws_ptr(void *ws, uint64_t off) {
 template <typename T>
 __host__ __device__ inline const T *ws_ptr(const void *ws, uint64_t off) {
   return reinterpret_cast<const T *>(static_cast<const char *>(ws) + off);
+}
+
+__host__ __device__ inline const int32_t *deg_ids_of(const void *d, int k) {
+  return reinterpret_cast<const int32_t *>(static_cast<const char *>(d) + header(d)->deg_ids_off[k]);
+}
+__host__ __device__ inline const uint32_t *deg_starts_of(const void *d, int k) {
+  return reinterpret_cast<const uint32_t *>(static_cast<const char *>(d) + header(d)->deg_starts_off[k]);
 }
 
 // Largest i in [0, n) with a[i] <= x (a ascending, a[0] == 0).

@@ -119,15 +119,6 @@ __device__ inline void quat_rot_vjp(float w, float x, float y, float z, const fl
               x * G[6] + y * G[7]);
 }
 
-__device__ inline int find_set(const DevSet *sets, int n_sets, uint64_t g) {
-  int lo = 0, hi = n_sets - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (sets[mid].gauss_offset <= g) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 struct Raw {
   float mx, my, mz;
   float ls[3], s[3];
@@ -135,6 +126,7 @@ struct Raw {
   float logit, o;
   float M[9];  // rotation of the Gaussian
   int jstar;
+  float ax, ay, az;  // column jstar of M (the Gaussian normal, world frame)
 };
 
 __device__ inline void load_raw(const DevSet &S, int64_t i, Raw &g) {
@@ -158,6 +150,11 @@ __device__ inline void load_raw(const DevSet &S, int64_t i, Raw &g) {
   if (g.ls[1] < g.ls[j]) j = 1;
   if (g.ls[2] < g.ls[j]) j = 2;
   g.jstar = j;
+  // arithmetic selection keeps M in registers (no addressable array)
+  const float e0 = j == 0 ? 1.f : 0.f, e1 = j == 1 ? 1.f : 0.f, e2 = j == 2 ? 1.f : 0.f;
+  g.ax = e0 * g.M[0] + e1 * g.M[1] + e2 * g.M[2];
+  g.ay = e0 * g.M[3] + e1 * g.M[4] + e2 * g.M[5];
+  g.az = e0 * g.M[6] + e1 * g.M[7] + e2 * g.M[8];
 }
 
 // FP32 depth key of the mean: ((R20 x + R21 y) + R22 z) + t2, each operation
@@ -224,7 +221,7 @@ __device__ inline void project_view(const DevCamera &c, const Header &h, const R
   v.mx = c.fx * rx + c.cx;
   v.my = c.fy * ry + c.cy;
   // normal: axis j* of the Gaussian rotation, into the camera frame
-  const float ax = g.M[g.jstar], ay = g.M[3 + g.jstar], az = g.M[6 + g.jstar];
+  const float ax = g.ax, ay = g.ay, az = g.az;
   float n0 = R[0] * ax + R[1] * ay + R[2] * az;
   float n1 = R[3] * ax + R[4] * ay + R[5] * az;
   float n2 = R[6] * ax + R[7] * ay + R[8] * az;
@@ -238,24 +235,38 @@ __device__ inline void project_view(const DevCamera &c, const Header &h, const R
   v.dir[0] = dx * il; v.dir[1] = dy * il; v.dir[2] = dz * il;
 }
 
-__global__ void __launch_bounds__(256) preprocess_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+// Thread -> (set, Gaussian) for the sets of SH degree D.
+template <int D>
+__device__ inline bool locate(const void *desc, const DevSet *&S, int64_t &i) {
   const Header &h = *header(desc);
-  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= h.n_gauss) return;
-  const DevSet *sets = sets_of(desc);
+  const int32_t *ids = deg_ids_of(desc, D);
+  const uint32_t *starts = deg_starts_of(desc, D);
+  const int k = upper_index(starts, h.deg_count[D], (uint32_t)blockIdx.x);
+  S = sets_of(desc) + ids[k];
+  i = (int64_t)(blockIdx.x - starts[k]) * blockDim.x + threadIdx.x;
+  return i < S->n;
+}
+
+// Active tiles of a tile rectangle from the per-row prefix of active flags.
+__device__ inline uint32_t count_active(const uint32_t *rowsat, uint32_t pitch, uint32_t x0, uint32_t y0, uint32_t x1,
+                                        uint32_t y1) {
+  uint32_t c = 0;
+  for (uint32_t y = y0; y < y1; ++y) c += rowsat[y * pitch + x1] - rowsat[y * pitch + x0];
+  return c;
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) preprocess_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+  constexpr int K = (D + 1) * (D + 1);
+  const Header &h = *header(desc);
+  const DevSet *Sp;
+  int64_t i;
+  if (!locate<D>(desc, Sp, i)) return;
+  const DevSet &S = *Sp;
   const DevRender *rends = renders_of(desc);
-  const DevSet &S = sets[find_set(sets, h.n_sets, gid)];
-  const int64_t i = (int64_t)(gid - S.gauss_offset);
   const int64_t n = S.n;
   Raw g;
   load_raw(S, i, g);
-  const int K = (S.sh_degree + 1) * (S.sh_degree + 1);
-  float sh[48];
-#pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (j < K)
-      for (int k = 0; k < 3; ++k) sh[3 * j + k] = S.sh[(3 * j + k) * n + i];
-
   float4 *rec4 = ws_ptr<float4>(ws, h.ws.rec);
   uint32_t *dkey = ws_ptr<uint32_t>(ws, h.ws.depth_key);
   uint2 *rect = ws_ptr<uint2>(ws, h.ws.rect);
@@ -287,26 +298,24 @@ __global__ void __launch_bounds__(256) preprocess_kernel(const void *__restrict_
         const int u0 = (int)fu0, u1 = (int)fu1, w0 = (int)fv0, w1 = (int)fv1;
         if (u0 <= u1 && w0 <= w1) {
           const uint32_t x0 = u0 / tile, x1 = u1 / tile + 1, y0 = w0 / tile, y1 = w1 / tile + 1;
-          const uint32_t *st = sat + rd.sat_offset;
-          const uint32_t pitch = rd.tiles_x + 1;
-          count = st[y1 * pitch + x1] - st[y0 * pitch + x1] - st[y1 * pitch + x0] + st[y0 * pitch + x0];
+          count = count_active(sat + rd.sat_offset, rd.tiles_x + 1, x0, y0, x1, y1);
           rr = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
         }
         if (count > 0) {
           float B[16];
-          sh_basis(S.sh_degree, v.dir[0], v.dir[1], v.dir[2], B);
+          sh_basis(D, v.dir[0], v.dir[1], v.dir[2], B);
           float col[3];
+#pragma unroll
           for (int k = 0; k < 3; ++k) {
             float a = 0.5f;
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
-              if (j < K) a += B[j] * sh[3 * j + k];
+            for (int j = 0; j < K; ++j) a += B[j] * S.sh[(3 * j + k) * n + i];
             col[k] = fmaxf(a, 0.f);
           }
           rec4[r * 4 + 0] = make_float4(v.mx, v.my, v.ca, v.cb);
           rec4[r * 4 + 1] = make_float4(v.cc, g.o, col[0], col[1]);
           rec4[r * 4 + 2] = make_float4(col[2], v.n[0], v.n[1], v.n[2]);
-          rec4[r * 4 + 3] = make_float4(v.d, hx, hy, v.tz);
+          rec4[r * 4 + 3] = make_float4(v.d, hx, hy, __log2f(g.o));
         }
       }
     }
@@ -318,18 +327,19 @@ __global__ void __launch_bounds__(256) preprocess_kernel(const void *__restrict_
 
 // ------------------------------------------------------------ backward
 
+template <int D>
 __global__ void __launch_bounds__(256) backward_preprocess_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+  constexpr int K = (D + 1) * (D + 1);
   const Header &h = *header(desc);
-  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= h.n_gauss) return;
-  const DevSet *sets = sets_of(desc);
+  const DevSet *Sp;
+  int64_t i;
+  if (!locate<D>(desc, Sp, i)) return;
+  const DevSet &S = *Sp;
   const DevRender *rends = renders_of(desc);
-  const DevSet &S = sets[find_set(sets, h.n_sets, gid)];
-  const int64_t i = (int64_t)(gid - S.gauss_offset);
   const int64_t n = S.n;
   Raw g;
   load_raw(S, i, g);
-  const int K = (S.sh_degree + 1) * (S.sh_degree + 1);
+  const float4 *rec4 = ws_ptr<float4>(ws, h.ws.rec);
   const uint32_t *nact = ws_ptr<uint32_t>(ws, h.ws.nact);
   const float4 *g2 = ws_ptr<float4>(ws, h.ws.g2);
 
@@ -337,9 +347,9 @@ __global__ void __launch_bounds__(256) backward_preprocess_kernel(const void *__
   float gs[3] = {0.f, 0.f, 0.f};     // dL/ds
   float gM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // dL/dM (Gaussian rotation)
   float go = 0.f;
-  float gsh[48];
+  float gsh[3 * K];
 #pragma unroll
-  for (int j = 0; j < 48; ++j) gsh[j] = 0.f;
+  for (int j = 0; j < 3 * K; ++j) gsh[j] = 0.f;
   bool any = false;
 
   for (int vi = 0; vi < S.n_renders; ++vi) {
@@ -362,28 +372,26 @@ __global__ void __launch_bounds__(256) backward_preprocess_kernel(const void *__
     // opacity
     go += d_o;
 
-    // colour -> SH coefficients and view direction
+    // colour -> SH coefficients and view direction; the clamp at 0 is
+    // read back from the stored (clamped) colour
     {
       float B[16];
-      sh_basis(S.sh_degree, v.dir[0], v.dir[1], v.dir[2], B);
+      sh_basis(D, v.dir[0], v.dir[1], v.dir[2], B);
+      const float4 c1 = rec4[r * 4 + 1], c2 = rec4[r * 4 + 2];
+      const float dc[3] = {c1.z > 0.f ? d_col[0] : 0.f, c1.w > 0.f ? d_col[1] : 0.f,
+                           c2.x > 0.f ? d_col[2] : 0.f};
       float w[16];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) w[j] = 0.f;
-      for (int k = 0; k < 3; ++k) {
-        float a = 0.5f;
+      for (int j = 0; j < K; ++j) {
+        w[j] = 0.f;
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (j < K) a += B[j] * S.sh[(3 * j + k) * n + i];
-        const float dc = a < 0.f ? 0.f : d_col[k];
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (j < K) {
-            gsh[3 * j + k] += B[j] * dc;
-            w[j] += dc * S.sh[(3 * j + k) * n + i];
-          }
+        for (int k = 0; k < 3; ++k) {
+          gsh[3 * j + k] += B[j] * dc[k];
+          w[j] += dc[k] * S.sh[(3 * j + k) * n + i];
+        }
       }
       float gx, gy, gz;
-      sh_basis_grad(S.sh_degree, v.dir[0], v.dir[1], v.dir[2], w, gx, gy, gz);
+      sh_basis_grad(D, v.dir[0], v.dir[1], v.dir[2], w, gx, gy, gz);
       const float dd = gx * v.dir[0] + gy * v.dir[1] + gz * v.dir[2];
       const float il = 1.f / v.vlen;
       gmean[0] += (gx - dd * v.dir[0]) * il;
@@ -401,9 +409,14 @@ __global__ void __launch_bounds__(256) backward_preprocess_kernel(const void *__
       const float ga0 = v.sgn * (R[0] * d_n[0] + R[3] * d_n[1] + R[6] * d_n[2]);
       const float ga1 = v.sgn * (R[1] * d_n[0] + R[4] * d_n[1] + R[7] * d_n[2]);
       const float ga2 = v.sgn * (R[2] * d_n[0] + R[5] * d_n[1] + R[8] * d_n[2]);
-      gM[g.jstar] += ga0;
-      gM[3 + g.jstar] += ga1;
-      gM[6 + g.jstar] += ga2;
+      const int j = g.jstar;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float sel = c == j ? 1.f : 0.f;
+        gM[c] += sel * ga0;
+        gM[3 + c] += sel * ga1;
+        gM[6 + c] += sel * ga2;
+      }
     }
 
     // 2D mean = (fx tx / tz + cx, fy ty / tz + cy)
@@ -490,23 +503,28 @@ __global__ void __launch_bounds__(256) backward_preprocess_kernel(const void *__
   if (go_) go_[i] = go * g.o * (1.f - g.o);
   if (gsh_) {
 #pragma unroll
-    for (int j = 0; j < 48; ++j)
-      if (j < 3 * K) gsh_[j * n + i] = gsh[j];
+    for (int j = 0; j < 3 * K; ++j) gsh_[j * n + i] = gsh[j];
   }
 }
 
 }  // namespace
 
 void launch_preprocess(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
-  if (h.n_gauss == 0) return;
-  const unsigned blocks = (unsigned)((h.n_gauss + 255) / 256);
-  hipLaunchKernelGGL(preprocess_kernel, dim3(blocks), dim3(256), 0, s, d_desc, ws);
+  if (h.deg_blocks[0]) hipLaunchKernelGGL(preprocess_kernel<0>, dim3(h.deg_blocks[0]), dim3(256), 0, s, d_desc, ws);
+  if (h.deg_blocks[1]) hipLaunchKernelGGL(preprocess_kernel<1>, dim3(h.deg_blocks[1]), dim3(256), 0, s, d_desc, ws);
+  if (h.deg_blocks[2]) hipLaunchKernelGGL(preprocess_kernel<2>, dim3(h.deg_blocks[2]), dim3(256), 0, s, d_desc, ws);
+  if (h.deg_blocks[3]) hipLaunchKernelGGL(preprocess_kernel<3>, dim3(h.deg_blocks[3]), dim3(256), 0, s, d_desc, ws);
 }
 
 void launch_backward_preprocess(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
-  if (h.n_gauss == 0) return;
-  const unsigned blocks = (unsigned)((h.n_gauss + 255) / 256);
-  hipLaunchKernelGGL(backward_preprocess_kernel, dim3(blocks), dim3(256), 0, s, d_desc, ws);
+  if (h.deg_blocks[0])
+    hipLaunchKernelGGL(backward_preprocess_kernel<0>, dim3(h.deg_blocks[0]), dim3(256), 0, s, d_desc, ws);
+  if (h.deg_blocks[1])
+    hipLaunchKernelGGL(backward_preprocess_kernel<1>, dim3(h.deg_blocks[1]), dim3(256), 0, s, d_desc, ws);
+  if (h.deg_blocks[2])
+    hipLaunchKernelGGL(backward_preprocess_kernel<2>, dim3(h.deg_blocks[2]), dim3(256), 0, s, d_desc, ws);
+  if (h.deg_blocks[3])
+    hipLaunchKernelGGL(backward_preprocess_kernel<3>, dim3(h.deg_blocks[3]), dim3(256), 0, s, d_desc, ws);
 }
 
 }  // namespace pgsag
