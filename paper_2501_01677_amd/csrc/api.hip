@@ -58,7 +58,7 @@ int validate(const pgsag_config *cfg, const pgsag_gaussians *sets, int32_t n_set
   if (!(cfg->t_min > 0.f && cfg->t_min < 1.f)) return fail(PGSAG_INVALID_ARGUMENT, "need 0 < t_min < 1");
   if (!(cfg->z_near > 0.f) || !(cfg->fov_clamp > 0.f) || !(cfg->dilation >= 0.f))
     return fail(PGSAG_INVALID_ARGUMENT, "need z_near > 0, fov_clamp > 0, dilation >= 0");
-  if (cap < 1 || cap > 0x7fffffffull) return fail(PGSAG_INVALID_ARGUMENT, "pair_capacity must be in 1..2^31-1");
+  if (cap < 1 || cap > 0x3fffffffull) return fail(PGSAG_INVALID_ARGUMENT, "pair_capacity must be in 1..2^30-1");
   std::vector<int> per_set(n_sets, 0);
   for (int s = 0; s < n_sets; ++s) {
     if (sets[s].n < 0) return fail(PGSAG_INVALID_ARGUMENT, "set %d: n < 0", s);
@@ -83,8 +83,8 @@ int validate(const pgsag_config *cfg, const pgsag_gaussians *sets, int32_t n_set
     z.n_pixels += (uint64_t)c.width * c.height;
     z.n_records += (uint64_t)sets[rd.set].n;
   }
-  if (z.n_tiles >= 0xffffffffull || z.n_records >= 0xffffffffull || z.sat_total >= 0xffffffffull)
-    return fail(PGSAG_UNSUPPORTED, "batch too large: tiles, records and SAT entries must stay below 2^32");
+  if (z.n_tiles >= 0xffffffffull || z.n_records >= 0x3fffffffull || z.sat_total >= 0xffffffffull)
+    return fail(PGSAG_UNSUPPORTED, "batch too large: records must stay below 2^30, tiles below 2^32");
   uint32_t bits = 0;
   while (bits < 32 && (1ull << bits) < z.n_tiles) ++bits;
   z.tile_bits = bits;
@@ -99,8 +99,6 @@ Layout make_layout(const Sizes &z, uint64_t cap, int n_renders) {
     off = align_up(off + (bytes ? bytes : 4), 256);
     return o;
   };
-  const uint64_t big = z.n_records > cap ? z.n_records : cap;
-  L.status = take(S_WORDS * 4);
   L.tile_count = take(z.n_tiles * 4);
   L.sat = take(z.sat_total * 4);
   L.ranges = take(z.n_tiles * 8);
@@ -114,15 +112,24 @@ Layout make_layout(const Sizes &z, uint64_t cap, int n_renders) {
   L.pair_off = take(z.n_records * 4);
   for (int k = 0; k < 2; ++k) L.pair_key[k] = take(cap * 4);
   for (int k = 0; k < 2; ++k) L.pair_val[k] = take(cap * 4);
-  const int passes = (int)((z.tile_bits + kRadixBits - 1) / kRadixBits);
+  const int passes = tile_passes(z.tile_bits);
   L.sorted_key = L.pair_key[passes & 1];
   L.sorted_val = L.pair_val[passes & 1];
   L.pix_T = take(z.n_pixels * 4);
   L.pix_last = take(z.n_pixels * 4);
   L.g2 = take(z.n_records * kG2 * 4);
-  L.scan_sums = take(scan_scratch_words(big) * 4);
-  L.hist = take(radix_hist_words(big) * 4);
+  // contiguous zero-initialised region (status words first)
+  L.zero_begin = off;
+  const uint64_t status_at = take(S_WORDS * 4);
+  L.lb_compact = take((chunks_of(z.n_records) + 1) * 8);
+  L.lb_emit = take((chunks_of(z.n_records) + 1) * 8);
+  L.dhist = take(4 * 256 * 4);
+  L.thist = take(4 * 256 * 4);
+  L.lb_depth = take((uint64_t)kDepthPasses * (chunks_of(z.n_records) + 1) * 256 * 4);
+  L.lb_tile = take((uint64_t)(passes > 0 ? passes : 1) * (chunks_of(cap) + 1) * 256 * 4);
   L.bucket = take(64 * 4);
+  L.zero_end = off;
+  L.status = status_at;
   L.stats = take((uint64_t)n_renders * 8 * 8);
   L.end = off;
   return L;
@@ -409,7 +416,7 @@ int pgsag_forward(const void *host_desc, const void *dev_desc, void *workspace, 
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   StageTimer tm{events, s};
-  launch_fill_u32(ws_ptr<uint32_t>(workspace, h->ws.status), 0u, S_WORDS, s);
+  launch_fill_u32(ws_ptr<uint32_t>(workspace, h->ws.zero_begin), 0u, (h->ws.zero_end - h->ws.zero_begin) / 4, s);
   tm.begin(PGSAG_STAGE_TILE_MASK);
   launch_tile_mask(dev_desc, *h, workspace, s);
   tm.end(PGSAG_STAGE_TILE_MASK);
@@ -462,7 +469,7 @@ int pgsag_binning(const void *host_desc, const void *dev_desc, void *workspace, 
   int rc = check_run_args(h, dev_desc, workspace, workspace_bytes);
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  launch_fill_u32(ws_ptr<uint32_t>(workspace, h->ws.status), 0u, S_WORDS, s);
+  launch_fill_u32(ws_ptr<uint32_t>(workspace, h->ws.zero_begin), 0u, (h->ws.zero_end - h->ws.zero_begin) / 4, s);
   launch_tile_mask(dev_desc, *h, workspace, s);
   launch_recount(dev_desc, *h, workspace, s);
   launch_depth_sort(dev_desc, *h, workspace, s);

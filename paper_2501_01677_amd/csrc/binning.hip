@@ -2,13 +2,14 @@
 // and sorted), restricted to tiles that hold building-mask pixels.
 //
 // Pipeline (all counts stay on the device; grids are sized from host bounds
-// and blocks past the device count exit or contribute nothing):
+// and blocks past the device count exit):
 //   tile_mask     masked pixels per tile and, per tile row, the prefix count
 //                 of active tiles (one workgroup per tile row), so a support
 //                 rectangle's active-tile count is two loads per tile row
 //   compact       stable compaction of records with >= 1 active tile into
 //                 (depth key, record) lists
-//   radix sort    stable LSD sort of that list by the FP32 depth key
+//   radix sort    stable LSD sort of that list by the FP32 depth key; a pass
+//                 whose digit is the same for every key is skipped
 //   pair scan     exclusive scan of active-tile counts in depth order
 //   emit          (global tile, record) pairs, depth order preserved
 //   radix sort    stable LSD sort of the pairs by tile id -> every tile's list
@@ -16,6 +17,14 @@
 //   ranges        per tile [start, end) into the sorted pairs
 //   queue         tiles ordered by decreasing list length (LPT) in buckets of
 //                 log2(length), tiles without masked pixels last
+//
+// The scans and radix passes are single pass: each workgroup takes the next
+// chunk index from an atomic counter (so every chunk before it belongs to a
+// workgroup that is already running), publishes its chunk total, and looks
+// back over its predecessors' published totals until it meets an inclusive
+// prefix (decoupled look-back).  Waits only ever point backwards, to
+// workgroups that are resident and do not wait on later ones, so they end;
+// a bounded spin sets an error word instead of waiting forever.
 #include "internal.h"
 
 namespace pgsag {
@@ -159,164 +168,242 @@ __device__ inline uint64_t bounded_count(const uint32_t *n_dev, uint64_t n_bound
   return d < n_bound ? d : n_bound;
 }
 
-// Inputs of the scans.
-struct InVisible {  // 1 for records with at least one active tile
-  const uint32_t *nact;
-  __device__ uint32_t operator()(uint64_t i) const { return nact[i] > 0 ? 1u : 0u; }
-};
-struct InPairs {  // active-tile count of the i-th record in depth order
-  const uint32_t *nact, *order;
-  __device__ uint32_t operator()(uint64_t i) const { return nact[order[i]]; }
-};
-struct InArray {
-  const uint32_t *a;
-  __device__ uint32_t operator()(uint64_t i) const { return a[i]; }
-};
+// ------------------------------------------------------ look-back helpers
 
-// Outputs of the scans: called for every i < n with its exclusive prefix.
-struct OutCompact {
-  const uint32_t *key_in;
-  uint32_t *key_out, *val_out;
-  __device__ void operator()(uint64_t i, uint32_t pos, uint32_t v) const {
-    if (v) {
-      key_out[pos] = key_in[i];
-      val_out[pos] = (uint32_t)i;
-    }
-  }
-};
-struct OutArray {
-  uint32_t *a;
-  __device__ void operator()(uint64_t i, uint32_t pos, uint32_t) const { a[i] = pos; }
-};
+constexpr uint32_t kMaxSpins = 1u << 22;
+constexpr uint64_t kAgg64 = 1ull << 62, kInc64 = 2ull << 62, kVal64 = (1ull << 62) - 1;
+constexpr uint32_t kAgg32 = 1u << 30, kInc32 = 2u << 30, kVal32 = (1u << 30) - 1;
 
-template <class In>
-__global__ void __launch_bounds__(256) scan_reduce_kernel(In in, uint64_t n_bound, const uint32_t *n_dev, uint32_t *sums) {
-  const uint64_t n = bounded_count(n_dev, n_bound);
-  const uint64_t base = (uint64_t)blockIdx.x * kScanChunk;
-  uint32_t s = 0;
-  for (int k = 0; k < kScanItems; ++k) {
-    const uint64_t i = base + (uint64_t)k * kScanBlock + threadIdx.x;
-    if (i < n) s += in(i);
-  }
-  uint32_t total;
-  block_exclusive_scan(s, &total);
-  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+__device__ inline uint64_t ld64(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st64(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t ld32(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st32(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Exclusive scan of sums[0..nb) in place by one workgroup; the grand total
-// goes to total_out[0] (and, as 64 bits, to total64 if given).
-__global__ void __launch_bounds__(256) scan_top_kernel(uint32_t *sums, uint32_t nb, uint32_t *total_out,
-                                                       uint32_t *total64) {
-  uint64_t running = 0;
-  for (uint32_t c = 0; c < nb; c += kScanChunk) {
-    uint32_t v[kScanItems];
-    uint32_t ts = 0;
-    const uint32_t b = c + threadIdx.x * kScanItems;
-    for (int k = 0; k < kScanItems; ++k) {
-      v[k] = (b + k < nb) ? sums[b + k] : 0u;
-      ts += v[k];
-    }
-    uint32_t tot;
-    uint32_t off = block_exclusive_scan(ts, &tot);
-    uint32_t acc = (uint32_t)running + off;
-    for (int k = 0; k < kScanItems; ++k) {
-      if (b + k < nb) sums[b + k] = acc;
-      acc += v[k];
-    }
-    running += tot;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    if (total_out) total_out[0] = (uint32_t)running;
-    if (total64) {
-      total64[0] = (uint32_t)running;
-      total64[1] = (uint32_t)(running >> 32);
-    }
-  }
+// Chunk index of this workgroup, in launch order of the workgroups.
+__device__ inline uint32_t virtual_block(uint32_t *ctr) {
+  __shared__ uint32_t s_vid;
+  if (threadIdx.x == 0) s_vid = atomicAdd(ctr, 1u);
+  __syncthreads();
+  return s_vid;
 }
 
-template <class In, class Out>
-__global__ void __launch_bounds__(256) scan_down_kernel(In in, Out out, uint64_t n_bound, const uint32_t *n_dev,
-                                                        const uint32_t *sums) {
-  const uint64_t n = bounded_count(n_dev, n_bound);
-  const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
+__device__ inline uint64_t wave_sum64(uint64_t v) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t olo = __shfl_xor(lo, o, 64), ohi = __shfl_xor(hi, o, 64);
+    const uint32_t nlo = lo + olo;
+    hi = hi + ohi + (nlo < lo ? 1u : 0u);
+    lo = nlo;
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Exclusive prefix of chunk `vid` whose own total is `agg`; called by the
+// 64 lanes of one wave, which inspect 64 predecessors at a time.
+__device__ uint64_t lookback64(uint64_t *st, uint32_t vid, uint64_t agg, uint32_t *err) {
+  const int lane = threadIdx.x & 63;
+  if (vid == 0) {
+    if (lane == 0) st64(&st[0], kInc64 | agg);
+    return 0;
+  }
+  if (lane == 0) st64(&st[vid], kAgg64 | agg);
+  uint64_t excl = 0;
+  int64_t hi = (int64_t)vid - 1;
+  for (;;) {
+    const int64_t idx = hi - lane;
+    uint64_t w = kInc64;  // before chunk 0: an inclusive zero
+    if (idx >= 0) {
+      uint32_t spins = 0;
+      for (;;) {
+        w = ld64(&st[idx]);
+        if ((w >> 62) != 0) break;
+        if (++spins >= kMaxSpins) {
+          atomicOr(err, 1u);
+          w = kInc64;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    const uint64_t inc = __ballot((w >> 62) == 2);
+    const int first = inc ? (__ffsll((unsigned long long)inc) - 1) : 64;
+    excl += wave_sum64(lane <= first ? (w & kVal64) : 0ull);
+    if (inc) break;
+    hi -= 64;
+  }
+  if (lane == 0) st64(&st[vid], kInc64 | (excl + agg));
+  return excl;
+}
+
+// Per-digit exclusive prefix of chunk `vid` (one thread per digit).  The
+// predecessors' words are read eight at a time so that a walk over chunks
+// that have only published their own totals costs one memory round trip
+// per eight chunks.
+__device__ uint32_t lookback_digit(uint32_t *lb, uint32_t vid, int d, uint32_t agg, uint32_t *err) {
+  if (vid == 0) {
+    st32(&lb[d], kInc32 | agg);
+    return 0;
+  }
+  st32(&lb[(uint64_t)vid * kRadixBins + d], kAgg32 | agg);
+  uint32_t excl = 0;
+  int64_t j = (int64_t)vid - 1;
+  bool done = false;
+  while (!done) {
+    uint32_t w[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) w[u] = (j - u >= 0) ? ld32(&lb[(uint64_t)(j - u) * kRadixBins + d]) : kInc32;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (done) break;
+      uint32_t x = w[u], spins = 0;
+      while ((x >> 30) == 0) {  // not published yet: wait for it
+        if (++spins >= kMaxSpins) {
+          atomicOr(err, 1u);
+          x = kInc32;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        x = ld32(&lb[(uint64_t)(j - u) * kRadixBins + d]);
+      }
+      excl += x & kVal32;
+      if ((x >> 30) == 2) done = true;
+    }
+    j -= 8;
+  }
+  st32(&lb[(uint64_t)vid * kRadixBins + d], kInc32 | (excl + agg));
+  return excl;
+}
+
+// ------------------------------------------------------------ compaction
+
+// Records with at least one active tile, in record order, as (depth key,
+// record id) -> vis_key[0], vis_val[0]; the count goes to the status word.
+__global__ void __launch_bounds__(256) compact_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+  const Header &h = *header(desc);
+  uint32_t *st = status_of(ws, h);
+  const uint64_t n = h.n_records;
+  const uint32_t nb = (uint32_t)chunks_of(n);
+  const uint32_t vid = virtual_block(st + S_CTR_COMPACT);
+  if (vid >= nb) return;
+  const uint32_t *nact = ws_ptr<uint32_t>(ws, h.ws.nact);
+  const uint64_t base = (uint64_t)vid * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
+  uint32_t f[kScanItems];
   uint32_t ts = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const uint64_t i = base + k;
-    v[k] = i < n ? in(i) : 0u;
-    ts += v[k];
+    f[k] = (i < n && nact[i] > 0) ? 1u : 0u;
+    ts += f[k];
   }
   uint32_t tot;
-  uint32_t acc = block_exclusive_scan(ts, &tot) + sums[blockIdx.x];
+  const uint32_t ex = block_exclusive_scan(ts, &tot);
+  __shared__ uint64_t s_prefix;
+  if (threadIdx.x < 64) {
+    const uint64_t p = lookback64(ws_ptr<uint64_t>(ws, h.ws.lb_compact), vid, tot, st + S_ERROR);
+    if (threadIdx.x == 0) s_prefix = p;
+  }
+  __syncthreads();
+  const uint64_t prefix = s_prefix;
+  if (vid == nb - 1 && threadIdx.x == 0) st[S_NVIS] = (uint32_t)(prefix + tot);
+  const uint32_t *dkey = ws_ptr<uint32_t>(ws, h.ws.depth_key);
+  uint32_t *ko = ws_ptr<uint32_t>(ws, h.ws.vis_key[0]);
+  uint32_t *vo = ws_ptr<uint32_t>(ws, h.ws.vis_val[0]);
+  uint64_t pos = prefix + ex;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const uint64_t i = base + k;
-    if (i < n) out(i, acc, v[k]);
-    acc += v[k];
+    if (f[k]) {
+      const uint64_t i = base + k;
+      ko[pos] = dkey[i];
+      vo[pos] = (uint32_t)i;
+      ++pos;
+    }
   }
-}
-
-template <class In, class Out>
-void device_scan(In in, Out out, uint64_t n_bound, const uint32_t *n_dev, uint32_t *sums,
-                 uint32_t *total_out, uint32_t *total64, hipStream_t s) {
-  const uint32_t nb = (uint32_t)((n_bound + kScanChunk - 1) / kScanChunk);
-  if (nb == 0) {
-    // nothing to scan: still publish a zero total
-    hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanBlock), 0, s, sums, 0u, total_out, total64);
-    return;
-  }
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(scan_reduce_kernel<In>), dim3(nb), dim3(kScanBlock), 0, s, in, n_bound, n_dev, sums);
-  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanBlock), 0, s, sums, nb, total_out, total64);
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(scan_down_kernel<In, Out>), dim3(nb), dim3(kScanBlock), 0, s, in, out, n_bound,
-                     n_dev, sums);
 }
 
 // ------------------------------------------------------- radix sort
 
-__global__ void __launch_bounds__(256) radix_hist_kernel(const uint32_t *__restrict__ keys, uint64_t n_bound,
-                                                         const uint32_t *n_dev, int shift, uint32_t *hist,
-                                                         uint32_t nblocks) {
-  __shared__ uint32_t hs[kRadixBins];
-  hs[threadIdx.x] = 0;
+// Digit histograms of every pass in one read of the keys.
+__global__ void __launch_bounds__(256) digit_hist_kernel(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
+                                                         uint64_t n_bound, int passes, uint32_t *hist) {
+  __shared__ uint32_t hs[4][kRadixBins];
+  for (int p = 0; p < 4; ++p) hs[p][threadIdx.x] = 0;
   __syncthreads();
   const uint64_t n = bounded_count(n_dev, n_bound);
-  const uint64_t base = (uint64_t)blockIdx.x * kScanChunk;
-  if (base < n) {
-    for (int k = 0; k < kScanItems; ++k) {
-      const uint64_t i = base + (uint64_t)k * kScanBlock + threadIdx.x;
-      if (i < n) atomicAdd(&hs[(keys[i] >> shift) & (kRadixBins - 1)], 1u);
-    }
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint32_t k = keys[i];
+    for (int p = 0; p < passes; ++p) atomicAdd(&hs[p][(k >> (kRadixBits * p)) & (kRadixBins - 1)], 1u);
   }
   __syncthreads();
-  hist[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = hs[threadIdx.x];
+  for (int p = 0; p < passes; ++p)
+    if (hs[p][threadIdx.x]) atomicAdd(&hist[p * kRadixBins + threadIdx.x], hs[p][threadIdx.x]);
 }
 
-// Stable scatter of one 8-bit digit.  The block's 4096 keys are taken in 16
-// rounds of 256 consecutive keys; inside a round each wave ranks its keys
-// among equal digits with ballots (lane order), the four waves are ordered by
-// index, and every digit keeps a running base across rounds.
-__global__ void __launch_bounds__(256) radix_scatter_kernel(const uint32_t *__restrict__ kin,
-                                                            const uint32_t *__restrict__ vin,
-                                                            uint32_t *__restrict__ kout,
-                                                            uint32_t *__restrict__ vout, uint64_t n_bound,
-                                                            const uint32_t *n_dev, int shift,
-                                                            const uint32_t *__restrict__ hist,
-                                                            uint32_t nblocks) {
-  __shared__ uint32_t base[kRadixBins];
+// One stable LSD pass over the 8-bit digit `pass`.  With `dynamic`, passes
+// whose digit is constant over all keys are skipped (every workgroup of such
+// a pass returns at once) and the ping-pong buffer of each pass follows the
+// number of non-skipped passes before it; the buffer holding the final
+// order is published in status[cur_word].
+__global__ void __launch_bounds__(256) onesweep_kernel(uint32_t *keys0, uint32_t *vals0, uint32_t *keys1,
+                                                       uint32_t *vals1, const uint32_t *n_dev, uint64_t n_bound,
+                                                       int pass, int passes, int dynamic,
+                                                       const uint32_t *__restrict__ hist, uint32_t *lb,
+                                                       uint32_t *ctr, uint32_t *st, int cur_word) {
+  __shared__ uint32_t dbase[kRadixBins], run[kRadixBins];
   __shared__ uint32_t wcnt[4][kRadixBins];
   __shared__ uint32_t woff[4][kRadixBins];
+  __shared__ int s_skip;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t n = bounded_count(n_dev, n_bound);
-  const uint64_t blk = (uint64_t)blockIdx.x * kScanChunk;
-  if (blk >= n) return;
-  base[tid] = hist[(uint64_t)tid * nblocks + blockIdx.x];
+  const uint32_t nb = (uint32_t)chunks_of(n);
+  // which passes are real
+  int parity = pass & 1, final_parity = passes & 1, skip = 0;
+  if (dynamic) {
+    if (tid == 0) s_skip = 0;
+    __syncthreads();
+    int np = 0, before = 0;
+    for (int p = 0; p < passes; ++p) {
+      const int trivial = __syncthreads_or(n > 0 && hist[p * kRadixBins + tid] == n);
+      if (!trivial) {
+        if (p < pass) ++before;
+        ++np;
+      } else if (p == pass) {
+        skip = 1;
+      }
+    }
+    parity = before & 1;
+    final_parity = np & 1;
+  }
+  const uint32_t vid = virtual_block(ctr);
+  if (vid == 0 && tid == 0 && cur_word >= 0) st[cur_word] = (uint32_t)final_parity;
+  if (skip || vid >= nb) return;
+  const uint32_t *kin = parity ? keys1 : keys0;
+  const uint32_t *vin = parity ? vals1 : vals0;
+  uint32_t *kout = parity ? keys0 : keys1;
+  uint32_t *vout = parity ? vals0 : vals1;
+  const int shift = kRadixBits * pass;
+  {
+    uint32_t tot;
+    dbase[tid] = block_exclusive_scan(hist[pass * kRadixBins + tid], &tot);
+  }
+  run[tid] = 0;
   for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int round = 0; round < kScanItems; ++round) {
-    const uint64_t i = blk + (uint64_t)round * kScanBlock + tid;
+  const uint64_t blk = (uint64_t)vid * kScanChunk;
+  uint32_t kk[kScanItems], vv[kScanItems], rk[kScanItems];
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const uint64_t i = blk + (uint64_t)r * kScanBlock + tid;
     const bool valid = i < n;
     const uint32_t key = valid ? kin[i] : 0u;
     const uint32_t d = (key >> shift) & (kRadixBins - 1);
@@ -332,51 +419,109 @@ __global__ void __launch_bounds__(256) radix_scatter_kernel(const uint32_t *__re
     __syncthreads();
     {
       const uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
-      const uint32_t b0 = base[tid];
+      const uint32_t b0 = run[tid];
       woff[0][tid] = b0;
       woff[1][tid] = b0 + c0;
       woff[2][tid] = b0 + c0 + c1;
       woff[3][tid] = b0 + c0 + c1 + c2;
-      base[tid] = b0 + c0 + c1 + c2 + c3;
+      run[tid] = b0 + c0 + c1 + c2 + c3;
       wcnt[0][tid] = wcnt[1][tid] = wcnt[2][tid] = wcnt[3][tid] = 0;
     }
     __syncthreads();
-    if (valid) {
-      const uint32_t pos = woff[wave][d] + rank;
-      kout[pos] = key;
-      vout[pos] = vin[i];
+    kk[r] = key;
+    vv[r] = valid ? vin[i] : 0u;
+    rk[r] = valid ? woff[wave][d] + rank : 0xffffffffu;
+  }
+  // global position of each digit's run for this chunk
+  const uint32_t excl = lookback_digit(lb, vid, tid, run[tid], st + S_ERROR);
+  __syncthreads();
+  run[tid] = dbase[tid] + excl;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    if (rk[r] != 0xffffffffu) {
+      const uint32_t d = (kk[r] >> shift) & (kRadixBins - 1);
+      const uint32_t pos = run[d] + rk[r];
+      kout[pos] = kk[r];
+      vout[pos] = vv[r];
     }
   }
 }
 
-// Sorts (keys, vals) held in buffers [0] by `bits` low bits of the key;
-// returns the index of the buffer holding the result.
-int radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint64_t n_bound, const uint32_t *n_dev, int bits,
-               uint32_t *hist, uint32_t *sums, hipStream_t s) {
-  const uint32_t nb = (uint32_t)((n_bound + kScanChunk - 1) / kScanChunk);
-  int cur = 0;
-  if (nb == 0) return 0;
-  for (int shift = 0; shift < bits; shift += kRadixBits) {
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(nb), dim3(kScanBlock), 0, s, keys[cur], n_bound, n_dev, shift, hist, nb);
-    device_scan(InArray{hist}, OutArray{hist}, (uint64_t)nb * kRadixBins, nullptr, sums, nullptr, nullptr, s);
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb), dim3(kScanBlock), 0, s, keys[cur], vals[cur], keys[1 - cur],
-                       vals[1 - cur], n_bound, n_dev, shift, hist, nb);
-    cur = 1 - cur;
-  }
-  return cur;
+// Sorts (keys, vals) in buffers [0] by `bits` low key bits; with `dynamic`
+// the result buffer is published in st[cur_word], otherwise it is buffer
+// (passes & 1).
+void radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint64_t n_bound, const uint32_t *n_dev, int bits,
+                int dynamic, uint32_t *hist, uint32_t *lb, uint32_t *ctr, uint32_t *st, int cur_word,
+                hipStream_t s) {
+  const int passes = (bits + kRadixBits - 1) / kRadixBits;
+  const uint32_t nb = (uint32_t)chunks_of(n_bound);
+  if (nb == 0 || passes == 0) return;
+  unsigned hb = nb < 2048 ? nb : 2048;
+  hipLaunchKernelGGL(digit_hist_kernel, dim3(hb), dim3(256), 0, s, keys[0], n_dev, n_bound, passes, hist);
+  for (int p = 0; p < passes; ++p)
+    hipLaunchKernelGGL(onesweep_kernel, dim3(nb), dim3(256), 0, s, keys[0], vals[0], keys[1], vals[1], n_dev,
+                       n_bound, p, passes, dynamic, hist, lb + (uint64_t)p * (nb + 1) * kRadixBins, ctr + p, st,
+                       cur_word);
 }
 
 // -------------------------------------------------------------- emission
 
-__global__ void __launch_bounds__(256) emit_kernel(const void *__restrict__ desc, void *__restrict__ ws,
-                                                   const uint32_t *__restrict__ order,
-                                                   uint32_t *__restrict__ key_out,
-                                                   uint32_t *__restrict__ val_out) {
+// Exclusive scan of the active-tile counts of the depth-sorted visible
+// records -> pair_off[], and the pair total / overflow in the status word.
+__global__ void __launch_bounds__(256) pair_scan_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+  const Header &h = *header(desc);
+  uint32_t *st = status_of(ws, h);
+  const uint64_t nvis = st[S_NVIS];
+  const uint32_t nb = (uint32_t)chunks_of(nvis);
+  const uint32_t vid = virtual_block(st + S_CTR_EMIT);
+  if (vid >= nb) return;
+  const uint32_t *order = ws_ptr<uint32_t>(ws, h.ws.vis_val[st[S_DEPTH_CUR] ? 1 : 0]);
+  const uint32_t *nact = ws_ptr<uint32_t>(ws, h.ws.nact);
+  const uint64_t base = (uint64_t)vid * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
+  uint32_t cnt[kScanItems];
+  uint32_t ts = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = base + k;
+    cnt[k] = i < nvis ? nact[order[i]] : 0u;
+    ts += cnt[k];
+  }
+  uint32_t tot;
+  const uint32_t ex = block_exclusive_scan(ts, &tot);
+  __shared__ uint64_t s_prefix;
+  if (threadIdx.x < 64) {
+    const uint64_t p = lookback64(ws_ptr<uint64_t>(ws, h.ws.lb_emit), vid, tot, st + S_ERROR);
+    if (threadIdx.x == 0) s_prefix = p;
+  }
+  __syncthreads();
+  const uint64_t prefix = s_prefix;
+  const uint64_t cap = h.pair_capacity;
+  if (vid == nb - 1 && threadIdx.x == 0) {
+    const uint64_t need = prefix + tot;
+    st[S_PAIRS_LO] = (uint32_t)need;
+    st[S_PAIRS_HI] = (uint32_t)(need >> 32);
+    st[S_OVERFLOW] = need > cap ? 1u : 0u;
+    st[S_NPAIRS] = (uint32_t)(need > cap ? cap : need);
+  }
+  uint32_t *off = ws_ptr<uint32_t>(ws, h.ws.pair_off);
+  uint64_t o = prefix + ex;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = base + k;
+    if (i < nvis) off[i] = (uint32_t)(o < cap ? o : cap);
+    o += cnt[k];
+  }
+}
+
+// One thread per depth-sorted visible record: its (global tile, record)
+// pairs, active tiles of its rectangle in row-major order, up to capacity.
+__global__ void __launch_bounds__(256) emit_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
   const Header &h = *header(desc);
   const uint32_t *st = status_of(ws, h);
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= st[S_NVIS]) return;
-  const uint32_t rec = order[i];
+  const uint32_t rec = ws_ptr<uint32_t>(ws, h.ws.vis_val[st[S_DEPTH_CUR] ? 1 : 0])[i];
   uint64_t off = ws_ptr<uint32_t>(ws, h.ws.pair_off)[i];
   const uint64_t cap = h.pair_capacity;
   if (off >= cap) return;
@@ -386,6 +531,8 @@ __global__ void __launch_bounds__(256) emit_kernel(const void *__restrict__ desc
   const uint32_t x0 = rr.x & 0xffffu, y0 = rr.x >> 16;
   const uint32_t x1 = min(rr.y & 0xffffu, (uint32_t)rd.tiles_x), y1 = min(rr.y >> 16, (uint32_t)rd.tiles_y);
   const uint32_t *tc = ws_ptr<uint32_t>(ws, h.ws.tile_count);
+  uint32_t *key_out = ws_ptr<uint32_t>(ws, h.ws.pair_key[0]);
+  uint32_t *val_out = ws_ptr<uint32_t>(ws, h.ws.pair_val[0]);
   for (uint32_t ty = y0; ty < y1; ++ty) {
     const uint32_t row = rd.tile_offset + ty * rd.tiles_x;
     for (uint32_t tx = x0; tx < x1; ++tx) {
@@ -398,16 +545,6 @@ __global__ void __launch_bounds__(256) emit_kernel(const void *__restrict__ desc
       }
     }
   }
-}
-
-// Pairs actually stored (min(needed, capacity)) and the overflow flag.
-__global__ void pair_status_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
-  const Header &h = *header(desc);
-  uint32_t *st = status_of(ws, h);
-  const uint64_t need = (uint64_t)st[S_PAIRS_LO] | ((uint64_t)st[S_PAIRS_HI] << 32);
-  const uint64_t cap = h.pair_capacity;
-  st[S_OVERFLOW] = need > cap ? 1u : 0u;
-  st[S_NPAIRS] = (uint32_t)(need > cap ? cap : need);
 }
 
 // ------------------------------------------------------------ ranges
@@ -467,18 +604,6 @@ inline unsigned blocks_for(uint64_t n, unsigned bs = 256) { return (unsigned)((n
 
 }  // namespace
 
-uint64_t scan_scratch_words(uint64_t max_n) {
-  // block sums of a scan over max_n elements, or over a radix histogram
-  const uint64_t nb = (max_n + kScanChunk - 1) / kScanChunk;
-  const uint64_t hb = (nb * kRadixBins + kScanChunk - 1) / kScanChunk;
-  return (nb > hb ? nb : hb) + 64;
-}
-
-uint64_t radix_hist_words(uint64_t max_n) {
-  const uint64_t nb = (max_n + kScanChunk - 1) / kScanChunk;
-  return nb * kRadixBins + 64;
-}
-
 void launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t s) {
   if (n == 0) return;
   uint64_t blocks = (n + 255) / 256;
@@ -495,43 +620,32 @@ void launch_recount(const void *d_desc, const Header &h, void *ws, hipStream_t s
   hipLaunchKernelGGL(recount_kernel, dim3(blocks_for(h.n_records)), dim3(256), 0, s, d_desc, ws);
 }
 
-// Compaction of visible records + stable depth sort.  The sorted record
-// ids end in vis_val[cur] (cur recorded in the header by the host: the
-// number of passes is fixed, so it is known).
 void launch_depth_sort(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
+  if (h.n_records == 0) return;
   uint32_t *st = ws_ptr<uint32_t>(ws, h.ws.status);
-  uint32_t *sums = ws_ptr<uint32_t>(ws, h.ws.scan_sums);
+  hipLaunchKernelGGL(compact_kernel, dim3((unsigned)chunks_of(h.n_records)), dim3(256), 0, s, d_desc, ws);
   uint32_t *keys[2] = {ws_ptr<uint32_t>(ws, h.ws.vis_key[0]), ws_ptr<uint32_t>(ws, h.ws.vis_key[1])};
   uint32_t *vals[2] = {ws_ptr<uint32_t>(ws, h.ws.vis_val[0]), ws_ptr<uint32_t>(ws, h.ws.vis_val[1])};
-  const uint32_t *nact = ws_ptr<uint32_t>(ws, h.ws.nact);
-  device_scan(InVisible{nact}, OutCompact{ws_ptr<uint32_t>(ws, h.ws.depth_key), keys[0], vals[0]}, h.n_records,
-              nullptr, sums, st + S_NVIS, nullptr, s);
-  radix_sort(keys, vals, h.n_records, st + S_NVIS, 32, ws_ptr<uint32_t>(ws, h.ws.hist), sums, s);
+  radix_sort(keys, vals, h.n_records, st + S_NVIS, 32, 1, ws_ptr<uint32_t>(ws, h.ws.dhist),
+             ws_ptr<uint32_t>(ws, h.ws.lb_depth), st + S_CTR_DEPTH, st, S_DEPTH_CUR, s);
 }
 
 void launch_emit(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
-  uint32_t *st = ws_ptr<uint32_t>(ws, h.ws.status);
-  uint32_t *sums = ws_ptr<uint32_t>(ws, h.ws.scan_sums);
-  const uint32_t *order = ws_ptr<uint32_t>(ws, h.ws.vis_val[0]);  // 4 passes: back in buffer 0
-  const uint32_t *nact = ws_ptr<uint32_t>(ws, h.ws.nact);
-  device_scan(InPairs{nact, order}, OutArray{ws_ptr<uint32_t>(ws, h.ws.pair_off)}, h.n_records, st + S_NVIS, sums,
-              nullptr, st + S_PAIRS_LO, s);
-  hipLaunchKernelGGL(pair_status_kernel, dim3(1), dim3(1), 0, s, d_desc, ws);
   if (h.n_records == 0) return;
-  hipLaunchKernelGGL(emit_kernel, dim3(blocks_for(h.n_records)), dim3(256), 0, s, d_desc, ws, order,
-                     ws_ptr<uint32_t>(ws, h.ws.pair_key[0]), ws_ptr<uint32_t>(ws, h.ws.pair_val[0]));
+  hipLaunchKernelGGL(pair_scan_kernel, dim3((unsigned)chunks_of(h.n_records)), dim3(256), 0, s, d_desc, ws);
+  hipLaunchKernelGGL(emit_kernel, dim3(blocks_for(h.n_records)), dim3(256), 0, s, d_desc, ws);
 }
 
 void launch_tile_sort(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
   uint32_t *st = ws_ptr<uint32_t>(ws, h.ws.status);
   uint32_t *keys[2] = {ws_ptr<uint32_t>(ws, h.ws.pair_key[0]), ws_ptr<uint32_t>(ws, h.ws.pair_key[1])};
   uint32_t *vals[2] = {ws_ptr<uint32_t>(ws, h.ws.pair_val[0]), ws_ptr<uint32_t>(ws, h.ws.pair_val[1])};
-  const int cur = radix_sort(keys, vals, h.pair_capacity, st + S_NPAIRS, (int)h.tile_bits,
-                             ws_ptr<uint32_t>(ws, h.ws.hist), ws_ptr<uint32_t>(ws, h.ws.scan_sums), s);
+  radix_sort(keys, vals, h.pair_capacity, st + S_NPAIRS, (int)h.tile_bits, 0, ws_ptr<uint32_t>(ws, h.ws.thist),
+             ws_ptr<uint32_t>(ws, h.ws.lb_tile), st + S_CTR_TILE, st, -1, s);
+  const uint32_t *sorted_tiles = ws_ptr<uint32_t>(ws, h.ws.sorted_key);
   launch_fill_u32(ws_ptr<uint32_t>(ws, h.ws.ranges), 0u, 2 * h.n_tiles, s);
-  hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(h.pair_capacity)), dim3(256), 0, s, d_desc, ws, keys[cur]);
+  hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(h.pair_capacity)), dim3(256), 0, s, d_desc, ws, sorted_tiles);
   if (h.cfg.persistent) {
-    launch_fill_u32(ws_ptr<uint32_t>(ws, h.ws.bucket), 0u, 64, s);
     hipLaunchKernelGGL(queue_count_kernel, dim3(blocks_for(h.n_tiles)), dim3(256), 0, s, d_desc, ws);
     hipLaunchKernelGGL(queue_offsets_kernel, dim3(1), dim3(64), 0, s, d_desc, ws);
     hipLaunchKernelGGL(queue_fill_kernel, dim3(blocks_for(h.n_tiles)), dim3(256), 0, s, d_desc, ws);

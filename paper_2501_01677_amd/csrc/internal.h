@@ -77,7 +77,16 @@ struct Layout {
   uint64_t pair_key[2], pair_val[2];
   uint64_t sorted_key, sorted_val;  // the pair buffers holding the tile-sorted result
   uint64_t pix_T, pix_last, g2;
-  uint64_t scan_sums, hist, bucket, stats;
+  // Region [zero_begin, zero_end) is cleared at the start of every forward:
+  // status words, single-pass scan look-back words, digit histograms,
+  // radix look-back words and the queue buckets.
+  uint64_t zero_begin;
+  uint64_t lb_compact, lb_emit;  // uint64 [blocks] look-back words of the scans
+  uint64_t dhist, thist;         // uint32 [4][256] digit histograms (depth, tile)
+  uint64_t lb_depth, lb_tile;    // uint32 [passes][blocks][256] radix look-back words
+  uint64_t bucket;               // uint32 [64] queue buckets
+  uint64_t zero_end;
+  uint64_t stats;
   uint64_t end;
 };
 
@@ -85,6 +94,11 @@ struct Layout {
 enum StatusField {
   S_PAIRS_LO = 0, S_PAIRS_HI = 1, S_OVERFLOW = 2, S_NVIS = 3,
   S_QUEUE_FWD = 4, S_QUEUE_BWD = 5, S_NPAIRS = 6, S_NQUEUE = 7,
+  S_DEPTH_CUR = 8,   // which vis buffer holds the depth-sorted records
+  S_ERROR = 9,       // non-zero if a look-back wait gave up (results invalid)
+  S_CTR_COMPACT = 16, S_CTR_EMIT = 17,
+  S_CTR_DEPTH = 24,  // 4 counters, one per depth-sort pass
+  S_CTR_TILE = 28,   // 4 counters, one per tile-sort pass
   S_WORDS = 64
 };
 
@@ -170,8 +184,9 @@ void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float 
 void launch_load_stats(const void *d_desc, const Header &h, const void *ws, int r,
                        const float *pixel_weight, float *out, hipStream_t s);
 
-// Scratch sizes the binning stages need (elements of uint32).
-uint64_t scan_scratch_words(uint64_t max_n);
-uint64_t radix_hist_words(uint64_t max_n);
+// Blocks of kScanChunk elements covering n.
+__host__ __device__ inline uint64_t chunks_of(uint64_t n) { return (n + kScanChunk - 1) / kScanChunk; }
+constexpr int kDepthPasses = 4;
+inline int tile_passes(uint32_t tile_bits) { return (int)((tile_bits + kRadixBits - 1) / kRadixBits); }
 
 }  // namespace pgsag

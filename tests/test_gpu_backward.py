@@ -114,8 +114,10 @@ def test_autograd_function_matches_direct_backward():
     gg = {k: g[k].detach() for k in g}
     gg["depth"] = torch.zeros_like(out["depth"])
     b.backward([gg])
+    # two runs of the same kernels differ only by the order of float atomics
     for k, t in zip(PARAMS, got):
-        torch.testing.assert_close(t, b.grads[0][k], rtol=1e-5, atol=1e-7)
+        scale = float(b.grads[0][k].abs().max())
+        torch.testing.assert_close(t, b.grads[0][k], rtol=1e-4, atol=1e-5 * scale)
 
 
 def test_batched_gradients_equal_loop():
@@ -140,7 +142,8 @@ def test_batched_gradients_equal_loop():
         bs.backward(gl[r:r + len(s.renders)])
         r += len(s.renders)
         for name in PARAMS:
-            torch.testing.assert_close(bb.grads[k][name], bs.grads[0][name], rtol=1e-5, atol=1e-6)
+            scale = float(bs.grads[0][name].abs().max())
+            torch.testing.assert_close(bb.grads[k][name], bs.grads[0][name], rtol=1e-4, atol=1e-5 * scale)
 
 
 def test_empty_mask_gives_zero_gradients():
