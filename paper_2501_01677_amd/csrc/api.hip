@@ -38,6 +38,7 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 struct Sizes {
   uint64_t n_gauss = 0, n_records = 0, n_tiles = 0, n_pixels = 0, sat_total = 0, n_tile_rows = 0;
+  uint64_t amask_words = 0;
   uint32_t tile_bits = 0;
   int max_deg = 0;
 };
@@ -80,6 +81,7 @@ int validate(const pgsag_config *cfg, const pgsag_gaussians *sets, int32_t n_set
     z.n_tiles += tx * ty;
     z.sat_total += (tx + 1) * (ty + 1);
     z.n_tile_rows += ty;
+    z.amask_words += ty * ((tx + 31) / 32);
     z.n_pixels += (uint64_t)c.width * c.height;
     z.n_records += (uint64_t)sets[rd.set].n;
   }
@@ -101,6 +103,7 @@ Layout make_layout(const Sizes &z, uint64_t cap, int n_renders) {
   };
   L.tile_count = take(z.n_tiles * 4);
   L.sat = take(z.sat_total * 4);
+  L.amask = take(z.amask_words * 4);
   L.ranges = take(z.n_tiles * 8);
   L.queue = take(z.n_tiles * 4);
   L.rec = take(z.n_records * kRec * 4);
@@ -125,10 +128,15 @@ Layout make_layout(const Sizes &z, uint64_t cap, int n_renders) {
   L.lb_emit = take((chunks_of(z.n_records) + 1) * 8);
   L.dhist = take(4 * 256 * 4);
   L.thist = take(4 * 256 * 4);
-  L.lb_depth = take((uint64_t)kDepthPasses * (chunks_of(z.n_records) + 1) * 256 * 4);
-  L.lb_tile = take((uint64_t)(passes > 0 ? passes : 1) * (chunks_of(cap) + 1) * 256 * 4);
-  L.bucket = take(64 * 4);
+  L.qhist = take(256 * 4);
   L.zero_end = off;
+  {
+    uint64_t big = z.n_records > cap ? z.n_records : cap;
+    big = big > z.n_tiles ? big : z.n_tiles;
+    L.rtable = take((chunks_of(big) + 1) * 256 * 4);
+  }
+  for (int k = 0; k < 2; ++k) L.qkey[k] = take(z.n_tiles * 4);
+  L.qval0 = take(z.n_tiles * 4);
   L.status = status_at;
   L.stats = take((uint64_t)n_renders * 8 * 8);
   L.end = off;
@@ -329,7 +337,7 @@ int pgsag_pack(const pgsag_config *cfg, const pgsag_gaussians *sets, const pgsag
   uint32_t *tile_starts = reinterpret_cast<uint32_t *>(base + d.tile_starts_off);
   uint32_t *row_starts = reinterpret_cast<uint32_t *>(base + d.row_starts_off);
   uint64_t *rec_starts = reinterpret_cast<uint64_t *>(base + d.rec_starts_off);
-  uint64_t toff = 0, rowoff = 0, satoff = 0, recoff = 0, pixoff = 0;
+  uint64_t toff = 0, rowoff = 0, satoff = 0, recoff = 0, pixoff = 0, amoff = 0;
   const int T = cfg->tile;
   for (int r = 0; r < n_renders; ++r) {
     const pgsag_render &in = renders[r];
@@ -369,6 +377,8 @@ int pgsag_pack(const pgsag_config *cfg, const pgsag_gaussians *sets, const pgsag
     o.tile_offset = (uint32_t)toff;
     o.sat_offset = (uint32_t)satoff;
     o.row_offset = (uint32_t)rowoff;
+    o.amask_offset = (uint32_t)amoff;
+    amoff += (uint64_t)o.tiles_y * ((o.tiles_x + 31) / 32);
     tile_starts[r] = (uint32_t)toff;
     row_starts[r] = (uint32_t)rowoff;
     rec_starts[r] = recoff;

@@ -11,20 +11,24 @@
 //   radix sort    stable LSD sort of that list by the FP32 depth key; a pass
 //                 whose digit is the same for every key is skipped
 //   pair scan     exclusive scan of active-tile counts in depth order
-//   emit          (global tile, record) pairs, depth order preserved
+//   emit          (global tile, record) pairs, depth order preserved, one
+//                 wave per 64 records emitting 64 pairs at a time
 //   radix sort    stable LSD sort of the pairs by tile id -> every tile's list
 //                 is in (depth, record) order
 //   ranges        per tile [start, end) into the sorted pairs
 //   queue         tiles ordered by decreasing list length (LPT) in buckets of
-//                 log2(length), tiles without masked pixels last
+//                 log2(length), tiles without masked pixels last, by a stable
+//                 radix pass (tile order kept inside a bucket)
 //
-// The scans and radix passes are single pass: each workgroup takes the next
-// chunk index from an atomic counter (so every chunk before it belongs to a
-// workgroup that is already running), publishes its chunk total, and looks
-// back over its predecessors' published totals until it meets an inclusive
-// prefix (decoupled look-back).  Waits only ever point backwards, to
-// workgroups that are resident and do not wait on later ones, so they end;
-// a bounded spin sets an error word instead of waiting forever.
+// The compaction and pair scans are single pass: each workgroup takes the
+// next chunk index from an atomic counter (so every chunk before it belongs
+// to a workgroup that is already running), publishes its chunk total, and
+// looks back 64 predecessors at a time until it meets an inclusive prefix
+// (decoupled look-back).  Waits only ever point backwards, to workgroups
+// that are resident and do not wait on later ones, so they end; a bounded
+// spin sets an error word instead of waiting forever.  Radix passes use
+// reduce-then-scan (chunk digit counts, a per-digit scan, a scatter) with
+// digit histograms accumulated by the kernel that produced the keys.
 #include "internal.h"
 
 namespace pgsag {
@@ -122,6 +126,18 @@ __global__ void __launch_bounds__(256) tile_mask_kernel(const void *__restrict__
     }
   }
   __syncthreads();
+  {
+    const uint32_t wpr = (tx_n + 31) / 32;
+    uint32_t *am = ws_ptr<uint32_t>(ws, h.ws.amask) + rd.amask_offset + (uint64_t)ty * wpr;
+    for (uint32_t w = threadIdx.x; w < wpr; w += blockDim.x) {
+      uint32_t bits = 0;
+      for (int b = 0; b < 32; ++b) {
+        const uint32_t x = w * 32 + b;
+        if (x < (uint32_t)tx_n && cnt[x] > 0) bits |= 1u << b;
+      }
+      am[w] = bits;
+    }
+  }
   uint32_t *tc = ws_ptr<uint32_t>(ws, h.ws.tile_count) + rd.tile_offset + (uint64_t)ty * tx_n;
   uint32_t *rs = ws_ptr<uint32_t>(ws, h.ws.sat) + rd.sat_offset + (uint64_t)ty * (tx_n + 1);
   if (threadIdx.x == 0) rs[0] = 0;
@@ -244,45 +260,6 @@ __device__ uint64_t lookback64(uint64_t *st, uint32_t vid, uint64_t agg, uint32_
   return excl;
 }
 
-// Per-digit exclusive prefix of chunk `vid` (one thread per digit).  The
-// predecessors' words are read eight at a time so that a walk over chunks
-// that have only published their own totals costs one memory round trip
-// per eight chunks.
-__device__ uint32_t lookback_digit(uint32_t *lb, uint32_t vid, int d, uint32_t agg, uint32_t *err) {
-  if (vid == 0) {
-    st32(&lb[d], kInc32 | agg);
-    return 0;
-  }
-  st32(&lb[(uint64_t)vid * kRadixBins + d], kAgg32 | agg);
-  uint32_t excl = 0;
-  int64_t j = (int64_t)vid - 1;
-  bool done = false;
-  while (!done) {
-    uint32_t w[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) w[u] = (j - u >= 0) ? ld32(&lb[(uint64_t)(j - u) * kRadixBins + d]) : kInc32;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (done) break;
-      uint32_t x = w[u], spins = 0;
-      while ((x >> 30) == 0) {  // not published yet: wait for it
-        if (++spins >= kMaxSpins) {
-          atomicOr(err, 1u);
-          x = kInc32;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        x = ld32(&lb[(uint64_t)(j - u) * kRadixBins + d]);
-      }
-      excl += x & kVal32;
-      if ((x >> 30) == 2) done = true;
-    }
-    j -= 8;
-  }
-  st32(&lb[(uint64_t)vid * kRadixBins + d], kInc32 | (excl + agg));
-  return excl;
-}
-
 // ------------------------------------------------------------ compaction
 
 // Records with at least one active tile, in record order, as (depth key,
@@ -317,16 +294,27 @@ __global__ void __launch_bounds__(256) compact_kernel(const void *__restrict__ d
   const uint32_t *dkey = ws_ptr<uint32_t>(ws, h.ws.depth_key);
   uint32_t *ko = ws_ptr<uint32_t>(ws, h.ws.vis_key[0]);
   uint32_t *vo = ws_ptr<uint32_t>(ws, h.ws.vis_val[0]);
+  // digit histograms of the depth keys for the radix passes
+  __shared__ uint32_t hs[kDepthPasses][kRadixBins];
+  for (int p = 0; p < kDepthPasses; ++p) hs[p][threadIdx.x] = 0;
+  __syncthreads();
   uint64_t pos = prefix + ex;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
+    const uint64_t i = base + k;
+    const uint32_t key = f[k] ? dkey[i] : 0u;
     if (f[k]) {
-      const uint64_t i = base + k;
-      ko[pos] = dkey[i];
+      ko[pos] = key;
       vo[pos] = (uint32_t)i;
       ++pos;
     }
+    if (f[k])
+      for (int p = 0; p < kDepthPasses; ++p) atomicAdd(&hs[p][(key >> (kRadixBits * p)) & (kRadixBins - 1)], 1u);
   }
+  __syncthreads();
+  uint32_t *dh = ws_ptr<uint32_t>(ws, h.ws.dhist);
+  for (int p = 0; p < kDepthPasses; ++p)
+    if (hs[p][threadIdx.x]) atomicAdd(&dh[p * kRadixBins + threadIdx.x], hs[p][threadIdx.x]);
 }
 
 // ------------------------------------------------------- radix sort
@@ -348,62 +336,116 @@ __global__ void __launch_bounds__(256) digit_hist_kernel(const uint32_t *__restr
     if (hs[p][threadIdx.x]) atomicAdd(&hist[p * kRadixBins + threadIdx.x], hs[p][threadIdx.x]);
 }
 
-// One stable LSD pass over the 8-bit digit `pass`.  With `dynamic`, passes
-// whose digit is constant over all keys are skipped (every workgroup of such
-// a pass returns at once) and the ping-pong buffer of each pass follows the
-// number of non-skipped passes before it; the buffer holding the final
-// order is published in status[cur_word].
-__global__ void __launch_bounds__(256) onesweep_kernel(uint32_t *keys0, uint32_t *vals0, uint32_t *keys1,
-                                                       uint32_t *vals1, const uint32_t *n_dev, uint64_t n_bound,
-                                                       int pass, int passes, int dynamic,
-                                                       const uint32_t *__restrict__ hist, uint32_t *lb,
-                                                       uint32_t *ctr, uint32_t *st, int cur_word) {
-  __shared__ uint32_t dbase[kRadixBins], run[kRadixBins];
-  __shared__ uint32_t wcnt[4][kRadixBins];
-  __shared__ uint32_t woff[4][kRadixBins];
-  __shared__ int s_skip;
+// Which passes of a sort are real.  With `dynamic`, a pass whose digit is
+// the same for every key (one histogram bin holds all n keys) is skipped and
+// the ping-pong buffer of each pass follows the number of real passes before
+// it.  Evaluated identically by every workgroup of every pass kernel.
+struct PassPlan {
+  int skip, parity, final_parity;
+};
+
+__device__ inline PassPlan plan_pass(const uint32_t *hist, uint64_t n, int pass, int passes, int dynamic) {
+  PassPlan pp{0, pass & 1, passes & 1};
+  if (!dynamic) return pp;
+  int np = 0, before = 0;
+  for (int p = 0; p < passes; ++p) {
+    const int trivial = __syncthreads_or(n > 0 && hist[p * kRadixBins + threadIdx.x] == n);
+    if (!trivial) {
+      if (p < pass) ++before;
+      ++np;
+    } else if (p == pass) {
+      pp.skip = 1;
+    }
+  }
+  pp.parity = before & 1;
+  pp.final_parity = np & 1;
+  return pp;
+}
+
+// Pass part 1: digit counts of every chunk -> table[digit][chunk].
+__global__ void __launch_bounds__(256) chunk_count_kernel(const uint32_t *keys0, const uint32_t *keys1,
+                                                          const uint32_t *n_dev, uint64_t n_bound, int pass,
+                                                          int passes, int dynamic, const uint32_t *hist,
+                                                          uint32_t *table, uint32_t nb_bound) {
+  __shared__ uint32_t hs[kRadixBins];
+  const uint64_t n = bounded_count(n_dev, n_bound);
+  const PassPlan pp = plan_pass(hist, n, pass, passes, dynamic);
+  if (pp.skip) return;
+  const uint32_t c = blockIdx.x;
+  hs[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t *kin = pp.parity ? keys1 : keys0;
+  const int shift = kRadixBits * pass;
+  const uint64_t base = (uint64_t)c * kScanChunk;
+  for (int r = 0; r < kScanItems; ++r) {
+    const uint64_t i = base + (uint64_t)r * kScanBlock + threadIdx.x;
+    if (i < n) atomicAdd(&hs[(kin[i] >> shift) & (kRadixBins - 1)], 1u);
+  }
+  __syncthreads();
+  table[(uint64_t)threadIdx.x * nb_bound + c] = hs[threadIdx.x];
+}
+
+// Pass part 2: per digit, exclusive scan of its chunk counts along the
+// chunks, offset by the digit's base (exclusive scan of the digit totals):
+// table[d][c] becomes the output position of chunk c's first key of digit d.
+// One wave per digit.
+__global__ void __launch_bounds__(256) chunk_scan_kernel(const uint32_t *n_dev, uint64_t n_bound, int pass,
+                                                         int passes, int dynamic, const uint32_t *hist,
+                                                         uint32_t *table, uint32_t nb_bound) {
+  const uint64_t n = bounded_count(n_dev, n_bound);
+  const PassPlan pp = plan_pass(hist, n, pass, passes, dynamic);
+  if (pp.skip) return;
+  const uint32_t nb = (uint32_t)chunks_of(n);
+  const int lane = threadIdx.x & 63;
+  const int d = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t *h = hist + pass * kRadixBins;
+  uint32_t run = 0;
+  for (int k = lane; k < d; k += 64) run += h[k];
+  for (int o = 32; o > 0; o >>= 1) run += __shfl_xor(run, o, 64);
+  uint32_t *row = table + (uint64_t)d * nb_bound;
+  for (uint32_t c0 = 0; c0 < nb; c0 += 64) {
+    const uint32_t c = c0 + lane;
+    const uint32_t v = c < nb ? row[c] : 0u;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
+    }
+    if (c < nb) row[c] = run + inc - v;
+    run += __shfl(inc, 63, 64);
+  }
+}
+
+// Pass part 3: stable scatter.  Each wave ranks its own contiguous quarter
+// of the chunk, 64 keys at a time, against wave-private running counts (no
+// workgroup barriers); waves are ordered by index and chunks by the table.
+__global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uint32_t *vals0, uint32_t *keys1,
+                                                            uint32_t *vals1, const uint32_t *n_dev,
+                                                            uint64_t n_bound, int pass, int passes, int dynamic,
+                                                            const uint32_t *hist, const uint32_t *table,
+                                                            uint32_t nb_bound, uint32_t *st, int cur_word) {
+  __shared__ uint32_t wrun[4][kRadixBins];  // per-wave running digit counts
+  __shared__ uint32_t woff[4][kRadixBins];  // output position of each wave's first key of a digit
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t n = bounded_count(n_dev, n_bound);
-  const uint32_t nb = (uint32_t)chunks_of(n);
-  // which passes are real
-  int parity = pass & 1, final_parity = passes & 1, skip = 0;
-  if (dynamic) {
-    if (tid == 0) s_skip = 0;
-    __syncthreads();
-    int np = 0, before = 0;
-    for (int p = 0; p < passes; ++p) {
-      const int trivial = __syncthreads_or(n > 0 && hist[p * kRadixBins + tid] == n);
-      if (!trivial) {
-        if (p < pass) ++before;
-        ++np;
-      } else if (p == pass) {
-        skip = 1;
-      }
-    }
-    parity = before & 1;
-    final_parity = np & 1;
-  }
-  const uint32_t vid = virtual_block(ctr);
-  if (vid == 0 && tid == 0 && cur_word >= 0) st[cur_word] = (uint32_t)final_parity;
-  if (skip || vid >= nb) return;
-  const uint32_t *kin = parity ? keys1 : keys0;
-  const uint32_t *vin = parity ? vals1 : vals0;
-  uint32_t *kout = parity ? keys0 : keys1;
-  uint32_t *vout = parity ? vals0 : vals1;
+  const PassPlan pp = plan_pass(hist, n, pass, passes, dynamic);
+  const uint32_t c = blockIdx.x;
+  if (c == 0 && tid == 0 && cur_word >= 0) st[cur_word] = (uint32_t)pp.final_parity;
+  if (pp.skip || (uint64_t)c * kScanChunk >= n) return;
+  const uint32_t *kin = pp.parity ? keys1 : keys0;
+  const uint32_t *vin = pp.parity ? vals1 : vals0;
+  uint32_t *kout = pp.parity ? keys0 : keys1;
+  uint32_t *vout = pp.parity ? vals0 : vals1;
   const int shift = kRadixBits * pass;
-  {
-    uint32_t tot;
-    dbase[tid] = block_exclusive_scan(hist[pass * kRadixBins + tid], &tot);
-  }
-  run[tid] = 0;
-  for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
+  for (int w = 0; w < 4; ++w) wrun[w][tid] = 0;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint64_t blk = (uint64_t)vid * kScanChunk;
-  uint32_t kk[kScanItems], vv[kScanItems], rk[kScanItems];
+  const uint64_t qbase = (uint64_t)c * kScanChunk + (uint64_t)wave * (kScanChunk / 4);
+  uint32_t kk[kScanItems], rk[kScanItems];
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
-    const uint64_t i = blk + (uint64_t)r * kScanBlock + tid;
+    const uint64_t i = qbase + (uint64_t)r * 64 + lane;
     const bool valid = i < n;
     const uint32_t key = valid ? kin[i] : 0u;
     const uint32_t d = (key >> shift) & (kRadixBins - 1);
@@ -415,57 +457,78 @@ __global__ void __launch_bounds__(256) onesweep_kernel(uint32_t *keys0, uint32_t
       peers &= bit ? bb : ~bb;
     }
     const uint32_t rank = __popcll(peers & lt);
-    if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
-    __syncthreads();
-    {
-      const uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
-      const uint32_t b0 = run[tid];
-      woff[0][tid] = b0;
-      woff[1][tid] = b0 + c0;
-      woff[2][tid] = b0 + c0 + c1;
-      woff[3][tid] = b0 + c0 + c1 + c2;
-      run[tid] = b0 + c0 + c1 + c2 + c3;
-      wcnt[0][tid] = wcnt[1][tid] = wcnt[2][tid] = wcnt[3][tid] = 0;
-    }
-    __syncthreads();
+    const uint32_t base = wrun[wave][d];
+    __builtin_amdgcn_wave_barrier();
+    if (valid && rank == 0) wrun[wave][d] = base + __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
     kk[r] = key;
-    vv[r] = valid ? vin[i] : 0u;
-    rk[r] = valid ? woff[wave][d] + rank : 0xffffffffu;
+    rk[r] = valid ? base + rank : 0xffffffffu;
   }
-  // global position of each digit's run for this chunk
-  const uint32_t excl = lookback_digit(lb, vid, tid, run[tid], st + S_ERROR);
   __syncthreads();
-  run[tid] = dbase[tid] + excl;
+  // chunk-local digit-major order: the chunk's keys are first placed in LDS
+  // sorted by digit, then every digit's run is written out contiguously
+  __shared__ uint32_t cbase[kRadixBins];   // chunk-local start of each digit
+  __shared__ uint32_t gbase[kRadixBins];   // output position of each digit's run
+  __shared__ uint32_t skey[kScanChunk], sval[kScanChunk];
+  {
+    const uint32_t c0 = wrun[0][tid], c1 = wrun[1][tid], c2 = wrun[2][tid], c3 = wrun[3][tid];
+    uint32_t tot;
+    const uint32_t cb = block_exclusive_scan(c0 + c1 + c2 + c3, &tot);
+    cbase[tid] = cb;
+    gbase[tid] = table[(uint64_t)tid * nb_bound + c];
+    woff[0][tid] = cb;
+    woff[1][tid] = cb + c0;
+    woff[2][tid] = cb + c0 + c1;
+    woff[3][tid] = cb + c0 + c1 + c2;
+  }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
     if (rk[r] != 0xffffffffu) {
       const uint32_t d = (kk[r] >> shift) & (kRadixBins - 1);
-      const uint32_t pos = run[d] + rk[r];
-      kout[pos] = kk[r];
-      vout[pos] = vv[r];
+      const uint32_t lp = woff[wave][d] + rk[r];
+      skey[lp] = kk[r];
+      sval[lp] = vin[qbase + (uint64_t)r * 64 + lane];
     }
+  }
+  __syncthreads();
+  const uint64_t cstart = (uint64_t)c * kScanChunk;
+  const uint32_t cnt = (uint32_t)min((uint64_t)kScanChunk, n - cstart);
+  for (uint32_t i = tid; i < cnt; i += kScanBlock) {
+    const uint32_t key = skey[i];
+    const uint32_t d = (key >> shift) & (kRadixBins - 1);
+    const uint32_t pos = gbase[d] + (i - cbase[d]);
+    kout[pos] = key;
+    vout[pos] = sval[i];
   }
 }
 
 // Sorts (keys, vals) in buffers [0] by `bits` low key bits; with `dynamic`
 // the result buffer is published in st[cur_word], otherwise it is buffer
-// (passes & 1).
+// (passes & 1).  With `hist_ready` the digit histograms were accumulated by
+// the kernel that produced the keys.  `table` holds uint32 [256][chunks].
 void radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint64_t n_bound, const uint32_t *n_dev, int bits,
-                int dynamic, uint32_t *hist, uint32_t *lb, uint32_t *ctr, uint32_t *st, int cur_word,
+                int dynamic, int hist_ready, uint32_t *hist, uint32_t *table, uint32_t *st, int cur_word,
                 hipStream_t s) {
   const int passes = (bits + kRadixBits - 1) / kRadixBits;
   const uint32_t nb = (uint32_t)chunks_of(n_bound);
   if (nb == 0 || passes == 0) return;
-  unsigned hb = nb < 2048 ? nb : 2048;
-  hipLaunchKernelGGL(digit_hist_kernel, dim3(hb), dim3(256), 0, s, keys[0], n_dev, n_bound, passes, hist);
-  for (int p = 0; p < passes; ++p)
-    hipLaunchKernelGGL(onesweep_kernel, dim3(nb), dim3(256), 0, s, keys[0], vals[0], keys[1], vals[1], n_dev,
-                       n_bound, p, passes, dynamic, hist, lb + (uint64_t)p * (nb + 1) * kRadixBins, ctr + p, st,
-                       cur_word);
+  if (!hist_ready) {
+    unsigned hb = nb < 2048 ? nb : 2048;
+    hipLaunchKernelGGL(digit_hist_kernel, dim3(hb), dim3(256), 0, s, keys[0], n_dev, n_bound, passes, hist);
+  }
+  for (int p = 0; p < passes; ++p) {
+    hipLaunchKernelGGL(chunk_count_kernel, dim3(nb), dim3(256), 0, s, keys[0], keys[1], n_dev, n_bound, p, passes,
+                       dynamic, hist, table, nb);
+    hipLaunchKernelGGL(chunk_scan_kernel, dim3(kRadixBins / 4), dim3(256), 0, s, n_dev, n_bound, p, passes, dynamic,
+                       hist, table, nb);
+    hipLaunchKernelGGL(chunk_scatter_kernel, dim3(nb), dim3(256), 0, s, keys[0], vals[0], keys[1], vals[1], n_dev,
+                       n_bound, p, passes, dynamic, hist, table, nb, st, cur_word);
+  }
 }
 
 // -------------------------------------------------------------- emission
+
 
 // Exclusive scan of the active-tile counts of the depth-sorted visible
 // records -> pair_off[], and the pair total / overflow in the status word.
@@ -514,37 +577,105 @@ __global__ void __launch_bounds__(256) pair_scan_kernel(const void *__restrict__
   }
 }
 
-// One thread per depth-sorted visible record: its (global tile, record)
-// pairs, active tiles of its rectangle in row-major order, up to capacity.
+// Pair emission: one wave per 64 consecutive depth-sorted records.  Each
+// lane loads one record (id, pair offset, rectangle, render) once; the wave
+// then emits the records' pairs 64 at a time, every lane finding the record
+// of its pair with a six-step search over the lanes' prefix offsets
+// (shuffles) and the k-th active tile of that record's rectangle from the
+// per-row active-tile bit masks.  Work per lane is balanced whatever the
+// spread of rectangle sizes.  The digit histograms of the emitted tile ids
+// (for the tile sort) are accumulated on the way.
 __global__ void __launch_bounds__(256) emit_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
   const Header &h = *header(desc);
   const uint32_t *st = status_of(ws, h);
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= st[S_NVIS]) return;
-  const uint32_t rec = ws_ptr<uint32_t>(ws, h.ws.vis_val[st[S_DEPTH_CUR] ? 1 : 0])[i];
-  uint64_t off = ws_ptr<uint32_t>(ws, h.ws.pair_off)[i];
+  __shared__ uint32_t hs[4][kRadixBins];
+  const int passes = tile_passes(h.tile_bits);
+  for (int q = 0; q < 4; ++q) hs[q][threadIdx.x] = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const uint32_t nvis = st[S_NVIS];
   const uint64_t cap = h.pair_capacity;
-  if (off >= cap) return;
-  const int r = upper_index(rec_starts_of(desc), h.n_renders, (uint64_t)rec);
-  const DevRender &rd = renders_of(desc)[r];
-  const uint2 rr = ws_ptr<uint2>(ws, h.ws.rect)[rec];
-  const uint32_t x0 = rr.x & 0xffffu, y0 = rr.x >> 16;
-  const uint32_t x1 = min(rr.y & 0xffffu, (uint32_t)rd.tiles_x), y1 = min(rr.y >> 16, (uint32_t)rd.tiles_y);
-  const uint32_t *tc = ws_ptr<uint32_t>(ws, h.ws.tile_count);
-  uint32_t *key_out = ws_ptr<uint32_t>(ws, h.ws.pair_key[0]);
-  uint32_t *val_out = ws_ptr<uint32_t>(ws, h.ws.pair_val[0]);
-  for (uint32_t ty = y0; ty < y1; ++ty) {
-    const uint32_t row = rd.tile_offset + ty * rd.tiles_x;
-    for (uint32_t tx = x0; tx < x1; ++tx) {
-      const uint32_t gt = row + tx;
-      if (tc[gt] > 0) {
-        if (off >= cap) return;
-        key_out[off] = gt;
-        val_out[off] = rec;
-        ++off;
+  const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  const uint64_t wbase = i - lane;
+  if (wbase < nvis) {  // uniform per wave
+    const bool own = i < nvis;
+    const uint32_t rec = own ? ws_ptr<uint32_t>(ws, h.ws.vis_val[st[S_DEPTH_CUR] ? 1 : 0])[i] : 0u;
+    const uint32_t cnt = own ? ws_ptr<uint32_t>(ws, h.ws.nact)[rec] : 0u;
+    const uint64_t off0 = ws_ptr<uint32_t>(ws, h.ws.pair_off)[wbase];  // first pair of the wave
+    // inclusive prefix of the counts across the wave
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
+    }
+    const uint32_t excl = inc - cnt;
+    const uint32_t total = __shfl(inc, 63, 64);
+    // this lane's record geometry
+    uint32_t x0 = 0, y0 = 0, x1 = 0, y1 = 0, toff = 0, txn = 1, amoff = 0;
+    if (own) {
+      const int r = upper_index(rec_starts_of(desc), h.n_renders, (uint64_t)rec);
+      const DevRender &rd = renders_of(desc)[r];
+      const uint2 rr = ws_ptr<uint2>(ws, h.ws.rect)[rec];
+      x0 = rr.x & 0xffffu;
+      y0 = rr.x >> 16;
+      x1 = min(rr.y & 0xffffu, (uint32_t)rd.tiles_x);
+      y1 = min(rr.y >> 16, (uint32_t)rd.tiles_y);
+      toff = rd.tile_offset;
+      txn = rd.tiles_x;
+      amoff = rd.amask_offset;
+    }
+    const uint32_t *am_all = ws_ptr<uint32_t>(ws, h.ws.amask);
+    uint32_t *key_out = ws_ptr<uint32_t>(ws, h.ws.pair_key[0]);
+    uint32_t *val_out = ws_ptr<uint32_t>(ws, h.ws.pair_val[0]);
+    for (uint32_t j = 0; j < total; j += 64) {
+      const uint32_t t = j + lane;
+      const bool live = t < total && off0 + t < cap;
+      // owner: the last lane whose exclusive prefix is <= t
+      int owner = 0;
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1) {
+        const int cand = owner + step;
+        const uint32_t ce = __shfl(excl, cand, 64);
+        if (ce <= t) owner = cand;
+      }
+      uint32_t k = t - __shfl(excl, owner, 64);
+      const uint32_t orec = __shfl(rec, owner, 64);
+      const uint32_t ox0 = __shfl(x0, owner, 64), oy0 = __shfl(y0, owner, 64);
+      const uint32_t ox1 = __shfl(x1, owner, 64), oy1 = __shfl(y1, owner, 64);
+      const uint32_t otoff = __shfl(toff, owner, 64), otxn = __shfl(txn, owner, 64);
+      const uint32_t oam = __shfl(amoff, owner, 64);
+      if (live) {
+        const uint32_t wpr = (otxn + 31) / 32;
+        const uint32_t *am = am_all + oam;
+        uint32_t gt = otoff + oy0 * otxn + ox0;  // (the k-th active tile always exists)
+        bool found = false;
+        for (uint32_t ty = oy0; ty < oy1 && !found; ++ty) {
+          for (uint32_t w = ox0 / 32; w * 32 < ox1; ++w) {
+            uint32_t bits = am[ty * wpr + w];
+            const uint32_t lo32 = w * 32;
+            if (ox0 > lo32) bits &= ~0u << (ox0 - lo32);
+            if (ox1 < lo32 + 32) bits &= (1u << (ox1 - lo32)) - 1u;
+            const uint32_t c = __popc(bits);
+            if (k < c) {
+              for (uint32_t q = 0; q < k; ++q) bits &= bits - 1;
+              gt = otoff + ty * otxn + lo32 + (__ffs(bits) - 1);
+              found = true;
+              break;
+            }
+            k -= c;
+          }
+        }
+        key_out[off0 + t] = gt;
+        val_out[off0 + t] = orec;
+        for (int q = 0; q < passes; ++q) atomicAdd(&hs[q][(gt >> (kRadixBits * q)) & (kRadixBins - 1)], 1u);
       }
     }
   }
+  __syncthreads();
+  uint32_t *th = ws_ptr<uint32_t>(ws, h.ws.thist);
+  for (int q = 0; q < passes; ++q)
+    if (hs[q][threadIdx.x]) atomicAdd(&th[q * kRadixBins + threadIdx.x], hs[q][threadIdx.x]);
 }
 
 // ------------------------------------------------------------ ranges
@@ -569,35 +700,15 @@ __device__ inline uint32_t lpt_bucket(uint32_t masked, uint32_t len) {
   return (uint32_t)__clz(len);             // longer lists first (0 = longest)
 }
 
-__global__ void queue_count_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+// Sort key of every tile for the LPT queue (value: the tile id).
+__global__ void queue_key_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
   const Header &h = *header(desc);
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= h.n_tiles) return;
   const uint2 rg = ws_ptr<uint2>(ws, h.ws.ranges)[t];
   const uint32_t m = ws_ptr<uint32_t>(ws, h.ws.tile_count)[t];
-  atomicAdd(ws_ptr<uint32_t>(ws, h.ws.bucket) + lpt_bucket(m, rg.y - rg.x), 1u);
-}
-
-__global__ void queue_offsets_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
-  const Header &h = *header(desc);
-  if (threadIdx.x != 0) return;
-  uint32_t *b = ws_ptr<uint32_t>(ws, h.ws.bucket);
-  uint32_t acc = 0;
-  for (int k = 0; k < 34; ++k) {
-    const uint32_t c = b[k];
-    b[k] = acc;
-    acc += c;
-  }
-}
-
-__global__ void queue_fill_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
-  const Header &h = *header(desc);
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= h.n_tiles) return;
-  const uint2 rg = ws_ptr<uint2>(ws, h.ws.ranges)[t];
-  const uint32_t m = ws_ptr<uint32_t>(ws, h.ws.tile_count)[t];
-  const uint32_t pos = atomicAdd(ws_ptr<uint32_t>(ws, h.ws.bucket) + lpt_bucket(m, rg.y - rg.x), 1u);
-  ws_ptr<uint32_t>(ws, h.ws.queue)[pos] = (uint32_t)t;
+  ws_ptr<uint32_t>(ws, h.ws.qkey[0])[t] = lpt_bucket(m, rg.y - rg.x);
+  ws_ptr<uint32_t>(ws, h.ws.qval0)[t] = (uint32_t)t;
 }
 
 inline unsigned blocks_for(uint64_t n, unsigned bs = 256) { return (unsigned)((n + bs - 1) / bs); }
@@ -626,8 +737,8 @@ void launch_depth_sort(const void *d_desc, const Header &h, void *ws, hipStream_
   hipLaunchKernelGGL(compact_kernel, dim3((unsigned)chunks_of(h.n_records)), dim3(256), 0, s, d_desc, ws);
   uint32_t *keys[2] = {ws_ptr<uint32_t>(ws, h.ws.vis_key[0]), ws_ptr<uint32_t>(ws, h.ws.vis_key[1])};
   uint32_t *vals[2] = {ws_ptr<uint32_t>(ws, h.ws.vis_val[0]), ws_ptr<uint32_t>(ws, h.ws.vis_val[1])};
-  radix_sort(keys, vals, h.n_records, st + S_NVIS, 32, 1, ws_ptr<uint32_t>(ws, h.ws.dhist),
-             ws_ptr<uint32_t>(ws, h.ws.lb_depth), st + S_CTR_DEPTH, st, S_DEPTH_CUR, s);
+  radix_sort(keys, vals, h.n_records, st + S_NVIS, 32, 1, 1, ws_ptr<uint32_t>(ws, h.ws.dhist),
+             ws_ptr<uint32_t>(ws, h.ws.rtable), st, S_DEPTH_CUR, s);
 }
 
 void launch_emit(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
@@ -640,15 +751,19 @@ void launch_tile_sort(const void *d_desc, const Header &h, void *ws, hipStream_t
   uint32_t *st = ws_ptr<uint32_t>(ws, h.ws.status);
   uint32_t *keys[2] = {ws_ptr<uint32_t>(ws, h.ws.pair_key[0]), ws_ptr<uint32_t>(ws, h.ws.pair_key[1])};
   uint32_t *vals[2] = {ws_ptr<uint32_t>(ws, h.ws.pair_val[0]), ws_ptr<uint32_t>(ws, h.ws.pair_val[1])};
-  radix_sort(keys, vals, h.pair_capacity, st + S_NPAIRS, (int)h.tile_bits, 0, ws_ptr<uint32_t>(ws, h.ws.thist),
-             ws_ptr<uint32_t>(ws, h.ws.lb_tile), st + S_CTR_TILE, st, -1, s);
+  radix_sort(keys, vals, h.pair_capacity, st + S_NPAIRS, (int)h.tile_bits, 0, 1, ws_ptr<uint32_t>(ws, h.ws.thist),
+             ws_ptr<uint32_t>(ws, h.ws.rtable), st, -1, s);
   const uint32_t *sorted_tiles = ws_ptr<uint32_t>(ws, h.ws.sorted_key);
   launch_fill_u32(ws_ptr<uint32_t>(ws, h.ws.ranges), 0u, 2 * h.n_tiles, s);
   hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(h.pair_capacity)), dim3(256), 0, s, d_desc, ws, sorted_tiles);
   if (h.cfg.persistent) {
-    hipLaunchKernelGGL(queue_count_kernel, dim3(blocks_for(h.n_tiles)), dim3(256), 0, s, d_desc, ws);
-    hipLaunchKernelGGL(queue_offsets_kernel, dim3(1), dim3(64), 0, s, d_desc, ws);
-    hipLaunchKernelGGL(queue_fill_kernel, dim3(blocks_for(h.n_tiles)), dim3(256), 0, s, d_desc, ws);
+    // LPT queue: one stable radix pass on the length bucket, so tiles of a
+    // bucket keep their (render, row-major) order and stay spatially close
+    hipLaunchKernelGGL(queue_key_kernel, dim3(blocks_for(h.n_tiles)), dim3(256), 0, s, d_desc, ws);
+    uint32_t *qk[2] = {ws_ptr<uint32_t>(ws, h.ws.qkey[0]), ws_ptr<uint32_t>(ws, h.ws.qkey[1])};
+    uint32_t *qv[2] = {ws_ptr<uint32_t>(ws, h.ws.qval0), ws_ptr<uint32_t>(ws, h.ws.queue)};
+    radix_sort(qk, qv, h.n_tiles, nullptr, kRadixBits, 0, 0, ws_ptr<uint32_t>(ws, h.ws.qhist),
+               ws_ptr<uint32_t>(ws, h.ws.rtable), st, -1, s);
   }
 }
 

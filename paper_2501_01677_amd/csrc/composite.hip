@@ -50,7 +50,7 @@ struct Entry {   // one record in one wave's list (16 bytes)
 // smallest of the four edge minima.
 __device__ __forceinline__ float qmin_box(float a, float b, float c, float x0, float x1, float y0, float y1) {
   if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return 0.f;
-  const float ia = 1.f / a, ic = 1.f / c;
+  const float ia = __builtin_amdgcn_rcpf(a), ic = __builtin_amdgcn_rcpf(c);
   float best = 3.0e38f;
   {
     const float y = y0, x = fminf(fmaxf(-b * y * ia, x0), x1);
@@ -337,7 +337,10 @@ __device__ void backward_tile(const void *__restrict__ desc, const Header &h, vo
   float Tr = 1.f, Tf = 1.f;
   float gch[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float ga = 0.f;
-  float S[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  // GS = sum_c g_c S_c, S_c the blended features behind the current fragment
+  // (plus the background term): dL/dalpha only needs this dot product, so it
+  // is kept instead of the seven suffix sums.
+  float GS = 0.f;
   if (masked) {
     last = ws_ptr<int32_t>(ws, h.ws.pix_last)[rd.pixel_offset + pix];
     Tf = ws_ptr<float>(ws, h.ws.pix_T)[rd.pixel_offset + pix];
@@ -370,9 +373,7 @@ __device__ void backward_tile(const void *__restrict__ desc, const Header &h, vo
         gch[5] += k;
       }
     }
-    S[0] = h.cfg.bg[0] * Tf;
-    S[1] = h.cfg.bg[1] * Tf;
-    S[2] = h.cfg.bg[2] * Tf;
+    GS = Tf * (gch[0] * h.cfg.bg[0] + gch[1] * h.cfg.bg[1] + gch[2] * h.cfg.bg[2]);
   }
   if (threadIdx.x == 0) *smax = -1;
   __syncthreads();
@@ -393,46 +394,41 @@ __device__ void backward_tile(const void *__restrict__ desc, const Header &h, vo
       for (int t = len - 1; t >= 0; --t) {
         const Entry e = list[t];
         const int32_t idx = (int32_t)(bstart + e.k);
+        // Every lane evaluates the fragment (the wave executes it anyway when
+        // any lane contributes); lanes that do not contribute get zero weight.
+        const float ex = lane_exponent(e, sabc[e.k], g.L);
+        const bool contrib = idx <= last && ex >= l2min;
+        if (__ballot(contrib) == 0ull) continue;
+        const float raw = __builtin_amdgcn_exp2f(ex);
+        const float a = fminf(amax, raw);
+        const float4 r0 = srec[e.k][0], r1 = srec[e.k][1], r2 = srec[e.k][2], r3 = srec[e.k][3];
+        const float f[7] = {r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
+        const float iom = __builtin_amdgcn_rcpf(1.f - a);  // 1 / (1 - alpha), alpha <= 0.99
+        const float Tp = Tr * iom;
+        const float w = contrib ? a * Tp : 0.f;
+        // dL/dalpha = sum_c g_c (T f_c - S_c / (1 - alpha)) + g_alpha T_final / (1 - alpha)
+        float Gf = 0.f;
         float v[16];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) v[c] = 0.f;
-        bool contrib = false;
-        if (idx <= last) {
-          const float ex = lane_exponent(e, sabc[e.k], g.L);
-          if (ex >= l2min) {
-            contrib = true;
-            const float raw = __builtin_amdgcn_exp2f(ex);
-            const float a = fminf(amax, raw);
-            const float4 r0 = srec[e.k][0], r1 = srec[e.k][1], r2 = srec[e.k][2];
-            const float d = srec[e.k][3].x;
-            const float f[7] = {r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, d};
-            const float om = 1.f - a;
-            const float iom = 1.f / om;
-            const float Tp = Tr * iom;
-            const float w = a * Tp;
-            float dLda = ga * Tf * iom;
-#pragma unroll
-            for (int c = 0; c < 7; ++c) {
-              dLda += gch[c] * (Tp * f[c] - S[c] * iom);
-              v[6 + c] = w * gch[c];
-              S[c] = fmaf(w, f[c], S[c]);
-            }
-            Tr = Tp;
-            if (raw <= amax) {
-              // alpha = o G with G = exp(-q/2): dalpha/do = G = alpha / o,
-              // dalpha/dq = -alpha / 2
-              const float dx = fx - r0.x, dy = fy - r0.y;
-              v[G_O] = dLda * (a / r1.y);
-              const float dLdq = -0.5f * a * dLda;
-              v[G_MX] = -2.f * dLdq * (r0.z * dx + r0.w * dy);
-              v[G_MY] = -2.f * dLdq * (r0.w * dx + r1.x * dy);
-              v[G_CA] = dLdq * dx * dx;
-              v[G_CB] = 2.f * dLdq * dx * dy;
-              v[G_CC] = dLdq * dy * dy;
-            }
-          }
+        for (int c = 0; c < 7; ++c) {
+          Gf = fmaf(gch[c], f[c], Gf);
+          v[6 + c] = w * gch[c];
         }
-        if (__ballot(contrib) == 0ull) continue;
+        const float dLda = Tp * Gf + (ga * Tf - GS) * iom;
+        GS = contrib ? fmaf(w, Gf, GS) : GS;
+        Tr = contrib ? Tp : Tr;
+        // alpha = o G with G = exp(-q/2): dalpha/do = G = alpha / o,
+        // dalpha/dq = -alpha / 2 (zero on the clamped side of alpha_max)
+        const float gate = (contrib && raw <= amax) ? dLda : 0.f;
+        const float dx = fx - r0.x, dy = fy - r0.y;
+        const float dLdq = -0.5f * a * gate;
+        v[G_O] = gate * a * r3.y;
+        v[G_MX] = -2.f * dLdq * (r0.z * dx + r0.w * dy);
+        v[G_MY] = -2.f * dLdq * (r0.w * dx + r1.x * dy);
+        v[G_CA] = dLdq * dx * dx;
+        v[G_CB] = 2.f * dLdq * dx * dy;
+        v[G_CC] = dLdq * dy * dy;
+        v[13] = v[14] = v[15] = 0.f;
         const float tot = wave_reduce16(v);
         const int which = (lane >> 2) & 15;
         if ((lane & 3) == 0 && which < 13 && tot != 0.f)

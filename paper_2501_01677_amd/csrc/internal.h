@@ -27,7 +27,8 @@ enum RecField {
   R_R = 6, R_G = 7, R_B = 8,       // colour
   R_NX = 9, R_NY = 10, R_NZ = 11,  // camera-frame normal
   R_D = 12,                        // plane distance
-  R_RX = 13, R_RY = 14,            // support half-widths (pixels, with margin)
+  R_INV_O = 13,                    // 1 / opacity
+  R_RX = 14,                       // support half-width in x (pixels, with margin)
   R_LOG2O = 15                     // log2(opacity)
 };
 
@@ -68,12 +69,13 @@ struct DevRender {
   uint32_t tile_offset;    // first global tile id
   uint32_t sat_offset;     // first row-prefix entry (tiles_y rows of tiles_x+1)
   uint32_t row_offset;     // first global tile row
-  uint32_t reserved2;
+  uint32_t amask_offset;   // first word of the active-tile bit mask (rows of ceil(tiles_x/32) words)
 };
 
 struct Layout {
   uint64_t status, tile_count, sat, ranges, queue, rec, depth_key, rect, nact;
   uint64_t vis_key[2], vis_val[2], pair_off;
+  uint64_t amask;  // uint32 active-tile bit masks
   uint64_t pair_key[2], pair_val[2];
   uint64_t sorted_key, sorted_val;  // the pair buffers holding the tile-sorted result
   uint64_t pix_T, pix_last, g2;
@@ -83,9 +85,10 @@ struct Layout {
   uint64_t zero_begin;
   uint64_t lb_compact, lb_emit;  // uint64 [blocks] look-back words of the scans
   uint64_t dhist, thist;         // uint32 [4][256] digit histograms (depth, tile)
-  uint64_t lb_depth, lb_tile;    // uint32 [passes][blocks][256] radix look-back words
-  uint64_t bucket;               // uint32 [64] queue buckets
+  uint64_t qhist;                // histogram of the queue sort
   uint64_t zero_end;
+  uint64_t rtable;               // uint32 [256][chunks] radix chunk offsets
+  uint64_t qkey[2], qval0;       // queue sort buffers (the result lands in `queue`)
   uint64_t stats;
   uint64_t end;
 };
@@ -96,7 +99,7 @@ enum StatusField {
   S_QUEUE_FWD = 4, S_QUEUE_BWD = 5, S_NPAIRS = 6, S_NQUEUE = 7,
   S_DEPTH_CUR = 8,   // which vis buffer holds the depth-sorted records
   S_ERROR = 9,       // non-zero if a look-back wait gave up (results invalid)
-  S_CTR_COMPACT = 16, S_CTR_EMIT = 17,
+  S_CTR_COMPACT = 16, S_CTR_EMIT = 17, S_CTR_QUEUE = 18,
   S_CTR_DEPTH = 24,  // 4 counters, one per depth-sort pass
   S_CTR_TILE = 28,   // 4 counters, one per tile-sort pass
   S_WORDS = 64
@@ -187,6 +190,6 @@ void launch_load_stats(const void *d_desc, const Header &h, const void *ws, int 
 // Blocks of kScanChunk elements covering n.
 __host__ __device__ inline uint64_t chunks_of(uint64_t n) { return (n + kScanChunk - 1) / kScanChunk; }
 constexpr int kDepthPasses = 4;
-inline int tile_passes(uint32_t tile_bits) { return (int)((tile_bits + kRadixBits - 1) / kRadixBits); }
+__host__ __device__ inline int tile_passes(uint32_t tile_bits) { return (int)((tile_bits + kRadixBits - 1) / kRadixBits); }
 
 }  // namespace pgsag

@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(256) preprocess_kernel(const void *__restrict_
           rec4[r * 4 + 0] = make_float4(v.mx, v.my, v.ca, v.cb);
           rec4[r * 4 + 1] = make_float4(v.cc, g.o, col[0], col[1]);
           rec4[r * 4 + 2] = make_float4(col[2], v.n[0], v.n[1], v.n[2]);
-          rec4[r * 4 + 3] = make_float4(v.d, hx, hy, __log2f(g.o));
+          rec4[r * 4 + 3] = make_float4(v.d, 1.f / g.o, hx, __log2f(g.o));
         }
       }
     }
