@@ -128,9 +128,10 @@ def timed_steps(batch, steps, warmup, torch, events=True):
     return wall, stage
 
 
-def roofline(stage, batch, scene, torch):
+def roofline(stage, batch, scene, torch, tile):
     """Roofline entry of the dominant stage."""
     dom = max(stage, key=stage.get)
+    traffic = measured_traffic(dom, tile)
     t = stage[dom] * 1e-3
     blends = float(sum(int(o["n_contrib"].sum().item()) for o in batch.out))
     if dom in ("composite", "backward_composite"):
@@ -138,13 +139,39 @@ def roofline(stage, batch, scene, torch):
         work = per * blends
         ach = work / t / 1e12
         return dom, dict(bound="alu", achieved=round(ach, 3), peak=FP32_VECTOR_PEAK_TFLOPS,
-                         unit="TFLOP/s", frac=round(ach / FP32_VECTOR_PEAK_TFLOPS, 4), traffic=None,
+                         unit="TFLOP/s", frac=round(ach / FP32_VECTOR_PEAK_TFLOPS, 4), traffic=traffic,
                          kernel=dom, blends_per_launch=int(blends),
                          flops_per_blend=per)
     nbytes = algorithmic_bytes(dom, batch, scene)
     ach = nbytes / t / 1e9
     return dom, dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                     frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, kernel=dom)
+                     frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic, kernel=dom)
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hot_path_1080p_hbm_traffic.md")
+KERNEL_SOURCES = {"backward_composite": ("paper_2501_01677_amd/csrc/composite.hip",
+                                         "paper_2501_01677_amd/csrc/internal.h")}
+
+
+def measured_traffic(kernel, tile):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    counter summary (copy-calibrated), or None when that summary does not
+    cover this kernel source or launch shape."""
+    import hashlib
+    if kernel not in KERNEL_SOURCES or tile != 16 or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    sha = hashlib.sha256()
+    for p in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            sha.update(f.read())
+    nbytes = src = None
+    with open(TRAFFIC_PROFILE) as f:
+        for ln in f:
+            if "traffic_bytes_per_launch:" in ln:
+                nbytes = int(ln.split("traffic_bytes_per_launch:")[1].split()[0])
+            if ln.startswith("kernel_source_sha256:"):
+                src = ln.split()[1]
+    return nbytes if src == sha.hexdigest() else None
 
 
 def algorithmic_bytes(stage, batch, scene):
@@ -289,7 +316,7 @@ def main():
     ms_wall = min(ms_eager, ms_graph)
     masked = int(sc.renders[0].mask.sum())
     value = masked / (ms_wall * 1e-3) / 1e6
-    dom, roof = roofline(stage, batch, sc, torch)
+    dom, roof = roofline(stage, batch, sc, torch, args.tile)
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
