@@ -271,6 +271,58 @@ int pgsag_adam_step(float *params, const float *grads, float *m, float *v, int64
 int pgsag_load_stats(const void *host_desc, const void *dev_desc, const void *workspace,
                      const float *const *pixel_weight, float *out, void *stream);
 
+/* Weights of the training losses on the rendered outputs (Sec. 4.2 Eq. 8,
+ * Sec. 4.3 Eq. 11).  Defaults from pgsag_default_loss_config. */
+typedef struct pgsag_loss_config {
+  float lambda_rgb;      /* weight of the masked L1 colour term: 1 */
+  float lambda_normal;   /* weight of the boundary-aware normal term: 0.01 */
+  float boundary_weight; /* normal-term weight on mask-boundary pixels: 0.1 */
+  float lambda_load;     /* lambda of Eq. 11 (balance-load share): 0 */
+  int32_t normal_norm;   /* 1 = L1 (default), 2 = squared L2 (Eq. 8 as printed) */
+  float normal_eps;      /* rendered normals with |N| <= eps take no part: 1e-6 */
+  int32_t reserved[2];
+} pgsag_loss_config;
+
+void pgsag_default_loss_config(pgsag_loss_config *lc);
+
+/* Loss of the last forward of the batch and its gradient with respect to
+ * the rendered planes (Sec. 4.2 Eq. 8, Sec. 4.3 Eq. 11).  Per render, with
+ * M its masked pixels:
+ *   L_rgb = (1/3M) sum over masked pixels and channels |rgb - gt|
+ *   L_ban = (1/M) sum over masked pixels where both normals exist of
+ *           w * ||n_depth - N/|N|||  (L1 or squared L2), w = boundary_weight
+ *           on masked pixels with an unmasked 4-neighbour inside the image,
+ *           1 elsewhere; n_depth = normalize(dPy x dPx) from the points
+ *           depth * K^-1 p~ of masked pixels with depth > 0, central
+ *           differences along x and y with a missing neighbour replaced by
+ *           the pixel itself; it exists where the pixel has a neighbour
+ *           along each axis; N is used where |N| > normal_eps
+ *   L     = (1 - lambda_load)(lambda_rgb L_rgb + lambda_normal L_ban)
+ *           + lambda_load * Var(pair counts over tiles holding masked
+ *           pixels)   (that term is a value only: zero gradient)
+ * Reads each render's rgb, normal and depth outputs (required) and
+ * gt_rgb[r] (host array of n_renders device pointers to [3][H][W]).
+ * Writes dL/d(rgb, normal, depth) into the render's grad-output planes
+ * (required; the descriptor's const pointers are written here) and 0 into
+ * its dist and alpha grad-output planes if present, at masked pixels only:
+ * other pixels are left as they are (the backward ignores them).
+ * loss: device float [n_renders][4] = {L, L_rgb, L_ban, Var}.  Needs the
+ * workspace of the preceding pgsag_forward.  Capturable. */
+int pgsag_loss(const pgsag_loss_config *lc, const void *host_desc, const void *dev_desc, void *workspace,
+               uint64_t workspace_bytes, const float *const *gt_rgb, float *loss, void *stream);
+
+/* Per-pixel weights w_i of the gradient-constrained balance-load term
+ * (Sec. 4.3 Eq. 9), a reading of its "gradient-dependent weight":
+ * w = 0.1 + |grad Y| / mean over masked pixels of |grad Y|, Y = 0.299 R +
+ * 0.587 G + 0.114 B of the ground truth (device [3][H][W] of render
+ * `render`), gradients by central differences inside the image and
+ * one-sided differences on its border; w = 1 everywhere when that mean is
+ * 0.  weight: device float [H][W], every pixel written.  Feed it to
+ * pgsag_load_stats as pixel_weight.  Uses the workspace's loss
+ * accumulators of that render. */
+int pgsag_luminance_weights(const void *host_desc, const void *dev_desc, void *workspace, uint64_t workspace_bytes,
+                            int32_t render, const float *gt_rgb, float *weight, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,8 +32,8 @@ Readings (where the paper is silent):
   - The Eq. 9 weight w_i ("gradient-dependent", not fixed by the paper):
     0.1 + |grad Y| / mean over masked pixels of |grad Y|, Y the Rec. 601
     luminance of the ground-truth image, grad by numpy.gradient (central
-    differences inside, one-sided at the image border); 1 where the mean
-    is 0.  Parity unpinned against the paper (it prints no constants for
+    differences inside, one-sided at the image border, zero along an axis
+    one pixel long); 1 where the mean is 0.  Parity unpinned against the paper (it prints no constants for
     it); pinned only by closed forms of this reading.
 """
 from dataclasses import dataclass
@@ -54,19 +54,18 @@ class LossConfig:
     normal_eps: float = 1e-6
 
 
-def mask_boundary(mask):
+def as_mask(mask, shape):
+    """Boolean mask; None means every pixel is masked."""
+    return np.ones(shape, bool) if mask is None else np.asarray(mask).astype(bool)
+
+
+def mask_boundary(mask, shape=None):
     """MB: masked pixels with an unmasked 4-neighbour inside the image."""
-    m = np.asarray(mask).astype(bool)
-    H, W = m.shape
+    m = as_mask(mask, shape)
     out = np.zeros_like(m)
-    for v in range(H):
-        for u in range(W):
-            if not m[v, u]:
-                continue
-            for du, dv in ((1, 0), (-1, 0), (0, 1), (0, -1)):
-                x, y = u + du, v + dv
-                if 0 <= x < W and 0 <= y < H and not m[y, x]:
-                    out[v, u] = True
+    for du, dv in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+        # neighbour (u + du, v + dv) masked?  outside the image counts as masked
+        out |= m & ~_shift(m, du, dv, True)
     return out
 
 
@@ -97,7 +96,7 @@ def pixel_rays(cam):
 def depth_normals(depth, mask, cam):
     """Depth-derived normals (torch, differentiable in depth) and where they
     exist.  depth: float64 tensor [H][W]; mask: bool array [H][W]."""
-    valid = torch.from_numpy(np.asarray(mask).astype(bool)) & (depth.detach() > 0)
+    valid = torch.from_numpy(as_mask(mask, tuple(depth.shape))) & (depth.detach() > 0)
     P = depth[None] * torch.from_numpy(pixel_rays(cam))
     vxp, vxm = _shift(valid, 1, 0, False), _shift(valid, -1, 0, False)
     vyp, vym = _shift(valid, 0, 1, False), _shift(valid, 0, -1, False)
@@ -123,7 +122,8 @@ def normal_usable(normal32, eps):
 def geo_terms(rgb, normal, depth, gt, mask, cam, lc: LossConfig, normal32=None):
     """(L_rgb, L_ban) as torch scalars, differentiable in rgb, normal, depth
     (float64 tensors [3][H][W], [3][H][W], [H][W])."""
-    m = torch.from_numpy(np.asarray(mask).astype(bool))
+    shape = tuple(depth.shape)
+    m = torch.from_numpy(as_mask(mask, shape))
     M = max(int(m.sum()), 1)
     l_rgb = (torch.abs(rgb - torch.as_tensor(gt, dtype=F64)) * m[None]).sum() / (3.0 * M)
     nd, exists = depth_normals(depth, mask, cam)
@@ -133,7 +133,7 @@ def geo_terms(rgb, normal, depth, gt, mask, cam, lc: LossConfig, normal32=None):
     nr = normal / torch.sqrt(torch.where(use, sq, torch.ones_like(sq)))[None]
     diff = nd - nr
     e = torch.abs(diff).sum(0) if lc.normal_norm == 1 else (diff * diff).sum(0)
-    w = torch.where(torch.from_numpy(mask_boundary(mask)), lc.boundary_weight, 1.0).to(F64)
+    w = torch.where(torch.from_numpy(mask_boundary(mask, shape)), lc.boundary_weight, 1.0).to(F64)
     l_ban = (torch.where(use, w * e, torch.zeros_like(e))).sum() / M
     return l_rgb, l_ban
 
@@ -168,7 +168,7 @@ def sign_margins(rgb32, normal32, depth32, gt32, mask, cam, lc: LossConfig):
     nd, exists = depth_normals(dep, mask, cam)
     n = torch.tensor(np.asarray(normal32, np.float64))
     use = exists & torch.from_numpy(normal_usable(normal32, lc.normal_eps)) & torch.from_numpy(
-        np.asarray(mask).astype(bool))
+        as_mask(mask, tuple(dep.shape)))
     nr = n / torch.sqrt((n * n).sum(0)).clamp_min(1e-300)[None]
     mg = torch.abs(nd - nr).min(0).values
     return torch.where(use, mg, torch.full_like(mg, float("inf"))).numpy()
@@ -178,9 +178,11 @@ def luminance_weights(gt, mask):
     """Eq. 9 per-pixel weights w = 0.1 + |grad Y| / mean_mask |grad Y|."""
     g = np.asarray(gt, np.float64)
     Y = 0.299 * g[0] + 0.587 * g[1] + 0.114 * g[2]
-    gy, gx = np.gradient(Y)
+    # a one-pixel axis carries no gradient
+    gy = np.gradient(Y, axis=0) if Y.shape[0] > 1 else np.zeros_like(Y)
+    gx = np.gradient(Y, axis=1) if Y.shape[1] > 1 else np.zeros_like(Y)
     mag = np.sqrt(gx * gx + gy * gy)
-    m = np.asarray(mask).astype(bool)
+    m = as_mask(mask, Y.shape)
     mean = mag[m].mean() if m.any() else 0.0
     if mean > 0:
         return 0.1 + mag / mean
@@ -189,6 +191,6 @@ def luminance_weights(gt, mask):
 
 def gc_load(n_contrib, weight, mask):
     """Eq. 9: population standard deviation over masked pixels of g_i / w_i."""
-    m = np.asarray(mask).astype(bool)
+    m = as_mask(mask, np.shape(n_contrib))
     x = np.asarray(n_contrib, np.float64)[m] / np.asarray(weight, np.float64)[m]
     return float(x.std()) if x.size else 0.0

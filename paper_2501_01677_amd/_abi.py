@@ -68,13 +68,20 @@ class Layout(C.Structure):
                  "n_active", "pair_tile", "pair_record", "pixel_T", "pixel_last", "grad2d", "end")]
 
 
+class LossConfig(C.Structure):
+    _fields_ = [("lambda_rgb", C.c_float), ("lambda_normal", C.c_float), ("boundary_weight", C.c_float),
+                ("lambda_load", C.c_float), ("normal_norm", C.c_int32), ("normal_eps", C.c_float),
+                ("reserved", C.c_int32 * 2)]
+
+
 class Status(C.Structure):
     _fields_ = [("pairs_needed", C.c_uint64), ("overflow", C.c_uint32), ("n_visible", C.c_uint32)]
 
 
 SYMBOLS = ("pgsag_version", "pgsag_last_error", "pgsag_default_config", "pgsag_plan", "pgsag_pack",
            "pgsag_layout_of", "pgsag_forward", "pgsag_backward", "pgsag_binning",
-           "pgsag_read_status", "pgsag_adam_step", "pgsag_load_stats")
+           "pgsag_read_status", "pgsag_adam_step", "pgsag_load_stats", "pgsag_default_loss_config",
+           "pgsag_loss", "pgsag_luminance_weights")
 
 _lib = None
 
@@ -104,8 +111,12 @@ def lib():
     L.pgsag_read_status.argtypes = [vp, vp, C.POINTER(Status), vp]
     L.pgsag_adam_step.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp]
     L.pgsag_load_stats.argtypes = [vp, vp, vp, C.POINTER(vp), vp, vp]
+    L.pgsag_default_loss_config.argtypes = [C.POINTER(LossConfig)]
+    L.pgsag_default_loss_config.restype = None
+    L.pgsag_loss.argtypes = [C.POINTER(LossConfig), vp, vp, vp, u64, C.POINTER(vp), vp, vp]
+    L.pgsag_luminance_weights.argtypes = [vp, vp, vp, u64, i32, vp, vp, vp]
     for name in SYMBOLS:
-        if name not in ("pgsag_last_error", "pgsag_default_config"):
+        if name not in ("pgsag_last_error", "pgsag_default_config", "pgsag_default_loss_config"):
             getattr(L, name).restype = C.c_int
     if L.pgsag_version() != ABI_VERSION:
         raise RuntimeError("libpgsag.so ABI version mismatch")

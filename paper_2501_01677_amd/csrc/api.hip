@@ -139,6 +139,7 @@ Layout make_layout(const Sizes &z, uint64_t cap, int n_renders) {
   L.qval0 = take(z.n_tiles * 4);
   L.status = status_at;
   L.stats = take((uint64_t)n_renders * 8 * 8);
+  L.loss = take((uint64_t)n_renders * 8 * 8);
   L.end = off;
   return L;
 }
@@ -527,6 +528,51 @@ int pgsag_load_stats(const void *host_desc, const void *dev_desc, const void *wo
   for (int r = 0; r < h->n_renders; ++r)
     launch_load_stats(dev_desc, *h, workspace, r, pixel_weight ? pixel_weight[r] : nullptr, out, s);
   return check_hip("load stats");
+}
+
+void pgsag_default_loss_config(pgsag_loss_config *lc) {
+  if (!lc) return;
+  std::memset(lc, 0, sizeof *lc);
+  lc->lambda_rgb = 1.0f;
+  lc->lambda_normal = 0.01f;
+  lc->boundary_weight = 0.1f;
+  lc->lambda_load = 0.0f;
+  lc->normal_norm = 1;
+  lc->normal_eps = 1e-6f;
+}
+
+int pgsag_loss(const pgsag_loss_config *lc, const void *host_desc, const void *dev_desc, void *workspace,
+               uint64_t workspace_bytes, const float *const *gt_rgb, float *loss, void *stream) {
+  const Header *h = check_desc(host_desc);
+  if (!h) return PGSAG_INVALID_ARGUMENT;
+  if (!lc || !dev_desc || !workspace || !gt_rgb || !loss)
+    return fail(PGSAG_INVALID_ARGUMENT, "null config, descriptor, workspace, ground truth or loss output");
+  if (workspace_bytes < h->ws_bytes) return fail(PGSAG_WORKSPACE_TOO_SMALL, "workspace too small");
+  if (lc->normal_norm != 1 && lc->normal_norm != 2) return fail(PGSAG_INVALID_ARGUMENT, "normal_norm must be 1 or 2");
+  if (!(lc->lambda_load >= 0.f && lc->lambda_load <= 1.f)) return fail(PGSAG_INVALID_ARGUMENT, "lambda_load must be in [0, 1]");
+  if (!(lc->normal_eps >= 0.f)) return fail(PGSAG_INVALID_ARGUMENT, "normal_eps must be >= 0");
+  const DevRender *rd = renders_of(host_desc);
+  for (int r = 0; r < h->n_renders; ++r) {
+    if (!rd[r].o_rgb || !rd[r].o_normal || !rd[r].o_depth)
+      return fail(PGSAG_INVALID_ARGUMENT, "render %d: rgb, normal and depth outputs are required", r);
+    if (!rd[r].g_rgb || !rd[r].g_normal || !rd[r].g_depth)
+      return fail(PGSAG_INVALID_ARGUMENT, "render %d: rgb, normal and depth grad-output planes are required", r);
+    if (!gt_rgb[r]) return fail(PGSAG_INVALID_ARGUMENT, "render %d: null ground truth", r);
+  }
+  launch_loss(dev_desc, host_desc, workspace, *lc, gt_rgb, loss, static_cast<hipStream_t>(stream));
+  return check_hip("loss");
+}
+
+int pgsag_luminance_weights(const void *host_desc, const void *dev_desc, void *workspace, uint64_t workspace_bytes,
+                            int32_t render, const float *gt_rgb, float *weight, void *stream) {
+  const Header *h = check_desc(host_desc);
+  if (!h) return PGSAG_INVALID_ARGUMENT;
+  if (!dev_desc || !workspace || !gt_rgb || !weight)
+    return fail(PGSAG_INVALID_ARGUMENT, "null descriptor, workspace, ground truth or weight output");
+  if (workspace_bytes < h->ws_bytes) return fail(PGSAG_WORKSPACE_TOO_SMALL, "workspace too small");
+  if (render < 0 || render >= h->n_renders) return fail(PGSAG_INVALID_ARGUMENT, "render index out of range");
+  launch_luminance_weights(dev_desc, host_desc, workspace, render, gt_rgb, weight, static_cast<hipStream_t>(stream));
+  return check_hip("luminance weights");
 }
 
 }  // extern "C"

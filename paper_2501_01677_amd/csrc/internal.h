@@ -90,6 +90,7 @@ struct Layout {
   uint64_t rtable;               // uint32 [256][chunks] radix chunk offsets
   uint64_t qkey[2], qval0;       // queue sort buffers (the result lands in `queue`)
   uint64_t stats;
+  uint64_t loss;  // double [n_renders][8] loss accumulators
   uint64_t end;
 };
 
@@ -184,6 +185,10 @@ void launch_backward_composite(const void *d_desc, const Header &h, void *ws, hi
 void launch_backward_preprocess(const void *d_desc, const Header &h, void *ws, hipStream_t s);
 void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
                  float b2, float eps, int32_t step, hipStream_t s);
+void launch_loss(const void *d_desc, const void *h_desc, void *ws, const pgsag_loss_config &lc,
+                 const float *const *gt, float *out, hipStream_t s);
+void launch_luminance_weights(const void *d_desc, const void *h_desc, void *ws, int r, const float *gt,
+                              float *weight, hipStream_t s);
 void launch_load_stats(const void *d_desc, const Header &h, const void *ws, int r,
                        const float *pixel_weight, float *out, hipStream_t s);
 

@@ -50,6 +50,23 @@ class RenderConfig:
         return c
 
 
+@dataclass
+class LossConfig:
+    """Weights of the training losses (Sec. 4.2 Eq. 8, Sec. 4.3 Eq. 11)."""
+    lambda_rgb: float = 1.0
+    lambda_normal: float = 0.01
+    boundary_weight: float = 0.1
+    lambda_load: float = 0.0
+    normal_norm: int = 1
+    normal_eps: float = 1e-6
+
+    def to_c(self) -> A.LossConfig:
+        c = A.LossConfig()
+        for k in ("lambda_rgb", "lambda_normal", "boundary_weight", "lambda_load", "normal_norm", "normal_eps"):
+            setattr(c, k, getattr(self, k))
+        return c
+
+
 class CapacityError(RuntimeError):
     pass
 
@@ -90,7 +107,7 @@ class Batch:
 
     def __init__(self, sets, renders, cfg: RenderConfig | None = None, pair_capacity=None,
                  want_grads=True, outputs=tuple(n for n, _ in OUTPUTS), grad_outputs=GRAD_OUTPUTS,
-                 device="cuda"):
+                 device="cuda", grads=None):
         self.lib = A.lib()
         self.cfg = cfg or RenderConfig()
         self.sets = sets
@@ -117,8 +134,11 @@ class Batch:
             self.gout.append(g)
         self.grads = []
         if want_grads:
-            for s in sets:
-                self.grads.append({k: torch.zeros_like(s[k]) for k in PARAMS})
+            if grads is not None:       # caller-owned gradient tensors (e.g. views of one flat buffer)
+                self.grads = list(grads)
+            else:
+                for s in sets:
+                    self.grads.append({k: torch.zeros_like(s[k]) for k in PARAMS})
         n_rec = sum(int(sets[rd["set"]]["means"].shape[1]) for rd in renders)
         if pair_capacity is None:
             pair_capacity = max(1 << 16, 8 * n_rec)
@@ -241,6 +261,32 @@ class Batch:
             warr = (C.c_void_p * len(self.renders))(*[None if w is None else w.data_ptr() for w in weights])
         A.check(self.lib.pgsag_load_stats(self.host_desc, _p(self.dev_desc), _p(self.workspace), warr,
                                           _p(out), _stream(stream)), "pgsag_load_stats")
+        return out
+
+    def loss(self, gt, lc: LossConfig | None = None, out=None, stream=None):
+        """Loss of the last forward against ground-truth images gt[r]
+        (float32 [3,H,W]); writes dL/d(rgb, normal, depth) into the batch's
+        gradient planes.  Returns device float [n_renders, 4] = (total,
+        L_rgb, L_ban, tile-load variance)."""
+        lc = lc or LossConfig()
+        if out is None:
+            out = torch.empty((len(self.renders), 4), dtype=torch.float32, device=self.device)
+        for t in gt:
+            assert t.dtype == torch.float32 and t.is_contiguous()
+        arr = (C.c_void_p * len(self.renders))(*[t.data_ptr() for t in gt])
+        A.check(self.lib.pgsag_loss(C.byref(lc.to_c()), self.host_desc, _p(self.dev_desc), _p(self.workspace),
+                                    int(self.info.workspace_bytes), arr, _p(out), _stream(stream)), "pgsag_loss")
+        return out
+
+    def luminance_weights(self, render, gt, out=None, stream=None):
+        """Eq. 9 per-pixel weights of render `render` from its ground truth."""
+        cam = self.renders[render]["camera"]
+        if out is None:
+            out = torch.empty((int(cam.height), int(cam.width)), dtype=torch.float32, device=self.device)
+        assert gt.dtype == torch.float32 and gt.is_contiguous()
+        A.check(self.lib.pgsag_luminance_weights(self.host_desc, _p(self.dev_desc), _p(self.workspace),
+                                                 int(self.info.workspace_bytes), render, _p(gt), _p(out),
+                                                 _stream(stream)), "pgsag_luminance_weights")
         return out
 
     # ------------------------------------------------------ workspace views

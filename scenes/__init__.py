@@ -500,3 +500,36 @@ def crop_windows(seed, render: Render, count=4, size=64):
             if len(out) == count:
                 return out
     return out
+
+
+def loss_inputs(seed, render: Render):
+    """Seeded stand-ins for the rendered planes and a ground-truth image of
+    one render (float32): a smooth positive depth surface on masked pixels
+    with ~2% holes (depth 0), normals N(0, 1) per component with ~1% exact
+    zeros, colours U[0, 1] and a ground truth equal to the colour on ~1% of
+    the pixels.  Unmasked pixels hold 0 in rgb, normal and depth."""
+    cam = render.camera
+    H, W = cam.height, cam.width
+    rng = np.random.default_rng(seed)
+    m = np.ones((H, W), bool) if render.mask is None else np.asarray(render.mask).astype(bool)
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    surf = 4.0 + 0.6 * np.sin(xx / 23.0) * np.cos(yy / 17.0) + 0.002 * xx + rng.uniform(-0.01, 0.01, (H, W))
+    depth = np.where(m & (rng.uniform(size=(H, W)) > 0.02), surf, 0.0)
+    normal = rng.normal(size=(3, H, W))
+    normal[:, rng.uniform(size=(H, W)) < 0.01] = 0.0
+    normal *= m[None]
+    rgb = rng.uniform(size=(3, H, W)) * m[None]
+    gt = rng.uniform(size=(3, H, W))
+    same = rng.uniform(size=(H, W)) < 0.01
+    gt[:, same] = rgb[:, same]
+    return dict(rgb=_f32(rgb), normal=_f32(normal), depth=_f32(depth), gt=_f32(gt))
+
+
+def load_inputs(seed, render: Render, max_count=60):
+    """Seeded stand-ins for a render's per-pixel blended counts (int32) and
+    Eq. 9 pixel weights (float32, in [0.1, 3])."""
+    cam = render.camera
+    rng = np.random.default_rng(seed)
+    g = rng.integers(0, max_count, (cam.height, cam.width)).astype(np.int32)
+    w = _f32(rng.uniform(0.1, 3.0, (cam.height, cam.width)))
+    return g, w
