@@ -262,6 +262,14 @@ int pgsag_read_status(const void *host_desc, const void *workspace, pgsag_status
 int pgsag_adam_step(float *params, const float *grads, float *m, float *v, int64_t n,
                     float lr, float b1, float b2, float eps, int32_t step, void *stream);
 
+/* The same update with the step count kept on the device, for a training
+ * step captured once in a HIP graph and replayed: state is device int32[4]
+ * owned by the caller, state[0] = steps taken so far (0 before the first;
+ * incremented by this call before the update), state[1..2] receive the
+ * step's bias corrections 1/(1 - b1^t), 1/(1 - b2^t) as floats. */
+int pgsag_adam_step_device(float *params, const float *grads, float *m, float *v, int64_t n, float lr, float b1,
+                           float b2, float eps, int32_t *state, void *stream);
+
 /* Balance-load statistics of the last forward (Sec. 4.3, Eq. 9): per
  * render, over tiles with at least one masked pixel, the mean and the
  * population variance of the per-tile pair counts, and over masked pixels

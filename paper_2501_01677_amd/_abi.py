@@ -81,7 +81,7 @@ class Status(C.Structure):
 SYMBOLS = ("pgsag_version", "pgsag_last_error", "pgsag_default_config", "pgsag_plan", "pgsag_pack",
            "pgsag_layout_of", "pgsag_forward", "pgsag_backward", "pgsag_binning",
            "pgsag_read_status", "pgsag_adam_step", "pgsag_load_stats", "pgsag_default_loss_config",
-           "pgsag_loss", "pgsag_luminance_weights")
+           "pgsag_loss", "pgsag_luminance_weights", "pgsag_adam_step_device")
 
 _lib = None
 
@@ -110,6 +110,7 @@ def lib():
     L.pgsag_binning.argtypes = [vp, vp, vp, C.c_size_t, vp]
     L.pgsag_read_status.argtypes = [vp, vp, C.POINTER(Status), vp]
     L.pgsag_adam_step.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp]
+    L.pgsag_adam_step_device.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, vp, vp]
     L.pgsag_load_stats.argtypes = [vp, vp, vp, C.POINTER(vp), vp, vp]
     L.pgsag_default_loss_config.argtypes = [C.POINTER(LossConfig)]
     L.pgsag_default_loss_config.restype = None

@@ -512,8 +512,20 @@ int pgsag_adam_step(float *params, const float *grads, float *m, float *v, int64
   if (!(b1 >= 0.f && b1 < 1.f && b2 >= 0.f && b2 < 1.f)) return fail(PGSAG_INVALID_ARGUMENT, "betas must be in [0, 1)");
   if (((uintptr_t)params | (uintptr_t)grads | (uintptr_t)m | (uintptr_t)v) & 3u)
     return fail(PGSAG_INVALID_ARGUMENT, "pointers must be 4-byte aligned");
-  launch_adam(params, grads, m, v, n, lr, b1, b2, eps, step, static_cast<hipStream_t>(stream));
+  launch_adam(params, grads, m, v, n, lr, b1, b2, eps, step, nullptr, static_cast<hipStream_t>(stream));
   return check_hip("adam");
+}
+
+int pgsag_adam_step_device(float *params, const float *grads, float *m, float *v, int64_t n, float lr, float b1,
+                           float b2, float eps, int32_t *state, void *stream) {
+  if (n < 0) return fail(PGSAG_INVALID_ARGUMENT, "n < 0");
+  if (!state) return fail(PGSAG_INVALID_ARGUMENT, "null step state");
+  if (n > 0 && (!params || !grads || !m || !v)) return fail(PGSAG_INVALID_ARGUMENT, "null pointer");
+  if (!(b1 >= 0.f && b1 < 1.f && b2 >= 0.f && b2 < 1.f)) return fail(PGSAG_INVALID_ARGUMENT, "betas must be in [0, 1)");
+  if (((uintptr_t)params | (uintptr_t)grads | (uintptr_t)m | (uintptr_t)v | (uintptr_t)state) & 3u)
+    return fail(PGSAG_INVALID_ARGUMENT, "pointers must be 4-byte aligned");
+  launch_adam(params, grads, m, v, n, lr, b1, b2, eps, 0, state, static_cast<hipStream_t>(stream));
+  return check_hip("adam (device step)");
 }
 
 int pgsag_load_stats(const void *host_desc, const void *dev_desc, const void *workspace,

@@ -183,8 +183,8 @@ void launch_tile_sort(const void *d_desc, const Header &h, void *ws, hipStream_t
 void launch_composite(const void *d_desc, const Header &h, void *ws, hipStream_t s);
 void launch_backward_composite(const void *d_desc, const Header &h, void *ws, hipStream_t s);
 void launch_backward_preprocess(const void *d_desc, const Header &h, void *ws, hipStream_t s);
-void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
-                 float b2, float eps, int32_t step, hipStream_t s);
+void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
+                 int32_t step, int32_t *state, hipStream_t s);
 void launch_loss(const void *d_desc, const void *h_desc, void *ws, const pgsag_loss_config &lc,
                  const float *const *gt, float *out, hipStream_t s);
 void launch_luminance_weights(const void *d_desc, const void *h_desc, void *ws, int r, const float *gt,

@@ -20,9 +20,20 @@ __device__ __forceinline__ void adam1(float &p, float g, float &m, float &v, flo
   p -= lr * (m * c1) / (sqrtf(v * c2) + eps);
 }
 
+// Bias corrections 1/(1 - b^t) either as arguments or, for the device-step
+// form, from the two floats the coefficient kernel wrote.
+__device__ __forceinline__ void corrections(const float *coef, float &c1, float &c2) {
+  if (coef) {
+    c1 = coef[0];
+    c2 = coef[1];
+  }
+}
+
 __global__ void __launch_bounds__(256) adam_vec_kernel(float4 *__restrict__ p, const float4 *__restrict__ g,
                                                        float4 *__restrict__ m, float4 *__restrict__ v, int64_t n4,
-                                                       float lr, float b1, float b2, float eps, float c1, float c2) {
+                                                       float lr, float b1, float b2, float eps, float c1, float c2,
+                                                       const float *__restrict__ coef) {
+  corrections(coef, c1, c2);
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; i < n4; i += stride) {
@@ -40,7 +51,8 @@ __global__ void __launch_bounds__(256) adam_vec_kernel(float4 *__restrict__ p, c
 __global__ void __launch_bounds__(256) adam_kernel(float *__restrict__ p, const float *__restrict__ g,
                                                    float *__restrict__ m, float *__restrict__ v, int64_t lo,
                                                    int64_t n, float lr, float b1, float b2, float eps, float c1,
-                                                   float c2) {
+                                                   float c2, const float *__restrict__ coef) {
+  corrections(coef, c1, c2);
   int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) {
@@ -50,6 +62,17 @@ __global__ void __launch_bounds__(256) adam_kernel(float *__restrict__ p, const 
     m[i] = mm;
     v[i] = vv;
   }
+}
+
+// Device step counter: state[0] += 1, then the bias corrections of that
+// step into state[1], state[2] (as floats), computed in double.
+__global__ void adam_coef_kernel(int32_t *__restrict__ state, float b1, float b2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int32_t t = state[0] + 1;
+  state[0] = t;
+  float *coef = reinterpret_cast<float *>(state + 1);
+  coef[0] = (float)(1.0 / (1.0 - pow((double)b1, (double)t)));
+  coef[1] = (float)(1.0 / (1.0 - pow((double)b2, (double)t)));
 }
 
 // Sums over one render: [0] active tiles, [1] sum of counts, [2] sum of
@@ -111,10 +134,15 @@ __global__ void zero_f64_kernel(double *p, int n) {
 }  // namespace
 
 void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
-                 int32_t step, hipStream_t s) {
+                 int32_t step, int32_t *state, hipStream_t s) {
+  const float *coef = nullptr;
+  if (state) {
+    hipLaunchKernelGGL(adam_coef_kernel, dim3(1), dim3(64), 0, s, state, b1, b2);
+    coef = reinterpret_cast<const float *>(state + 1);
+  }
   if (n <= 0) return;
-  const double c1 = 1.0 / (1.0 - pow((double)b1, (double)step));
-  const double c2 = 1.0 / (1.0 - pow((double)b2, (double)step));
+  const double c1 = state ? 1.0 : 1.0 / (1.0 - pow((double)b1, (double)step));
+  const double c2 = state ? 1.0 : 1.0 / (1.0 - pow((double)b2, (double)step));
   const bool aligned = (((uintptr_t)p | (uintptr_t)g | (uintptr_t)m | (uintptr_t)v) & 15u) == 0;
   int64_t done = 0;
   if (aligned && n >= 4) {
@@ -122,14 +150,14 @@ void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float 
     int64_t blocks = (n4 + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(adam_vec_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (float4 *)p, (const float4 *)g,
-                       (float4 *)m, (float4 *)v, n4, lr, b1, b2, eps, (float)c1, (float)c2);
+                       (float4 *)m, (float4 *)v, n4, lr, b1, b2, eps, (float)c1, (float)c2, coef);
     done = n4 * 4;
   }
   if (done < n) {
     int64_t blocks = (n - done + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(adam_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, g, m, v, done, n, lr, b1, b2, eps,
-                       (float)c1, (float)c2);
+                       (float)c1, (float)c2, coef);
   }
 }
 

@@ -361,3 +361,94 @@ class MaskedRasterizer:
             d["n_contrib"] = outs[i * per + len(GRAD_OUTPUTS)]
             res.append(d)
         return res
+
+
+def adam_step_device(params, grads, m, v, lr, state, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    """Fused Adam update with the step count in ``state`` (device int32 [4],
+    state[0] = steps taken, incremented by this call), so a captured graph
+    replays with the right bias corrections."""
+    L = A.lib()
+    for t in (params, grads, m, v):
+        assert t.dtype == torch.float32 and t.is_contiguous() and t.numel() == params.numel()
+    assert state.dtype == torch.int32 and state.numel() >= 4
+    A.check(L.pgsag_adam_step_device(_p(params), _p(grads), _p(m), _p(v), params.numel(), lr, b1, b2, eps,
+                                     _p(state), _stream(stream)), "pgsag_adam_step_device")
+
+
+def _param_sizes(n, sh_degree):
+    K = (sh_degree + 1) ** 2
+    return (("means", (3, n)), ("log_scales", (3, n)), ("quats", (4, n)), ("opacity_logits", (n,)),
+            ("sh", (K, 3, n)))
+
+
+class Trainer:
+    """One optimisation step over a batch of renders: forward, the loss of
+    Sec. 4.2-4.3 against ground-truth images, backward, and one fused Adam
+    update over every raw parameter of every set.  Parameters, gradients and
+    Adam moments live in four flat device buffers (one Adam launch); the
+    per-set tensors are views into them.  ``step`` is capturable: ``capture``
+    records it once into a HIP graph and ``replay`` runs it."""
+
+    def __init__(self, sets, renders, gt, cfg: RenderConfig | None = None, lc: LossConfig | None = None,
+                 lr=1e-3, betas=(0.9, 0.999), eps=1e-8, pair_capacity=None, device="cuda"):
+        total = 0
+        for s in sets:
+            for _, shp in _param_sizes(int(s["means"].shape[1]), int(s["sh_degree"])):
+                total += int(np.prod(shp))
+        self.P = torch.empty(total, dtype=torch.float32, device=device)
+        self.G = torch.zeros(total, dtype=torch.float32, device=device)
+        self.m = torch.zeros_like(self.P)
+        self.v = torch.zeros_like(self.P)
+        self.state = torch.zeros(4, dtype=torch.int32, device=device)
+        self.params, grads = [], []
+        off = 0
+        for s in sets:
+            n = int(s["means"].shape[1])
+            pv, gv = {"sh_degree": int(s["sh_degree"])}, {}
+            for k, shp in _param_sizes(n, int(s["sh_degree"])):
+                c = int(np.prod(shp))
+                pv[k] = self.P[off:off + c].view(shp)
+                pv[k].copy_(s[k].reshape(shp))
+                gv[k] = self.G[off:off + c].view(shp)
+                off += c
+            self.params.append(pv)
+            grads.append(gv)
+        self.batch = Batch(self.params, renders, cfg, pair_capacity=pair_capacity, device=device, grads=grads)
+        self.gt = list(gt)
+        self.lc = lc or LossConfig()
+        self.lr, self.betas, self.eps = lr, betas, eps
+        self.loss_out = torch.zeros((len(renders), 4), dtype=torch.float32, device=device)
+        self.graph = None
+
+    def fit(self, slack=1.25):
+        """Runs one forward with the overflow check and sizes the pair
+        capacity to slack x what it needed (no parameter update)."""
+        self.batch.forward()
+        self.batch.fit_capacity(slack)
+
+    def step(self, stream=None):
+        b = self.batch
+        b.forward(stream=stream, check_overflow=False)
+        b.loss(self.gt, self.lc, out=self.loss_out, stream=stream)
+        b.backward(stream=stream)
+        adam_step_device(self.P, self.G, self.m, self.v, self.lr, self.state, self.betas[0], self.betas[1],
+                         self.eps, stream=stream)
+        return self.loss_out
+
+    def capture(self):
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                self.step()
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+        return self.loss_out
+
+    def overflowed(self):
+        return bool(self.batch.status().overflow)
