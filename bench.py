@@ -76,14 +76,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_batch(scene, cfg, torch):
+def build_batch(scene, cfg, torch, want_grads=True):
     from paper_2501_01677_amd.raster import Batch, gaussians_to_device
     sets = [gaussians_to_device(s) for s in scene.sets]
     renders = []
     for rd in scene.renders:
         m = None if rd.mask is None else torch.from_numpy(np.ascontiguousarray(rd.mask)).cuda()
         renders.append(dict(set=rd.set_index, camera=rd.camera, mask=m))
-    return Batch(sets, renders, cfg)
+    return Batch(sets, renders, cfg, want_grads=want_grads)
 
 
 def fill_gouts(batch, scene, seed, torch):
@@ -233,6 +233,92 @@ def _graph_time(bb, torch, steps):
     return dt
 
 
+def _replay_time(fn, torch, steps):
+    """Captures fn() once into a HIP graph and times `steps` replays (s)."""
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            fn()
+    torch.cuda.current_stream().wait_stream(s)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    del g
+    return dt
+
+
+def ground_truth(scene, torch, tile=16):
+    """Training targets: renders of the generating scene (rgb planes)."""
+    from paper_2501_01677_amd.raster import RenderConfig
+    b = build_batch(scene, RenderConfig(tile=tile), torch, want_grads=False)
+    b.forward()
+    gt = [o["rgb"].clone() for o in b.out]
+    del b.workspace
+    del b
+    torch.cuda.empty_cache()
+    return gt
+
+
+def with_loss_time(batch, gt, torch, steps):
+    """Forward + loss (masked L1 + 0.01 boundary-aware normal L1) + backward
+    of the 1080p workload, one captured graph; returns ms per step."""
+    from paper_2501_01677_amd.raster import LossConfig
+    out = torch.zeros((len(batch.renders), 4), dtype=torch.float32, device="cuda")
+    lc = LossConfig()
+
+    def step():
+        batch.forward(check_overflow=False)
+        batch.loss(gt, lc, out=out)
+        batch.backward()
+
+    return _replay_time(step, torch, steps) * 1e3, out
+
+
+def train_step_bench(torch, steps):
+    """The 10M-Gaussian, 2 x 5472x3648 training step (forward, loss with the
+    balance-load term at lambda 0.41, backward, fused Adam), one captured
+    graph, starting from the generating set plus noise."""
+    import scenes
+    from paper_2501_01677_amd.raster import LossConfig, RenderConfig, Trainer, gaussians_to_device
+    sc = scenes.config5()
+    gt = ground_truth(sc, torch)
+    start = [gaussians_to_device(scenes.perturbed(55, s)) for s in sc.sets]
+    renders = [dict(set=rd.set_index, camera=rd.camera, mask=torch.from_numpy(np.ascontiguousarray(rd.mask)).cuda())
+               for rd in sc.renders]
+    t = Trainer(start, renders, gt, RenderConfig(tile=16), LossConfig(lambda_load=0.41), lr=1e-3)
+    del start
+    t.fit(1.2)
+    for _ in range(2):
+        t.step()
+    torch.cuda.synchronize()
+    t.capture()
+    t.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    if t.overflowed():
+        raise RuntimeError("pair capacity overflow in the training step")
+    masked = sum(int(rd.mask.sum()) for rd in sc.renders)
+    loss = t.loss_out.cpu().numpy().tolist()
+    res = dict(workload="10M Gaussians SH3, 2 views 5472x3648, box-silhouette masks; forward + loss "
+                        "(masked L1 + 0.01 boundary-aware normal L1, 0.41 balance-load) + backward + Adam",
+               ms_per_step=round(dt * 1e3, 3), masked_pixels=masked,
+               mpix_s=round(masked / dt / 1e6, 1), params=int(t.P.numel()),
+               pairs=int(t.batch.status().pairs_needed), loss=[[round(x, 6) for x in r] for r in loss])
+    del t
+    torch.cuda.empty_cache()
+    return res
+
+
 def batched_speedup(torch, steps=5, scale=1.0):
     """Batched graph-captured step vs the per-sub-region launch loop on 16
     sub-regions x 4 views at 1600x1200 (one Batch per sub-region, launched
@@ -294,6 +380,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-scale", type=float, default=1.0)
+    ap.add_argument("--no-train", action="store_true", help="skip the 10M-Gaussian training step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -306,6 +393,7 @@ def main():
     torch.cuda.set_device(0)
     log("[bench] generating the 1M-Gaussian 1080p workload")
     sc = scenes.config2()
+    gt = ground_truth(sc, torch, args.tile)
     cfg = RenderConfig(tile=args.tile)
     batch = build_batch(sc, cfg, torch)
     fill_gouts(batch, sc, 2 + 1000, torch)
@@ -317,6 +405,8 @@ def main():
     masked = int(sc.renders[0].mask.sum())
     value = masked / (ms_wall * 1e-3) / 1e6
     dom, roof = roofline(stage, batch, sc, torch, args.tile)
+    log("[bench] forward+loss+backward")
+    ms_loss, _ = with_loss_time(batch, gt, torch, args.steps)
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -342,6 +432,9 @@ def main():
                                "fwd+bwd with fixed dL/dout",
                    "masked_pixels": masked, "tile": args.tile, "pairs": int(batch.status().pairs_needed)},
         "stages_ms": {k: round(v, 4) for k, v in stage.items()},
+        "with_loss": {"ms_per_step": round(ms_loss, 4), "mpix_s": round(masked / (ms_loss * 1e-3) / 1e6, 2),
+                      "note": "same step with the loss kernels in the graph (ground truth: the render of the "
+                              "generating scene)"},
         "roofline": roof,
     }
     del batch
@@ -352,6 +445,12 @@ def main():
             line["batched"] = batched_speedup(torch, steps=3, scale=args.batched_scale)
         except Exception as e:  # report, do not hide the headline
             line["batched"] = {"error": repr(e)}
+    if not args.no_train:
+        log("[bench] 10M-Gaussian training step")
+        try:
+            line["train_step"] = train_step_bench(torch, max(3, args.steps // 4))
+        except Exception as e:  # report, do not hide the headline
+            line["train_step"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(sc)

@@ -533,3 +533,15 @@ def load_inputs(seed, render: Render, max_count=60):
     g = rng.integers(0, max_count, (cam.height, cam.width)).astype(np.int32)
     w = _f32(rng.uniform(0.1, 3.0, (cam.height, cam.width)))
     return g, w
+
+
+def perturbed(seed, gs: GaussianSet) -> GaussianSet:
+    """The set a training run starts from: the generating set plus noise --
+    means N(0, 0.1 s) with s the Gaussian's mean axis scale, opacity logits
+    N(0, 0.1), SH coefficients N(0, 0.01)."""
+    rng = np.random.default_rng(seed)
+    s = np.exp(gs.log_scales.astype(np.float64)).mean(0)
+    means = gs.means + rng.normal(size=gs.means.shape) * (0.1 * s)[None]
+    logits = gs.opacity_logits + rng.normal(scale=0.1, size=gs.opacity_logits.shape)
+    sh = gs.sh + rng.normal(scale=0.01, size=gs.sh.shape)
+    return GaussianSet(_f32(means), gs.log_scales.copy(), gs.quats.copy(), _f32(logits), _f32(sh), gs.sh_degree)
