@@ -355,7 +355,8 @@ def batched_speedup(torch, steps=5, scale=1.0):
     masked = sum(int(rd.mask.sum()) for rd in sc.renders)
     best = None
     for name, cfg in (("graph", RenderConfig(tile=16)),
-                      ("persistent_graph", RenderConfig(tile=16, persistent=True, queue_chunk=2))):
+                      ("persistent_graph", RenderConfig(tile=16, persistent=True, queue_chunk=4,
+                                                        workgroups_per_cu=8))):
         bb = build_batch(sc, cfg, torch)
         fill_gouts(bb, sc, 4000, torch)
         _, stage = timed_steps(bb, 2, 1, torch)

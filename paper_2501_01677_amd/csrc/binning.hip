@@ -376,8 +376,9 @@ __global__ void __launch_bounds__(256) chunk_count_kernel(const uint32_t *keys0,
   __syncthreads();
   const uint32_t *kin = pp.parity ? keys1 : keys0;
   const int shift = kRadixBits * pass;
-  const uint64_t base = (uint64_t)c * kScanChunk;
-  for (int r = 0; r < kScanItems; ++r) {
+  const uint64_t base = (uint64_t)c * kRadixChunk;
+#pragma unroll
+  for (int r = 0; r < kRadixItems; ++r) {
     const uint64_t i = base + (uint64_t)r * kScanBlock + threadIdx.x;
     if (i < n) atomicAdd(&hs[(kin[i] >> shift) & (kRadixBins - 1)], 1u);
   }
@@ -388,32 +389,54 @@ __global__ void __launch_bounds__(256) chunk_count_kernel(const uint32_t *keys0,
 // Pass part 2: per digit, exclusive scan of its chunk counts along the
 // chunks, offset by the digit's base (exclusive scan of the digit totals):
 // table[d][c] becomes the output position of chunk c's first key of digit d.
-// One wave per digit.
+// One workgroup per digit; up to 8192 chunks per round are loaded at once
+// (coalesced), scanned through LDS as 256 contiguous segments, and stored.
+constexpr int kScanRound = 32;  // 256-chunk tiles per round
 __global__ void __launch_bounds__(256) chunk_scan_kernel(const uint32_t *n_dev, uint64_t n_bound, int pass,
                                                          int passes, int dynamic, const uint32_t *hist,
                                                          uint32_t *table, uint32_t nb_bound) {
+  __shared__ uint32_t seg[kScanRound * kScanBlock];
+  __shared__ uint32_t red[4];
   const uint64_t n = bounded_count(n_dev, n_bound);
   const PassPlan pp = plan_pass(hist, n, pass, passes, dynamic);
   if (pp.skip) return;
-  const uint32_t nb = (uint32_t)chunks_of(n);
-  const int lane = threadIdx.x & 63;
-  const int d = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t nb = (uint32_t)radix_chunks_of(n);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int d = blockIdx.x;
   const uint32_t *h = hist + pass * kRadixBins;
-  uint32_t run = 0;
-  for (int k = lane; k < d; k += 64) run += h[k];
-  for (int o = 32; o > 0; o >>= 1) run += __shfl_xor(run, o, 64);
+  // digit base: sum of the totals of the digits below d
+  uint32_t b = tid < d ? h[tid] : 0u;
+  for (int o = 32; o > 0; o >>= 1) b += __shfl_xor(b, o, 64);
+  if (lane == 0) red[wave] = b;
+  __syncthreads();
+  uint32_t run = red[0] + red[1] + red[2] + red[3];
   uint32_t *row = table + (uint64_t)d * nb_bound;
-  for (uint32_t c0 = 0; c0 < nb; c0 += 64) {
-    const uint32_t c = c0 + lane;
-    const uint32_t v = c < nb ? row[c] : 0u;
-    uint32_t inc = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t t = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += t;
+  for (uint32_t c0 = 0; c0 < nb; c0 += kScanRound * kScanBlock) {
+    const uint32_t m = min((uint32_t)(kScanRound * kScanBlock), nb - c0);
+    const uint32_t J = (m + kScanBlock - 1) / kScanBlock;  // entries per thread segment
+#pragma unroll 8
+    for (uint32_t j = 0; j < J; ++j) {
+      const uint32_t c = j * kScanBlock + tid;
+      seg[c] = c < m ? row[c0 + c] : 0u;
     }
-    if (c < nb) row[c] = run + inc - v;
-    run += __shfl(inc, 63, 64);
+    __syncthreads();
+    uint32_t sum = 0;
+    for (uint32_t j = 0; j < J; ++j) sum += seg[tid * J + j];
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(sum, &tot);
+    uint32_t acc = run + ex;
+    for (uint32_t j = 0; j < J; ++j) {
+      const uint32_t v = seg[tid * J + j];
+      seg[tid * J + j] = acc;
+      acc += v;
+    }
+    __syncthreads();
+    for (uint32_t j = 0; j < J; ++j) {
+      const uint32_t c = j * kScanBlock + tid;
+      if (c < m) row[c0 + c] = seg[c];
+    }
+    run += tot;
+    __syncthreads();
   }
 }
 
@@ -432,7 +455,7 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
   const PassPlan pp = plan_pass(hist, n, pass, passes, dynamic);
   const uint32_t c = blockIdx.x;
   if (c == 0 && tid == 0 && cur_word >= 0) st[cur_word] = (uint32_t)pp.final_parity;
-  if (pp.skip || (uint64_t)c * kScanChunk >= n) return;
+  if (pp.skip || (uint64_t)c * kRadixChunk >= n) return;
   const uint32_t *kin = pp.parity ? keys1 : keys0;
   const uint32_t *vin = pp.parity ? vals1 : vals0;
   uint32_t *kout = pp.parity ? keys0 : keys1;
@@ -441,10 +464,10 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
   for (int w = 0; w < 4; ++w) wrun[w][tid] = 0;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint64_t qbase = (uint64_t)c * kScanChunk + (uint64_t)wave * (kScanChunk / 4);
-  uint32_t kk[kScanItems], rk[kScanItems];
+  const uint64_t qbase = (uint64_t)c * kRadixChunk + (uint64_t)wave * (kRadixChunk / 4);
+  uint32_t kk[kRadixItems], rk[kRadixItems];
 #pragma unroll
-  for (int r = 0; r < kScanItems; ++r) {
+  for (int r = 0; r < kRadixItems; ++r) {
     const uint64_t i = qbase + (uint64_t)r * 64 + lane;
     const bool valid = i < n;
     const uint32_t key = valid ? kin[i] : 0u;
@@ -469,7 +492,7 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
   // sorted by digit, then every digit's run is written out contiguously
   __shared__ uint32_t cbase[kRadixBins];   // chunk-local start of each digit
   __shared__ uint32_t gbase[kRadixBins];   // output position of each digit's run
-  __shared__ uint32_t skey[kScanChunk], sval[kScanChunk];
+  __shared__ uint32_t skey[kRadixChunk], sval[kRadixChunk];
   {
     const uint32_t c0 = wrun[0][tid], c1 = wrun[1][tid], c2 = wrun[2][tid], c3 = wrun[3][tid];
     uint32_t tot;
@@ -483,7 +506,7 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kScanItems; ++r) {
+  for (int r = 0; r < kRadixItems; ++r) {
     if (rk[r] != 0xffffffffu) {
       const uint32_t d = (kk[r] >> shift) & (kRadixBins - 1);
       const uint32_t lp = woff[wave][d] + rk[r];
@@ -492,8 +515,8 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
     }
   }
   __syncthreads();
-  const uint64_t cstart = (uint64_t)c * kScanChunk;
-  const uint32_t cnt = (uint32_t)min((uint64_t)kScanChunk, n - cstart);
+  const uint64_t cstart = (uint64_t)c * kRadixChunk;
+  const uint32_t cnt = (uint32_t)min((uint64_t)kRadixChunk, n - cstart);
   for (uint32_t i = tid; i < cnt; i += kScanBlock) {
     const uint32_t key = skey[i];
     const uint32_t d = (key >> shift) & (kRadixBins - 1);
@@ -511,7 +534,7 @@ void radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint64_t n_bound, const ui
                 int dynamic, int hist_ready, uint32_t *hist, uint32_t *table, uint32_t *st, int cur_word,
                 hipStream_t s) {
   const int passes = (bits + kRadixBits - 1) / kRadixBits;
-  const uint32_t nb = (uint32_t)chunks_of(n_bound);
+  const uint32_t nb = (uint32_t)radix_chunks_of(n_bound);
   if (nb == 0 || passes == 0) return;
   if (!hist_ready) {
     unsigned hb = nb < 2048 ? nb : 2048;
@@ -520,7 +543,7 @@ void radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint64_t n_bound, const ui
   for (int p = 0; p < passes; ++p) {
     hipLaunchKernelGGL(chunk_count_kernel, dim3(nb), dim3(256), 0, s, keys[0], keys[1], n_dev, n_bound, p, passes,
                        dynamic, hist, table, nb);
-    hipLaunchKernelGGL(chunk_scan_kernel, dim3(kRadixBins / 4), dim3(256), 0, s, n_dev, n_bound, p, passes, dynamic,
+    hipLaunchKernelGGL(chunk_scan_kernel, dim3(kRadixBins), dim3(256), 0, s, n_dev, n_bound, p, passes, dynamic,
                        hist, table, nb);
     hipLaunchKernelGGL(chunk_scatter_kernel, dim3(nb), dim3(256), 0, s, keys[0], vals[0], keys[1], vals[1], n_dev,
                        n_bound, p, passes, dynamic, hist, table, nb, st, cur_word);

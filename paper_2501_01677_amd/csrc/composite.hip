@@ -210,32 +210,38 @@ __device__ void forward_tile(const void *__restrict__ desc, const Header &h, voi
     __syncthreads();
     if (__ballot(!done) == 0ull) continue;
     const int len = build_list(srec, (int)(b1 - b), g.ox, g.oy, l2min, list);
+    // Branch-free over the lanes (selects, no divergent blocks); the next
+    // entry and its coefficients are loaded while this one is evaluated.
+    Entry e = list[0];
+    float4 abc = sabc[len > 0 ? e.k : 0];
     for (int t = 0; t < len; ++t) {
-      const Entry e = list[t];
-      if (!done) {
-        const float ex = lane_exponent(e, sabc[e.k], g.L);
-        if (ex >= l2min) {
-          const float a = fminf(amax, __builtin_amdgcn_exp2f(ex));
-          const float Tn = Tr * (1.f - a);
-          if (Tn < tmin) {
-            done = true;
-          } else {
-            const float4 r1 = srec[e.k][1], r2 = srec[e.k][2];
-            const float d = srec[e.k][3].x;
-            const float w = a * Tr;
-            F[0] = fmaf(w, r1.z, F[0]);
-            F[1] = fmaf(w, r1.w, F[1]);
-            F[2] = fmaf(w, r2.x, F[2]);
-            F[3] = fmaf(w, r2.y, F[3]);
-            F[4] = fmaf(w, r2.z, F[4]);
-            F[5] = fmaf(w, r2.w, F[5]);
-            F[6] = fmaf(w, d, F[6]);
-            Tr = Tn;
-            ++n;
-            last = (int32_t)(b + e.k);
-          }
-        }
+      const int tn = t + 1 < len ? t + 1 : t;
+      const Entry en = list[tn];
+      const float4 abcn = sabc[en.k];
+      const float ex = lane_exponent(e, abc, g.L);
+      const bool pass = !done && ex >= l2min;
+      if (__ballot(pass) != 0ull) {
+        const float a = fminf(amax, __builtin_amdgcn_exp2f(ex));
+        const float Tn = Tr * (1.f - a);
+        const bool stop = pass && Tn < tmin;
+        const bool blend = pass && !stop;
+        const float4 r1 = srec[e.k][1], r2 = srec[e.k][2];
+        const float d = srec[e.k][3].x;
+        const float w = blend ? a * Tr : 0.f;
+        F[0] = fmaf(w, r1.z, F[0]);
+        F[1] = fmaf(w, r1.w, F[1]);
+        F[2] = fmaf(w, r2.x, F[2]);
+        F[3] = fmaf(w, r2.y, F[3]);
+        F[4] = fmaf(w, r2.z, F[4]);
+        F[5] = fmaf(w, r2.w, F[5]);
+        F[6] = fmaf(w, d, F[6]);
+        Tr = blend ? Tn : Tr;
+        n += blend ? 1 : 0;
+        last = blend ? (int32_t)(b + e.k) : last;
+        done = done || stop;
       }
+      e = en;
+      abc = abcn;
       if ((t & 7) == 7 && __ballot(!done) == 0ull) break;
     }
   }
@@ -392,16 +398,16 @@ __device__ void backward_tile(const void *__restrict__ desc, const Header &h, vo
     if (__ballot(last >= (int32_t)bstart) != 0ull) {
       const int len = build_list(srec, cnt, g.ox, g.oy, l2min, list);
       for (int t = len - 1; t >= 0; --t) {
-        const Entry e = list[t];
-        const int32_t idx = (int32_t)(bstart + e.k);
+        const Entry cur = list[t];
+        const int32_t idx = (int32_t)(bstart + cur.k);
         // Every lane evaluates the fragment (the wave executes it anyway when
         // any lane contributes); lanes that do not contribute get zero weight.
-        const float ex = lane_exponent(e, sabc[e.k], g.L);
+        const float ex = lane_exponent(cur, sabc[cur.k], g.L);
         const bool contrib = idx <= last && ex >= l2min;
         if (__ballot(contrib) == 0ull) continue;
         const float raw = __builtin_amdgcn_exp2f(ex);
         const float a = fminf(amax, raw);
-        const float4 r0 = srec[e.k][0], r1 = srec[e.k][1], r2 = srec[e.k][2], r3 = srec[e.k][3];
+        const float4 r0 = srec[cur.k][0], r1 = srec[cur.k][1], r2 = srec[cur.k][2], r3 = srec[cur.k][3];
         const float f[7] = {r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
         const float iom = __builtin_amdgcn_rcpf(1.f - a);  // 1 / (1 - alpha), alpha <= 0.99
         const float Tp = Tr * iom;
@@ -432,7 +438,7 @@ __device__ void backward_tile(const void *__restrict__ desc, const Header &h, vo
         const float tot = wave_reduce16(v);
         const int which = (lane >> 2) & 15;
         if ((lane & 3) == 0 && which < 13 && tot != 0.f)
-          unsafeAtomicAdd(g2 + (uint64_t)sid[e.k] * kG2 + which, tot);
+          unsafeAtomicAdd(g2 + (uint64_t)sid[cur.k] * kG2 + which, tot);
       }
     }
   }

@@ -16,6 +16,8 @@ constexpr int kG2 = 16;                   // floats per 2D-gradient slot
 constexpr int kScanItems = 16;            // items per thread in scans / sorts
 constexpr int kScanBlock = 256;           // threads per scan / sort block
 constexpr int kScanChunk = kScanItems * kScanBlock;  // 4096 elements per block
+constexpr int kRadixItems = 4;            // keys per thread in a radix pass
+constexpr int kRadixChunk = kRadixItems * kScanBlock;  // 1024 keys per radix chunk
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
 
@@ -70,6 +72,7 @@ struct DevRender {
   uint32_t sat_offset;     // first row-prefix entry (tiles_y rows of tiles_x+1)
   uint32_t row_offset;     // first global tile row
   uint32_t amask_offset;   // first word of the active-tile bit mask (rows of ceil(tiles_x/32) words)
+  uint32_t loss_block_offset;  // first 16x16 loss block of this render (partial-sum slots)
 };
 
 struct Layout {
@@ -90,7 +93,8 @@ struct Layout {
   uint64_t rtable;               // uint32 [256][chunks] radix chunk offsets
   uint64_t qkey[2], qval0;       // queue sort buffers (the result lands in `queue`)
   uint64_t stats;
-  uint64_t loss;  // double [n_renders][8] loss accumulators
+  uint64_t loss;       // double [n_renders][8] loss accumulators
+  uint64_t loss_part;  // double [loss blocks][2] per-block partial sums of the loss terms
   uint64_t end;
 };
 
@@ -194,6 +198,7 @@ void launch_load_stats(const void *d_desc, const Header &h, const void *ws, int 
 
 // Blocks of kScanChunk elements covering n.
 __host__ __device__ inline uint64_t chunks_of(uint64_t n) { return (n + kScanChunk - 1) / kScanChunk; }
+__host__ __device__ inline uint64_t radix_chunks_of(uint64_t n) { return (n + kRadixChunk - 1) / kRadixChunk; }
 constexpr int kDepthPasses = 4;
 __host__ __device__ inline int tile_passes(uint32_t tile_bits) { return (int)((tile_bits + kRadixBits - 1) / kRadixBits); }
 

@@ -24,7 +24,7 @@
 //                depth normals and their gradients are formed once per cell
 //                of the 18 x 18 ring, then every pixel gathers the depth
 //                gradient from the up-to-five normals its point enters
-//   loss_final   per render: the four loss values
+//   loss_final   per render: sum of the block partials, the four loss values
 // plus the luminance weights of Eq. 9 (weights_grad, weights_final).
 #include "internal.h"
 
@@ -46,6 +46,17 @@ __device__ __forceinline__ double wave_sum_d(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
   return x;
+}
+
+// Sum of one double per thread over a 256-thread block (valid in thread 0).
+__device__ inline double block_sum_d(double x) {
+  __shared__ double part[4];
+  x = wave_sum_d(x);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
+  __syncthreads();
+  const double t = part[0] + part[1] + part[2] + part[3];
+  __syncthreads();
+  return t;
 }
 
 __global__ void fill_f64_kernel(double *p, int n) {
@@ -74,11 +85,11 @@ __global__ void __launch_bounds__(256) loss_tiles_kernel(const void *__restrict_
       a3 += k * k;
     }
   }
-  a0 = wave_sum_d(a0);
-  a1 = wave_sum_d(a1);
-  a2 = wave_sum_d(a2);
-  a3 = wave_sum_d(a3);
-  if ((threadIdx.x & 63) == 0) {
+  a0 = block_sum_d(a0);
+  a1 = block_sum_d(a1);
+  a2 = block_sum_d(a2);
+  a3 = block_sum_d(a3);
+  if (threadIdx.x == 0) {
     double *acc = acc_all + kAcc * r;
     atomicAdd(&acc[0], a0);
     atomicAdd(&acc[1], a1);
@@ -89,7 +100,9 @@ __global__ void __launch_bounds__(256) loss_tiles_kernel(const void *__restrict_
 
 __device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
 
-// acc[4] sum |rgb - gt|, acc[5] sum w e.  One block per 16 x 16 pixels.
+// Per block: partial sums of |rgb - gt| and of w e into the block's two
+// loss_part slots (zeros for blocks without masked pixels).  One block per
+// 16 x 16 pixels.
 __global__ void __launch_bounds__(256) loss_pixels_kernel(const void *__restrict__ desc, void *__restrict__ ws, int r,
                                                           const float *__restrict__ gt, LossParams lp) {
   const Header &h = *header(desc);
@@ -97,13 +110,13 @@ __global__ void __launch_bounds__(256) loss_pixels_kernel(const void *__restrict
   const int W = rd.cam.W, H = rd.cam.H;
   const int bpr = (W + kLB - 1) / kLB;
   const int x0 = (blockIdx.x % bpr) * kLB, y0 = (blockIdx.x / bpr) * kLB;
-  double *acc = ws_ptr<double>(ws, h.ws.loss) + kAcc * r;
+  const double *acc = ws_ptr<double>(ws, h.ws.loss) + kAcc * r;
+  double *part = ws_ptr<double>(ws, h.ws.loss_part) + 2 * ((uint64_t)rd.loss_block_offset + blockIdx.x);
   const uint64_t plane = (uint64_t)W * H;
 
   __shared__ float sP[3][kSX * kSX];
   __shared__ uint8_t sF[kSX * kSX];   // bit0 valid (masked, depth > 0), bit1 masked, bit2 inside the image
   __shared__ float sG[6][kGX * kGX];  // dL/d(dPx), dL/d(dPy)
-  __shared__ double sred[2][4];
 
   const float fx = rd.cam.fx, fy = rd.cam.fy, cx = rd.cam.cx, cy = rd.cam.cy;
   int any = 0;
@@ -132,7 +145,13 @@ __global__ void __launch_bounds__(256) loss_pixels_kernel(const void *__restrict
     sP[1][k] = py;
     sP[2][k] = pz;
   }
-  if (__syncthreads_or(any) == 0) return;  // no masked pixel in this block
+  if (__syncthreads_or(any) == 0) {  // no masked pixel in this block
+    if (threadIdx.x == 0) {
+      part[0] = 0.0;
+      part[1] = 0.0;
+    }
+    return;
+  }
 
   const double Md = acc[0];
   const float inv_m = Md > 0.0 ? (float)(1.0 / Md) : 0.f;
@@ -253,26 +272,34 @@ __global__ void __launch_bounds__(256) loss_pixels_kernel(const void *__restrict
       if (rd.g_alpha) const_cast<float *>(rd.g_alpha)[p] = 0.f;
     }
   }
-  double a = wave_sum_d((double)r_sum), b = wave_sum_d((double)e_sum);
-  const int wv = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    sred[0][wv] = a;
-    sred[1][wv] = b;
-  }
-  __syncthreads();
+  const double a = block_sum_d((double)r_sum);
+  const double b = block_sum_d((double)e_sum);
   if (threadIdx.x == 0) {
-    atomicAdd(&acc[4], sred[0][0] + sred[0][1] + sred[0][2] + sred[0][3]);
-    atomicAdd(&acc[5], sred[1][0] + sred[1][1] + sred[1][2] + sred[1][3]);
+    part[0] = a;
+    part[1] = b;
   }
 }
 
-__global__ void loss_final_kernel(const double *__restrict__ acc_all, int n_renders, LossParams lp,
-                                  float *__restrict__ out) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_renders) return;
-  const double *acc = acc_all + kAcc * r;
+// One block per render: reduce the render's block partials, then the four
+// loss values.
+__global__ void __launch_bounds__(256) loss_final_kernel(const void *__restrict__ desc, const void *__restrict__ ws,
+                                                         LossParams lp, float *__restrict__ out) {
+  const Header &h = *header(desc);
+  const int r = blockIdx.x;
+  const DevRender &rd = renders_of(desc)[r];
+  const uint64_t nb = (uint64_t)((rd.cam.W + kLB - 1) / kLB) * ((rd.cam.H + kLB - 1) / kLB);
+  const double *part = ws_ptr<const double>(const_cast<void *>(ws), h.ws.loss_part) + 2 * (uint64_t)rd.loss_block_offset;
+  double s_rgb = 0.0, s_n = 0.0;
+  for (uint64_t k = threadIdx.x; k < nb; k += blockDim.x) {
+    s_rgb += part[2 * k];
+    s_n += part[2 * k + 1];
+  }
+  s_rgb = block_sum_d(s_rgb);
+  s_n = block_sum_d(s_n);
+  if (threadIdx.x != 0) return;
+  const double *acc = ws_ptr<const double>(const_cast<void *>(ws), h.ws.loss) + kAcc * r;
   const double M = acc[0] > 0 ? acc[0] : 1.0;
-  const double l_rgb = acc[4] / (3.0 * M), l_ban = acc[5] / M;
+  const double l_rgb = s_rgb / (3.0 * M), l_ban = s_n / M;
   const double nt = acc[1] > 0 ? acc[1] : 1.0;
   const double mean = acc[2] / nt;
   double var = acc[3] / nt - mean * mean;
@@ -316,9 +343,9 @@ __global__ void __launch_bounds__(256) weights_grad_kernel(const void *__restric
       n += 1.0;
     }
   }
-  s = wave_sum_d(s);
-  n = wave_sum_d(n);
-  if ((threadIdx.x & 63) == 0) {
+  s = block_sum_d(s);
+  n = block_sum_d(n);
+  if (threadIdx.x == 0) {
     double *acc = ws_ptr<double>(ws, h.ws.loss) + kAcc * r;
     atomicAdd(&acc[6], s);
     atomicAdd(&acc[7], n);
@@ -350,7 +377,7 @@ LossParams params_of(const pgsag_loss_config &lc) {
 
 unsigned grid_for(uint64_t n) {
   const uint64_t b = (n + 255) / 256;
-  return (unsigned)(b < 2048 ? (b ? b : 1) : 2048);
+  return (unsigned)(b < 512 ? (b ? b : 1) : 512);
 }
 
 }  // namespace
@@ -368,15 +395,14 @@ void launch_loss(const void *d_desc, const void *h_desc, void *ws, const pgsag_l
     max_tiles = t > max_tiles ? t : max_tiles;
   }
   unsigned tb = (unsigned)((max_tiles + 255) / 256);
-  tb = tb > 64 ? 64 : tb;
+  tb = tb > 16 ? 16 : tb;
   hipLaunchKernelGGL(loss_tiles_kernel, dim3(tb, h.n_renders), dim3(256), 0, s, d_desc, (const void *)ws, acc);
   const LossParams lp = params_of(lc);
   for (int r = 0; r < h.n_renders; ++r) {
     const unsigned blocks = (unsigned)(((rd[r].cam.W + kLB - 1) / kLB) * ((rd[r].cam.H + kLB - 1) / kLB));
     if (blocks) hipLaunchKernelGGL(loss_pixels_kernel, dim3(blocks), dim3(256), 0, s, d_desc, ws, r, gt[r], lp);
   }
-  hipLaunchKernelGGL(loss_final_kernel, dim3((h.n_renders + 63) / 64), dim3(64), 0, s, (const double *)acc,
-                     h.n_renders, lp, out);
+  hipLaunchKernelGGL(loss_final_kernel, dim3(h.n_renders), dim3(256), 0, s, d_desc, (const void *)ws, lp, out);
 }
 
 void launch_luminance_weights(const void *d_desc, const void *h_desc, void *ws, int r, const float *gt,

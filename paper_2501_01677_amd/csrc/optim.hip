@@ -106,11 +106,15 @@ __global__ void __launch_bounds__(256) load_sums_kernel(const void *__restrict__
       a[5] += x * x;
     }
   }
+  __shared__ double part[6][4];
   for (int k = 0; k < 6; ++k) {
     double x = a[k];
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    if ((threadIdx.x & 63) == 0) atomicAdd(&sums[k], x);
+    if ((threadIdx.x & 63) == 0) part[k][threadIdx.x >> 6] = x;
   }
+  __syncthreads();
+  if (threadIdx.x < 6) atomicAdd(&sums[threadIdx.x], part[threadIdx.x][0] + part[threadIdx.x][1] +
+                                                        part[threadIdx.x][2] + part[threadIdx.x][3]);
 }
 
 __global__ void load_final_kernel(const double *__restrict__ sums, float *__restrict__ out) {
@@ -165,7 +169,7 @@ void launch_load_stats(const void *d_desc, const Header &h, const void *ws, int 
                        float *out, hipStream_t s) {
   double *sums = reinterpret_cast<double *>(static_cast<char *>(const_cast<void *>(ws)) + h.ws.stats) + 8 * r;
   hipLaunchKernelGGL(zero_f64_kernel, dim3(1), dim3(64), 0, s, sums, 8);
-  hipLaunchKernelGGL(load_sums_kernel, dim3(1024), dim3(256), 0, s, d_desc, ws, r, pixel_weight, sums);
+  hipLaunchKernelGGL(load_sums_kernel, dim3(256), dim3(256), 0, s, d_desc, ws, r, pixel_weight, sums);
   hipLaunchKernelGGL(load_final_kernel, dim3(1), dim3(64), 0, s, sums, out + 4 * r);
 }
 
