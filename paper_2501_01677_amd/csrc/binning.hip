@@ -321,7 +321,8 @@ __global__ void __launch_bounds__(256) compact_kernel(const void *__restrict__ d
 
 // Digit histograms of every pass in one read of the keys.
 __global__ void __launch_bounds__(256) digit_hist_kernel(const uint32_t *__restrict__ keys, const uint32_t *n_dev,
-                                                         uint64_t n_bound, int passes, uint32_t *hist) {
+                                                         uint64_t n_bound, int passes, int dbits, uint32_t *hist) {
+  const uint32_t dmask = (1u << dbits) - 1u;
   __shared__ uint32_t hs[4][kRadixBins];
   for (int p = 0; p < 4; ++p) hs[p][threadIdx.x] = 0;
   __syncthreads();
@@ -329,7 +330,7 @@ __global__ void __launch_bounds__(256) digit_hist_kernel(const uint32_t *__restr
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const uint32_t k = keys[i];
-    for (int p = 0; p < passes; ++p) atomicAdd(&hs[p][(k >> (kRadixBits * p)) & (kRadixBins - 1)], 1u);
+    for (int p = 0; p < passes; ++p) atomicAdd(&hs[p][(k >> (dbits * p)) & dmask], 1u);
   }
   __syncthreads();
   for (int p = 0; p < passes; ++p)
@@ -365,7 +366,7 @@ __device__ inline PassPlan plan_pass(const uint32_t *hist, uint64_t n, int pass,
 // Pass part 1: digit counts of every chunk -> table[digit][chunk].
 __global__ void __launch_bounds__(256) chunk_count_kernel(const uint32_t *keys0, const uint32_t *keys1,
                                                           const uint32_t *n_dev, uint64_t n_bound, int pass,
-                                                          int passes, int dynamic, const uint32_t *hist,
+                                                          int passes, int dbits, int dynamic, const uint32_t *hist,
                                                           uint32_t *table, uint32_t nb_bound) {
   __shared__ uint32_t hs[kRadixBins];
   const uint64_t n = bounded_count(n_dev, n_bound);
@@ -375,15 +376,16 @@ __global__ void __launch_bounds__(256) chunk_count_kernel(const uint32_t *keys0,
   hs[threadIdx.x] = 0;
   __syncthreads();
   const uint32_t *kin = pp.parity ? keys1 : keys0;
-  const int shift = kRadixBits * pass;
+  const int shift = dbits * pass;
+  const uint32_t dmask = (1u << dbits) - 1u;
   const uint64_t base = (uint64_t)c * kRadixChunk;
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
     const uint64_t i = base + (uint64_t)r * kScanBlock + threadIdx.x;
-    if (i < n) atomicAdd(&hs[(kin[i] >> shift) & (kRadixBins - 1)], 1u);
+    if (i < n) atomicAdd(&hs[(kin[i] >> shift) & dmask], 1u);
   }
   __syncthreads();
-  table[(uint64_t)threadIdx.x * nb_bound + c] = hs[threadIdx.x];
+  if (threadIdx.x <= dmask) table[(uint64_t)threadIdx.x * nb_bound + c] = hs[threadIdx.x];
 }
 
 // Pass part 2: per digit, exclusive scan of its chunk counts along the
@@ -445,8 +447,8 @@ __global__ void __launch_bounds__(256) chunk_scan_kernel(const uint32_t *n_dev, 
 // workgroup barriers); waves are ordered by index and chunks by the table.
 __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uint32_t *vals0, uint32_t *keys1,
                                                             uint32_t *vals1, const uint32_t *n_dev,
-                                                            uint64_t n_bound, int pass, int passes, int dynamic,
-                                                            const uint32_t *hist, const uint32_t *table,
+                                                            uint64_t n_bound, int pass, int passes, int dbits,
+                                                            int dynamic, const uint32_t *hist, const uint32_t *table,
                                                             uint32_t nb_bound, uint32_t *st, int cur_word) {
   __shared__ uint32_t wrun[4][kRadixBins];  // per-wave running digit counts
   __shared__ uint32_t woff[4][kRadixBins];  // output position of each wave's first key of a digit
@@ -460,7 +462,8 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
   const uint32_t *vin = pp.parity ? vals1 : vals0;
   uint32_t *kout = pp.parity ? keys0 : keys1;
   uint32_t *vout = pp.parity ? vals0 : vals1;
-  const int shift = kRadixBits * pass;
+  const int shift = dbits * pass;
+  const uint32_t dmask = (1u << dbits) - 1u;
   for (int w = 0; w < 4; ++w) wrun[w][tid] = 0;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -471,10 +474,11 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
     const uint64_t i = qbase + (uint64_t)r * 64 + lane;
     const bool valid = i < n;
     const uint32_t key = valid ? kin[i] : 0u;
-    const uint32_t d = (key >> shift) & (kRadixBins - 1);
+    const uint32_t d = (key >> shift) & dmask;
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < kRadixBits; ++b) {
+      if (b >= dbits) break;
       const bool bit = (d >> b) & 1u;
       const uint64_t bb = __ballot(valid && bit);
       peers &= bit ? bb : ~bb;
@@ -498,7 +502,7 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
     uint32_t tot;
     const uint32_t cb = block_exclusive_scan(c0 + c1 + c2 + c3, &tot);
     cbase[tid] = cb;
-    gbase[tid] = table[(uint64_t)tid * nb_bound + c];
+    gbase[tid] = (uint32_t)tid <= dmask ? table[(uint64_t)tid * nb_bound + c] : 0u;
     woff[0][tid] = cb;
     woff[1][tid] = cb + c0;
     woff[2][tid] = cb + c0 + c1;
@@ -508,7 +512,7 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
 #pragma unroll
   for (int r = 0; r < kRadixItems; ++r) {
     if (rk[r] != 0xffffffffu) {
-      const uint32_t d = (kk[r] >> shift) & (kRadixBins - 1);
+      const uint32_t d = (kk[r] >> shift) & dmask;
       const uint32_t lp = woff[wave][d] + rk[r];
       skey[lp] = kk[r];
       sval[lp] = vin[qbase + (uint64_t)r * 64 + lane];
@@ -519,7 +523,7 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
   const uint32_t cnt = (uint32_t)min((uint64_t)kRadixChunk, n - cstart);
   for (uint32_t i = tid; i < cnt; i += kScanBlock) {
     const uint32_t key = skey[i];
-    const uint32_t d = (key >> shift) & (kRadixBins - 1);
+    const uint32_t d = (key >> shift) & dmask;
     const uint32_t pos = gbase[d] + (i - cbase[d]);
     kout[pos] = key;
     vout[pos] = sval[i];
@@ -534,19 +538,20 @@ void radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint64_t n_bound, const ui
                 int dynamic, int hist_ready, uint32_t *hist, uint32_t *table, uint32_t *st, int cur_word,
                 hipStream_t s) {
   const int passes = (bits + kRadixBits - 1) / kRadixBits;
+  const int dbits = digit_bits_for((uint32_t)bits);
   const uint32_t nb = (uint32_t)radix_chunks_of(n_bound);
   if (nb == 0 || passes == 0) return;
   if (!hist_ready) {
     unsigned hb = nb < 2048 ? nb : 2048;
-    hipLaunchKernelGGL(digit_hist_kernel, dim3(hb), dim3(256), 0, s, keys[0], n_dev, n_bound, passes, hist);
+    hipLaunchKernelGGL(digit_hist_kernel, dim3(hb), dim3(256), 0, s, keys[0], n_dev, n_bound, passes, dbits, hist);
   }
   for (int p = 0; p < passes; ++p) {
     hipLaunchKernelGGL(chunk_count_kernel, dim3(nb), dim3(256), 0, s, keys[0], keys[1], n_dev, n_bound, p, passes,
-                       dynamic, hist, table, nb);
-    hipLaunchKernelGGL(chunk_scan_kernel, dim3(kRadixBins), dim3(256), 0, s, n_dev, n_bound, p, passes, dynamic,
+                       dbits, dynamic, hist, table, nb);
+    hipLaunchKernelGGL(chunk_scan_kernel, dim3(1u << dbits), dim3(256), 0, s, n_dev, n_bound, p, passes, dynamic,
                        hist, table, nb);
     hipLaunchKernelGGL(chunk_scatter_kernel, dim3(nb), dim3(256), 0, s, keys[0], vals[0], keys[1], vals[1], n_dev,
-                       n_bound, p, passes, dynamic, hist, table, nb, st, cur_word);
+                       n_bound, p, passes, dbits, dynamic, hist, table, nb, st, cur_word);
   }
 }
 
@@ -613,6 +618,8 @@ __global__ void __launch_bounds__(256) emit_kernel(const void *__restrict__ desc
   const uint32_t *st = status_of(ws, h);
   __shared__ uint32_t hs[4][kRadixBins];
   const int passes = tile_passes(h.tile_bits);
+  const int tdb = digit_bits_for(h.tile_bits);
+  const uint32_t tmask = (1u << tdb) - 1u;
   for (int q = 0; q < 4; ++q) hs[q][threadIdx.x] = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -691,7 +698,7 @@ __global__ void __launch_bounds__(256) emit_kernel(const void *__restrict__ desc
         }
         key_out[off0 + t] = gt;
         val_out[off0 + t] = orec;
-        for (int q = 0; q < passes; ++q) atomicAdd(&hs[q][(gt >> (kRadixBits * q)) & (kRadixBins - 1)], 1u);
+        for (int q = 0; q < passes; ++q) atomicAdd(&hs[q][(gt >> (tdb * q)) & tmask], 1u);
       }
     }
   }

@@ -201,5 +201,12 @@ __host__ __device__ inline uint64_t chunks_of(uint64_t n) { return (n + kScanChu
 __host__ __device__ inline uint64_t radix_chunks_of(uint64_t n) { return (n + kRadixChunk - 1) / kRadixChunk; }
 constexpr int kDepthPasses = 4;
 __host__ __device__ inline int tile_passes(uint32_t tile_bits) { return (int)((tile_bits + kRadixBits - 1) / kRadixBits); }
+// Digit width of a sort over `bits` key bits: the passes of at most
+// kRadixBits each, with the bits spread evenly over them (fewer digits per
+// pass give longer runs per digit in a chunk, so better coalesced scatters).
+__host__ __device__ inline int digit_bits_for(uint32_t bits) {
+  const uint32_t passes = (bits + kRadixBits - 1) / kRadixBits;
+  return passes ? (int)((bits + passes - 1) / passes) : kRadixBits;
+}
 
 }  // namespace pgsag
