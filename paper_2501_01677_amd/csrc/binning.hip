@@ -363,7 +363,9 @@ __device__ inline PassPlan plan_pass(const uint32_t *hist, uint64_t n, int pass,
   return pp;
 }
 
-// Pass part 1: digit counts of every chunk -> table[digit][chunk].
+// Pass part 1: digit counts of every chunk -> table[digit][chunk].  RI keys
+// per thread: chunks of 256 RI keys.
+template <int RI>
 __global__ void __launch_bounds__(256) chunk_count_kernel(const uint32_t *keys0, const uint32_t *keys1,
                                                           const uint32_t *n_dev, uint64_t n_bound, int pass,
                                                           int passes, int dbits, int dynamic, const uint32_t *hist,
@@ -378,9 +380,9 @@ __global__ void __launch_bounds__(256) chunk_count_kernel(const uint32_t *keys0,
   const uint32_t *kin = pp.parity ? keys1 : keys0;
   const int shift = dbits * pass;
   const uint32_t dmask = (1u << dbits) - 1u;
-  const uint64_t base = (uint64_t)c * kRadixChunk;
+  const uint64_t base = (uint64_t)c * (RI * kScanBlock);
 #pragma unroll
-  for (int r = 0; r < kRadixItems; ++r) {
+  for (int r = 0; r < RI; ++r) {
     const uint64_t i = base + (uint64_t)r * kScanBlock + threadIdx.x;
     if (i < n) atomicAdd(&hs[(kin[i] >> shift) & dmask], 1u);
   }
@@ -396,13 +398,13 @@ __global__ void __launch_bounds__(256) chunk_count_kernel(const uint32_t *keys0,
 constexpr int kScanRound = 32;  // 256-chunk tiles per round
 __global__ void __launch_bounds__(256) chunk_scan_kernel(const uint32_t *n_dev, uint64_t n_bound, int pass,
                                                          int passes, int dynamic, const uint32_t *hist,
-                                                         uint32_t *table, uint32_t nb_bound) {
+                                                         uint32_t *table, uint32_t nb_bound, uint32_t chunk) {
   __shared__ uint32_t seg[kScanRound * kScanBlock];
   __shared__ uint32_t red[4];
   const uint64_t n = bounded_count(n_dev, n_bound);
   const PassPlan pp = plan_pass(hist, n, pass, passes, dynamic);
   if (pp.skip) return;
-  const uint32_t nb = (uint32_t)radix_chunks_of(n);
+  const uint32_t nb = (uint32_t)((n + chunk - 1) / chunk);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int d = blockIdx.x;
   const uint32_t *h = hist + pass * kRadixBins;
@@ -442,9 +444,10 @@ __global__ void __launch_bounds__(256) chunk_scan_kernel(const uint32_t *n_dev, 
   }
 }
 
-// Pass part 3: stable scatter.  Each wave ranks its own contiguous quarter
+// Pass part 3: stable scatter (chunks of 256 RI keys).  Each wave ranks its own contiguous quarter
 // of the chunk, 64 keys at a time, against wave-private running counts (no
 // workgroup barriers); waves are ordered by index and chunks by the table.
+template <int RI>
 __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uint32_t *vals0, uint32_t *keys1,
                                                             uint32_t *vals1, const uint32_t *n_dev,
                                                             uint64_t n_bound, int pass, int passes, int dbits,
@@ -457,7 +460,8 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
   const PassPlan pp = plan_pass(hist, n, pass, passes, dynamic);
   const uint32_t c = blockIdx.x;
   if (c == 0 && tid == 0 && cur_word >= 0) st[cur_word] = (uint32_t)pp.final_parity;
-  if (pp.skip || (uint64_t)c * kRadixChunk >= n) return;
+  constexpr int CH = RI * kScanBlock;
+  if (pp.skip || (uint64_t)c * CH >= n) return;
   const uint32_t *kin = pp.parity ? keys1 : keys0;
   const uint32_t *vin = pp.parity ? vals1 : vals0;
   uint32_t *kout = pp.parity ? keys0 : keys1;
@@ -467,10 +471,10 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
   for (int w = 0; w < 4; ++w) wrun[w][tid] = 0;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint64_t qbase = (uint64_t)c * kRadixChunk + (uint64_t)wave * (kRadixChunk / 4);
-  uint32_t kk[kRadixItems], rk[kRadixItems];
+  const uint64_t qbase = (uint64_t)c * CH + (uint64_t)wave * (CH / 4);
+  uint32_t kk[RI], rk[RI];
 #pragma unroll
-  for (int r = 0; r < kRadixItems; ++r) {
+  for (int r = 0; r < RI; ++r) {
     const uint64_t i = qbase + (uint64_t)r * 64 + lane;
     const bool valid = i < n;
     const uint32_t key = valid ? kin[i] : 0u;
@@ -496,7 +500,7 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
   // sorted by digit, then every digit's run is written out contiguously
   __shared__ uint32_t cbase[kRadixBins];   // chunk-local start of each digit
   __shared__ uint32_t gbase[kRadixBins];   // output position of each digit's run
-  __shared__ uint32_t skey[kRadixChunk], sval[kRadixChunk];
+  __shared__ uint32_t skey[CH], sval[CH];
   {
     const uint32_t c0 = wrun[0][tid], c1 = wrun[1][tid], c2 = wrun[2][tid], c3 = wrun[3][tid];
     uint32_t tot;
@@ -510,7 +514,7 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < kRadixItems; ++r) {
+  for (int r = 0; r < RI; ++r) {
     if (rk[r] != 0xffffffffu) {
       const uint32_t d = (kk[r] >> shift) & dmask;
       const uint32_t lp = woff[wave][d] + rk[r];
@@ -519,8 +523,8 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
     }
   }
   __syncthreads();
-  const uint64_t cstart = (uint64_t)c * kRadixChunk;
-  const uint32_t cnt = (uint32_t)min((uint64_t)kRadixChunk, n - cstart);
+  const uint64_t cstart = (uint64_t)c * CH;
+  const uint32_t cnt = (uint32_t)min((uint64_t)CH, n - cstart);
   for (uint32_t i = tid; i < cnt; i += kScanBlock) {
     const uint32_t key = skey[i];
     const uint32_t d = (key >> shift) & dmask;
@@ -539,19 +543,31 @@ void radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint64_t n_bound, const ui
                 hipStream_t s) {
   const int passes = (bits + kRadixBits - 1) / kRadixBits;
   const int dbits = digit_bits_for((uint32_t)bits);
-  const uint32_t nb = (uint32_t)radix_chunks_of(n_bound);
+  // large sorts take 2048-key chunks (longer per-digit runs, better
+  // coalesced scatters); smaller ones 1024 (more workgroups)
+  const bool big = n_bound >= (1ull << 21);
+  const uint32_t chunk = big ? 2 * kRadixChunk : kRadixChunk;
+  const uint32_t nb = (uint32_t)((n_bound + chunk - 1) / chunk);
   if (nb == 0 || passes == 0) return;
   if (!hist_ready) {
     unsigned hb = nb < 2048 ? nb : 2048;
     hipLaunchKernelGGL(digit_hist_kernel, dim3(hb), dim3(256), 0, s, keys[0], n_dev, n_bound, passes, dbits, hist);
   }
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(chunk_count_kernel, dim3(nb), dim3(256), 0, s, keys[0], keys[1], n_dev, n_bound, p, passes,
-                       dbits, dynamic, hist, table, nb);
+    if (big)
+      hipLaunchKernelGGL(chunk_count_kernel<2 * kRadixItems>, dim3(nb), dim3(256), 0, s, keys[0], keys[1], n_dev,
+                         n_bound, p, passes, dbits, dynamic, hist, table, nb);
+    else
+      hipLaunchKernelGGL(chunk_count_kernel<kRadixItems>, dim3(nb), dim3(256), 0, s, keys[0], keys[1], n_dev,
+                         n_bound, p, passes, dbits, dynamic, hist, table, nb);
     hipLaunchKernelGGL(chunk_scan_kernel, dim3(1u << dbits), dim3(256), 0, s, n_dev, n_bound, p, passes, dynamic,
-                       hist, table, nb);
-    hipLaunchKernelGGL(chunk_scatter_kernel, dim3(nb), dim3(256), 0, s, keys[0], vals[0], keys[1], vals[1], n_dev,
-                       n_bound, p, passes, dbits, dynamic, hist, table, nb, st, cur_word);
+                       hist, table, nb, chunk);
+    if (big)
+      hipLaunchKernelGGL(chunk_scatter_kernel<2 * kRadixItems>, dim3(nb), dim3(256), 0, s, keys[0], vals[0], keys[1],
+                         vals[1], n_dev, n_bound, p, passes, dbits, dynamic, hist, table, nb, st, cur_word);
+    else
+      hipLaunchKernelGGL(chunk_scatter_kernel<kRadixItems>, dim3(nb), dim3(256), 0, s, keys[0], vals[0], keys[1],
+                         vals[1], n_dev, n_bound, p, passes, dbits, dynamic, hist, table, nb, st, cur_word);
   }
 }
 
@@ -613,10 +629,12 @@ __global__ void __launch_bounds__(256) pair_scan_kernel(const void *__restrict__
 // per-row active-tile bit masks.  Work per lane is balanced whatever the
 // spread of rectangle sizes.  The digit histograms of the emitted tile ids
 // (for the tile sort) are accumulated on the way.
+constexpr uint32_t kSegRows = 8;  // rectangle rows staged per record in emission
 __global__ void __launch_bounds__(256) emit_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
   const Header &h = *header(desc);
   const uint32_t *st = status_of(ws, h);
   __shared__ uint32_t hs[4][kRadixBins];
+  __shared__ uint32_t s_seg[4][64][kSegRows];  // per wave, per owner record: row bits of its rectangle
   const int passes = tile_passes(h.tile_bits);
   const int tdb = digit_bits_for(h.tile_bits);
   const uint32_t tmask = (1u << tdb) - 1u;
@@ -658,6 +676,25 @@ __global__ void __launch_bounds__(256) emit_kernel(const void *__restrict__ desc
     const uint32_t *am_all = ws_ptr<uint32_t>(ws, h.ws.amask);
     uint32_t *key_out = ws_ptr<uint32_t>(ws, h.ws.pair_key[0]);
     uint32_t *val_out = ws_ptr<uint32_t>(ws, h.ws.pair_val[0]);
+    // Every lane, as owner of its record, stages the active-tile bits of its
+    // rectangle's rows (bit 0 = column x0) in LDS once, for rectangles of at
+    // most kSegRows rows and 32 columns; the pair lanes below then walk rows
+    // in LDS instead of issuing dependent global loads.
+    uint32_t *seg = s_seg[threadIdx.x >> 6][lane];
+    const bool staged = own && y1 - y0 <= kSegRows && x1 - x0 <= 32;
+    if (staged) {
+      const uint32_t wpr = (txn + 31) / 32;
+      const uint32_t wd = x1 - x0;
+      const uint32_t sh = x0 & 31;
+      for (uint32_t r = 0; r < y1 - y0; ++r) {
+        const uint32_t *row = am_all + amoff + (y0 + r) * wpr + x0 / 32;
+        uint64_t two = row[0];
+        if (sh + wd > 32) two |= (uint64_t)row[1] << 32;
+        seg[r] = (uint32_t)(two >> sh) & (wd == 32 ? ~0u : ((1u << wd) - 1u));
+      }
+    }
+    const uint64_t staged_mask = __ballot(staged);
+    __builtin_amdgcn_wave_barrier();
     for (uint32_t j = 0; j < total; j += 64) {
       const uint32_t t = j + lane;
       const bool live = t < total && off0 + t < cap;
@@ -676,24 +713,48 @@ __global__ void __launch_bounds__(256) emit_kernel(const void *__restrict__ desc
       const uint32_t otoff = __shfl(toff, owner, 64), otxn = __shfl(txn, owner, 64);
       const uint32_t oam = __shfl(amoff, owner, 64);
       if (live) {
-        const uint32_t wpr = (otxn + 31) / 32;
-        const uint32_t *am = am_all + oam;
         uint32_t gt = otoff + oy0 * otxn + ox0;  // (the k-th active tile always exists)
-        bool found = false;
-        for (uint32_t ty = oy0; ty < oy1 && !found; ++ty) {
-          for (uint32_t w = ox0 / 32; w * 32 < ox1; ++w) {
-            uint32_t bits = am[ty * wpr + w];
-            const uint32_t lo32 = w * 32;
-            if (ox0 > lo32) bits &= ~0u << (ox0 - lo32);
-            if (ox1 < lo32 + 32) bits &= (1u << (ox1 - lo32)) - 1u;
+        if ((staged_mask >> owner) & 1ull) {
+          const uint32_t *os = s_seg[threadIdx.x >> 6][owner];
+          for (uint32_t r = 0; r < oy1 - oy0; ++r) {
+            uint32_t bits = os[r];
             const uint32_t c = __popc(bits);
             if (k < c) {
-              for (uint32_t q = 0; q < k; ++q) bits &= bits - 1;
-              gt = otoff + ty * otxn + lo32 + (__ffs(bits) - 1);
-              found = true;
+              // position of the k-th set bit: halving search on popcounts
+              uint32_t pos = 0;
+#pragma unroll
+              for (uint32_t wdt = 16; wdt > 0; wdt >>= 1) {
+                const uint32_t lo = __popc(bits & ((1u << wdt) - 1u));
+                if (k >= lo) {
+                  k -= lo;
+                  bits >>= wdt;
+                  pos += wdt;
+                }
+              }
+              gt = otoff + (oy0 + r) * otxn + ox0 + pos;
               break;
             }
             k -= c;
+          }
+        } else {
+          const uint32_t wpr = (otxn + 31) / 32;
+          const uint32_t *am = am_all + oam;
+          bool found = false;
+          for (uint32_t ty = oy0; ty < oy1 && !found; ++ty) {
+            for (uint32_t w = ox0 / 32; w * 32 < ox1; ++w) {
+              uint32_t bits = am[ty * wpr + w];
+              const uint32_t lo32 = w * 32;
+              if (ox0 > lo32) bits &= ~0u << (ox0 - lo32);
+              if (ox1 < lo32 + 32) bits &= (1u << (ox1 - lo32)) - 1u;
+              const uint32_t c = __popc(bits);
+              if (k < c) {
+                for (uint32_t q = 0; q < k; ++q) bits &= bits - 1;
+                gt = otoff + ty * otxn + lo32 + (__ffs(bits) - 1);
+                found = true;
+                break;
+              }
+              k -= c;
+            }
           }
         }
         key_out[off0 + t] = gt;
