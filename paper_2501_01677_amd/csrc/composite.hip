@@ -220,7 +220,7 @@ __device__ void forward_tile(const void *__restrict__ desc, const Header &h, voi
       const float4 abcn = sabc[en.k];
       const float ex = lane_exponent(e, abc, g.L);
       const bool pass = !done && ex >= l2min;
-      if (__ballot(pass) != 0ull) {
+      {  // the wave's list is culled to its block: evaluate without a branch
         const float a = fminf(amax, __builtin_amdgcn_exp2f(ex));
         const float Tn = Tr * (1.f - a);
         const bool stop = pass && Tn < tmin;
