@@ -39,7 +39,6 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 struct Sizes {
   uint64_t n_gauss = 0, n_records = 0, n_tiles = 0, n_pixels = 0, sat_total = 0, n_tile_rows = 0;
   uint64_t amask_words = 0;
-  uint64_t loss_blocks = 0;
   uint32_t tile_bits = 0;
   int max_deg = 0;
 };
@@ -83,12 +82,10 @@ int validate(const pgsag_config *cfg, const pgsag_gaussians *sets, int32_t n_set
     z.sat_total += (tx + 1) * (ty + 1);
     z.n_tile_rows += ty;
     z.amask_words += ty * ((tx + 31) / 32);
-    z.loss_blocks += (uint64_t)((c.width + 15) / 16) * ((c.height + 15) / 16);
     z.n_pixels += (uint64_t)c.width * c.height;
     z.n_records += (uint64_t)sets[rd.set].n;
   }
-  if (z.n_tiles >= 0xffffffffull || z.n_records >= 0x3fffffffull || z.sat_total >= 0xffffffffull ||
-      z.loss_blocks >= 0xffffffffull)
+  if (z.n_tiles >= 0xffffffffull || z.n_records >= 0x3fffffffull || z.sat_total >= 0xffffffffull)
     return fail(PGSAG_UNSUPPORTED, "batch too large: records must stay below 2^30, tiles below 2^32");
   uint32_t bits = 0;
   while (bits < 32 && (1ull << bits) < z.n_tiles) ++bits;
@@ -143,7 +140,7 @@ Layout make_layout(const Sizes &z, uint64_t cap, int n_renders) {
   L.status = status_at;
   L.stats = take((uint64_t)n_renders * 8 * 8);
   L.loss = take((uint64_t)n_renders * 8 * 8);
-  L.loss_part = take(z.loss_blocks * 2 * 8);
+  L.loss_part = take((uint64_t)n_renders * 64 * 2 * 8);
   L.end = off;
   return L;
 }
@@ -342,7 +339,7 @@ int pgsag_pack(const pgsag_config *cfg, const pgsag_gaussians *sets, const pgsag
   uint32_t *tile_starts = reinterpret_cast<uint32_t *>(base + d.tile_starts_off);
   uint32_t *row_starts = reinterpret_cast<uint32_t *>(base + d.row_starts_off);
   uint64_t *rec_starts = reinterpret_cast<uint64_t *>(base + d.rec_starts_off);
-  uint64_t toff = 0, rowoff = 0, satoff = 0, recoff = 0, pixoff = 0, amoff = 0, lboff = 0;
+  uint64_t toff = 0, rowoff = 0, satoff = 0, recoff = 0, pixoff = 0, amoff = 0;
   const int T = cfg->tile;
   for (int r = 0; r < n_renders; ++r) {
     const pgsag_render &in = renders[r];
@@ -384,8 +381,6 @@ int pgsag_pack(const pgsag_config *cfg, const pgsag_gaussians *sets, const pgsag
     o.row_offset = (uint32_t)rowoff;
     o.amask_offset = (uint32_t)amoff;
     amoff += (uint64_t)o.tiles_y * ((o.tiles_x + 31) / 32);
-    o.loss_block_offset = (uint32_t)lboff;
-    lboff += (uint64_t)((c.width + 15) / 16) * ((c.height + 15) / 16);
     tile_starts[r] = (uint32_t)toff;
     row_starts[r] = (uint32_t)rowoff;
     rec_starts[r] = recoff;
@@ -469,7 +464,7 @@ int pgsag_backward(const void *host_desc, const void *dev_desc, void *workspace,
   hipStream_t s = static_cast<hipStream_t>(stream);
   StageTimer tm{events, s};
   launch_fill_u32(ws_ptr<uint32_t>(workspace, h->ws.g2), 0u, h->n_records * kG2, s);
-  launch_fill_u32(ws_ptr<uint32_t>(workspace, h->ws.status) + S_QUEUE_BWD, 0u, 1, s);
+  if (h->cfg.persistent) launch_fill_u32(ws_ptr<uint32_t>(workspace, h->ws.status) + S_QUEUE_BWD, 0u, 1, s);
   tm.begin(PGSAG_STAGE_BACKWARD_COMPOSITE);
   launch_backward_composite(dev_desc, *h, workspace, s);
   tm.end(PGSAG_STAGE_BACKWARD_COMPOSITE);

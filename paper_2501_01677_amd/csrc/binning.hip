@@ -138,6 +138,12 @@ __global__ void __launch_bounds__(256) tile_mask_kernel(const void *__restrict__
       am[w] = bits;
     }
   }
+  // empty [0, 0) ranges for every tile of the row (the ranges kernel only
+  // writes tiles that receive pairs)
+  {
+    uint2 *rg = ws_ptr<uint2>(ws, h.ws.ranges) + rd.tile_offset + (uint64_t)ty * tx_n;
+    for (int x = threadIdx.x; x < tx_n; x += blockDim.x) rg[x] = make_uint2(0u, 0u);
+  }
   uint32_t *tc = ws_ptr<uint32_t>(ws, h.ws.tile_count) + rd.tile_offset + (uint64_t)ty * tx_n;
   uint32_t *rs = ws_ptr<uint32_t>(ws, h.ws.sat) + rd.sat_offset + (uint64_t)ty * (tx_n + 1);
   if (threadIdx.x == 0) rs[0] = 0;
@@ -845,7 +851,6 @@ void launch_tile_sort(const void *d_desc, const Header &h, void *ws, hipStream_t
   radix_sort(keys, vals, h.pair_capacity, st + S_NPAIRS, (int)h.tile_bits, 0, 1, ws_ptr<uint32_t>(ws, h.ws.thist),
              ws_ptr<uint32_t>(ws, h.ws.rtable), st, -1, s);
   const uint32_t *sorted_tiles = ws_ptr<uint32_t>(ws, h.ws.sorted_key);
-  launch_fill_u32(ws_ptr<uint32_t>(ws, h.ws.ranges), 0u, 2 * h.n_tiles, s);
   hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(h.pair_capacity)), dim3(256), 0, s, d_desc, ws, sorted_tiles);
   if (h.cfg.persistent) {
     // LPT queue: one stable radix pass on the length bucket, so tiles of a

@@ -72,7 +72,6 @@ struct DevRender {
   uint32_t sat_offset;     // first row-prefix entry (tiles_y rows of tiles_x+1)
   uint32_t row_offset;     // first global tile row
   uint32_t amask_offset;   // first word of the active-tile bit mask (rows of ceil(tiles_x/32) words)
-  uint32_t loss_block_offset;  // first 16x16 loss block of this render (partial-sum slots)
 };
 
 struct Layout {
@@ -94,7 +93,7 @@ struct Layout {
   uint64_t qkey[2], qval0;       // queue sort buffers (the result lands in `queue`)
   uint64_t stats;
   uint64_t loss;       // double [n_renders][8] loss accumulators
-  uint64_t loss_part;  // double [loss blocks][2] per-block partial sums of the loss terms
+  uint64_t loss_part;  // double [n_renders][64][2] partial sums of the loss terms
   uint64_t end;
 };
 

@@ -36,6 +36,7 @@ constexpr int kHalo = 2;
 constexpr int kSX = kLB + 2 * kHalo;    // staged cells per side
 constexpr int kGX = kLB + 2;            // cells whose normal gradients are formed
 constexpr int kAcc = 8;                 // doubles per render
+constexpr int kSlots = 64;              // partial-sum slots per render (blocks add into slot block % 64)
 
 struct LossParams {
   float lambda_rgb, lambda_normal, boundary_weight, lambda_load, eps;
@@ -100,9 +101,9 @@ __global__ void __launch_bounds__(256) loss_tiles_kernel(const void *__restrict_
 
 __device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
 
-// Per block: partial sums of |rgb - gt| and of w e into the block's two
-// loss_part slots (zeros for blocks without masked pixels).  One block per
-// 16 x 16 pixels.
+// Per block: partial sums of |rgb - gt| and of w e, added into one of the
+// render's 64 partial-sum slots (block index mod 64: no address sees more
+// than 1/64 of the blocks).  One block per 16 x 16 pixels.
 __global__ void __launch_bounds__(256) loss_pixels_kernel(const void *__restrict__ desc, void *__restrict__ ws, int r,
                                                           const float *__restrict__ gt, LossParams lp) {
   const Header &h = *header(desc);
@@ -111,7 +112,7 @@ __global__ void __launch_bounds__(256) loss_pixels_kernel(const void *__restrict
   const int bpr = (W + kLB - 1) / kLB;
   const int x0 = (blockIdx.x % bpr) * kLB, y0 = (blockIdx.x / bpr) * kLB;
   const double *acc = ws_ptr<double>(ws, h.ws.loss) + kAcc * r;
-  double *part = ws_ptr<double>(ws, h.ws.loss_part) + 2 * ((uint64_t)rd.loss_block_offset + blockIdx.x);
+  double *part = ws_ptr<double>(ws, h.ws.loss_part) + 2 * ((uint64_t)r * kSlots + blockIdx.x % kSlots);
   const uint64_t plane = (uint64_t)W * H;
 
   __shared__ float sP[3][kSX * kSX];
@@ -145,13 +146,7 @@ __global__ void __launch_bounds__(256) loss_pixels_kernel(const void *__restrict
     sP[1][k] = py;
     sP[2][k] = pz;
   }
-  if (__syncthreads_or(any) == 0) {  // no masked pixel in this block
-    if (threadIdx.x == 0) {
-      part[0] = 0.0;
-      part[1] = 0.0;
-    }
-    return;
-  }
+  if (__syncthreads_or(any) == 0) return;  // no masked pixel in this block
 
   const double Md = acc[0];
   const float inv_m = Md > 0.0 ? (float)(1.0 / Md) : 0.f;
@@ -275,27 +270,20 @@ __global__ void __launch_bounds__(256) loss_pixels_kernel(const void *__restrict
   const double a = block_sum_d((double)r_sum);
   const double b = block_sum_d((double)e_sum);
   if (threadIdx.x == 0) {
-    part[0] = a;
-    part[1] = b;
+    atomicAdd(&part[0], a);
+    atomicAdd(&part[1], b);
   }
 }
 
-// One block per render: reduce the render's block partials, then the four
+// One wave per render: sum the render's partial-sum slots, then the four
 // loss values.
-__global__ void __launch_bounds__(256) loss_final_kernel(const void *__restrict__ desc, const void *__restrict__ ws,
-                                                         LossParams lp, float *__restrict__ out) {
+__global__ void __launch_bounds__(64) loss_final_kernel(const void *__restrict__ desc, const void *__restrict__ ws,
+                                                        LossParams lp, float *__restrict__ out) {
   const Header &h = *header(desc);
   const int r = blockIdx.x;
-  const DevRender &rd = renders_of(desc)[r];
-  const uint64_t nb = (uint64_t)((rd.cam.W + kLB - 1) / kLB) * ((rd.cam.H + kLB - 1) / kLB);
-  const double *part = ws_ptr<const double>(const_cast<void *>(ws), h.ws.loss_part) + 2 * (uint64_t)rd.loss_block_offset;
-  double s_rgb = 0.0, s_n = 0.0;
-  for (uint64_t k = threadIdx.x; k < nb; k += blockDim.x) {
-    s_rgb += part[2 * k];
-    s_n += part[2 * k + 1];
-  }
-  s_rgb = block_sum_d(s_rgb);
-  s_n = block_sum_d(s_n);
+  const double *part = ws_ptr<const double>(const_cast<void *>(ws), h.ws.loss_part) + 2 * (uint64_t)r * kSlots;
+  const double s_rgb = wave_sum_d(part[2 * threadIdx.x]);
+  const double s_n = wave_sum_d(part[2 * threadIdx.x + 1]);
   if (threadIdx.x != 0) return;
   const double *acc = ws_ptr<const double>(const_cast<void *>(ws), h.ws.loss) + kAcc * r;
   const double M = acc[0] > 0 ? acc[0] : 1.0;
@@ -389,6 +377,8 @@ void launch_loss(const void *d_desc, const void *h_desc, void *ws, const pgsag_l
   double *acc = ws_ptr<double>(ws, h.ws.loss);
   const int n = h.n_renders * kAcc;
   hipLaunchKernelGGL(fill_f64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, acc, n);
+  const int np = h.n_renders * kSlots * 2;
+  hipLaunchKernelGGL(fill_f64_kernel, dim3((np + 255) / 256), dim3(256), 0, s, ws_ptr<double>(ws, h.ws.loss_part), np);
   uint64_t max_tiles = 1;
   for (int r = 0; r < h.n_renders; ++r) {
     const uint64_t t = (uint64_t)rd[r].tiles_x * rd[r].tiles_y;
@@ -402,7 +392,7 @@ void launch_loss(const void *d_desc, const void *h_desc, void *ws, const pgsag_l
     const unsigned blocks = (unsigned)(((rd[r].cam.W + kLB - 1) / kLB) * ((rd[r].cam.H + kLB - 1) / kLB));
     if (blocks) hipLaunchKernelGGL(loss_pixels_kernel, dim3(blocks), dim3(256), 0, s, d_desc, ws, r, gt[r], lp);
   }
-  hipLaunchKernelGGL(loss_final_kernel, dim3(h.n_renders), dim3(256), 0, s, d_desc, (const void *)ws, lp, out);
+  hipLaunchKernelGGL(loss_final_kernel, dim3(h.n_renders), dim3(64), 0, s, d_desc, (const void *)ws, lp, out);
 }
 
 void launch_luminance_weights(const void *d_desc, const void *h_desc, void *ws, int r, const float *gt,

@@ -350,7 +350,6 @@ __global__ void __launch_bounds__(256) backward_preprocess_kernel(const void *__
   float gsh[3 * K];
 #pragma unroll
   for (int j = 0; j < 3 * K; ++j) gsh[j] = 0.f;
-  bool any = false;
 
   for (int vi = 0; vi < S.n_renders; ++vi) {
     const DevRender &rd = rends[S.renders[vi]];
@@ -363,7 +362,7 @@ __global__ void __launch_bounds__(256) backward_preprocess_kernel(const void *__
     const float d_col[3] = {a1.z, a1.w, a2.x};
     float d_n[3] = {a2.y, a2.z, a2.w};
     const float d_d = a3.x;
-    any = true;
+
     View v;
     project_view(c, h, g, v);
     const float *R = c.R;
@@ -479,14 +478,10 @@ __global__ void __launch_bounds__(256) backward_preprocess_kernel(const void *__
   }
 
   float *gm = S.g_means, *gl = S.g_log_scales, *gq = S.g_quats, *go_ = S.g_logits, *gsh_ = S.g_sh;
-  if (!any) {
-    if (gm) for (int k = 0; k < 3; ++k) gm[k * n + i] = 0.f;
-    if (gl) for (int k = 0; k < 3; ++k) gl[k * n + i] = 0.f;
-    if (gq) for (int k = 0; k < 4; ++k) gq[k * n + i] = 0.f;
-    if (go_) go_[i] = 0.f;
-    if (gsh_) for (int j = 0; j < 3 * K; ++j) gsh_[j * n + i] = 0.f;
-    return;
-  }
+  // A Gaussian seen by no view keeps every accumulator at zero, and the
+  // expressions below then give exact zeros: all lanes share one store
+  // sequence, so each gradient cache line is written once (a separate
+  // zero-writing branch made every line of a mixed wave be written twice).
   if (gm) for (int k = 0; k < 3; ++k) gm[k * n + i] = gmean[k];
   if (gl) for (int k = 0; k < 3; ++k) gl[k * n + i] = gs[k] * g.s[k];
   if (gq) {
