@@ -283,6 +283,23 @@ __global__ void __launch_bounds__(256) preprocess_kernel(const void *__restrict_
     uint32_t count = 0;
     uint2 rr = make_uint2(0u, 0u);
     if (key > h.cfg.z_near && opaque_enough) {
+      // Colour first: it needs only the view direction, so the SH
+      // coefficient loads (most of the bytes) are in flight while the
+      // projection and the support rectangle are computed.
+      float col[3];
+      {
+        const float dx = g.mx - c.centre[0], dy = g.my - c.centre[1], dz = g.mz - c.centre[2];
+        const float il = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
+        float B[16];
+        sh_basis(D, dx * il, dy * il, dz * il, B);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          float a = 0.5f;
+#pragma unroll
+          for (int j = 0; j < K; ++j) a += B[j] * S.sh[(3 * j + k) * n + i];
+          col[k] = fmaxf(a, 0.f);
+        }
+      }
       View v;
       project_view(c, h, g, v);
       // support: q <= 2 ln(o / alpha_min), with a small outward margin
@@ -302,16 +319,6 @@ __global__ void __launch_bounds__(256) preprocess_kernel(const void *__restrict_
           rr = make_uint2(x0 | (y0 << 16), x1 | (y1 << 16));
         }
         if (count > 0) {
-          float B[16];
-          sh_basis(D, v.dir[0], v.dir[1], v.dir[2], B);
-          float col[3];
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            float a = 0.5f;
-#pragma unroll
-            for (int j = 0; j < K; ++j) a += B[j] * S.sh[(3 * j + k) * n + i];
-            col[k] = fmaxf(a, 0.f);
-          }
           rec4[r * 4 + 0] = make_float4(v.mx, v.my, v.ca, v.cb);
           rec4[r * 4 + 1] = make_float4(v.cc, g.o, col[0], col[1]);
           rec4[r * 4 + 2] = make_float4(col[2], v.n[0], v.n[1], v.n[2]);
