@@ -270,6 +270,29 @@ int pgsag_adam_step(float *params, const float *grads, float *m, float *v, int64
 int pgsag_adam_step_device(float *params, const float *grads, float *m, float *v, int64_t n, float lr, float b1,
                            float b2, float eps, int32_t *state, void *stream);
 
+/* Adam folded into the backward pass (see pgsag_backward_adam). */
+typedef struct pgsag_adam_config {
+  float lr, b1, b2, eps;   /* as for pgsag_adam_step */
+  int32_t *step_state;     /* device int32[4], as for pgsag_adam_step_device */
+  int64_t m_offset;        /* first moment of every parameter array: its gradient pointer + m_offset floats */
+  int64_t v_offset;        /* second moment: gradient pointer + v_offset floats */
+  int32_t write_grads;     /* non-zero: also store the gradients at the gradient pointers */
+  int32_t reserved;
+} pgsag_adam_config;
+
+/* pgsag_backward followed, inside the backward projection kernel, by the
+ * Adam update of pgsag_adam_step_device applied to every raw-parameter array
+ * that has a gradient pointer in the descriptor: the parameters are updated
+ * IN PLACE (the descriptor's parameter pointers are written), the moments
+ * live at the gradient pointer plus m_offset / v_offset floats (the same
+ * layout as the gradients, e.g. three equal slices of one buffer), and the
+ * gradients themselves are stored only with write_grads.  Saves the
+ * gradient round trip through memory and a second read of the parameters
+ * (the separate update reads p, g, m, v and writes p, m, v).  Same stream,
+ * capture and ownership rules as pgsag_backward. */
+int pgsag_backward_adam(const void *host_desc, const void *dev_desc, void *workspace, size_t workspace_bytes,
+                        const pgsag_adam_config *adam, void *stream, void **events);
+
 /* Balance-load statistics of the last forward (Sec. 4.3, Eq. 9): per
  * render, over tiles with at least one masked pixel, the mean and the
  * population variance of the per-tile pair counts, and over masked pixels

@@ -74,6 +74,12 @@ class LossConfig(C.Structure):
                 ("reserved", C.c_int32 * 2)]
 
 
+class AdamConfig(C.Structure):
+    _fields_ = [("lr", C.c_float), ("b1", C.c_float), ("b2", C.c_float), ("eps", C.c_float),
+                ("step_state", C.c_void_p), ("m_offset", C.c_int64), ("v_offset", C.c_int64),
+                ("write_grads", C.c_int32), ("reserved", C.c_int32)]
+
+
 class Status(C.Structure):
     _fields_ = [("pairs_needed", C.c_uint64), ("overflow", C.c_uint32), ("n_visible", C.c_uint32)]
 
@@ -81,7 +87,7 @@ class Status(C.Structure):
 SYMBOLS = ("pgsag_version", "pgsag_last_error", "pgsag_default_config", "pgsag_plan", "pgsag_pack",
            "pgsag_layout_of", "pgsag_forward", "pgsag_backward", "pgsag_binning",
            "pgsag_read_status", "pgsag_adam_step", "pgsag_load_stats", "pgsag_default_loss_config",
-           "pgsag_loss", "pgsag_luminance_weights", "pgsag_adam_step_device")
+           "pgsag_loss", "pgsag_luminance_weights", "pgsag_adam_step_device", "pgsag_backward_adam")
 
 _lib = None
 
@@ -111,6 +117,7 @@ def lib():
     L.pgsag_read_status.argtypes = [vp, vp, C.POINTER(Status), vp]
     L.pgsag_adam_step.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp]
     L.pgsag_adam_step_device.argtypes = [vp, vp, vp, vp, i64, f32, f32, f32, f32, vp, vp]
+    L.pgsag_backward_adam.argtypes = [vp, vp, vp, C.c_size_t, C.POINTER(AdamConfig), vp, C.POINTER(vp)]
     L.pgsag_load_stats.argtypes = [vp, vp, vp, C.POINTER(vp), vp, vp]
     L.pgsag_default_loss_config.argtypes = [C.POINTER(LossConfig)]
     L.pgsag_default_loss_config.restype = None

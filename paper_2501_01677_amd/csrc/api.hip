@@ -455,12 +455,9 @@ int pgsag_forward(const void *host_desc, const void *dev_desc, void *workspace, 
   return check_hip("composite");
 }
 
-int pgsag_backward(const void *host_desc, const void *dev_desc, void *workspace, size_t workspace_bytes,
-                   void *stream, void **events) {
-  const Header *h = check_desc(host_desc);
-  int rc = check_run_args(h, dev_desc, workspace, workspace_bytes);
-  if (rc) return rc;
-  if (!h->any_grads) return fail(PGSAG_INVALID_ARGUMENT, "descriptor was packed without gradient buffers");
+namespace {
+int run_backward(const Header *h, const void *dev_desc, void *workspace, const AdamArgs &A, void *stream,
+                 void **events) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   StageTimer tm{events, s};
   launch_fill_u32(ws_ptr<uint32_t>(workspace, h->ws.g2), 0u, h->n_records * kG2, s);
@@ -468,11 +465,49 @@ int pgsag_backward(const void *host_desc, const void *dev_desc, void *workspace,
   tm.begin(PGSAG_STAGE_BACKWARD_COMPOSITE);
   launch_backward_composite(dev_desc, *h, workspace, s);
   tm.end(PGSAG_STAGE_BACKWARD_COMPOSITE);
+  int rc;
   if ((rc = check_hip("backward composite"))) return rc;
   tm.begin(PGSAG_STAGE_BACKWARD_PREPROCESS);
-  launch_backward_preprocess(dev_desc, *h, workspace, s);
+  launch_backward_preprocess(dev_desc, *h, workspace, A, s);
   tm.end(PGSAG_STAGE_BACKWARD_PREPROCESS);
   return check_hip("backward preprocess");
+}
+}  // namespace
+
+int pgsag_backward(const void *host_desc, const void *dev_desc, void *workspace, size_t workspace_bytes,
+                   void *stream, void **events) {
+  const Header *h = check_desc(host_desc);
+  int rc = check_run_args(h, dev_desc, workspace, workspace_bytes);
+  if (rc) return rc;
+  if (!h->any_grads) return fail(PGSAG_INVALID_ARGUMENT, "descriptor was packed without gradient buffers");
+  AdamArgs A{};
+  return run_backward(h, dev_desc, workspace, A, stream, events);
+}
+
+int pgsag_backward_adam(const void *host_desc, const void *dev_desc, void *workspace, size_t workspace_bytes,
+                        const pgsag_adam_config *adam, void *stream, void **events) {
+  const Header *h = check_desc(host_desc);
+  int rc = check_run_args(h, dev_desc, workspace, workspace_bytes);
+  if (rc) return rc;
+  if (!h->any_grads) return fail(PGSAG_INVALID_ARGUMENT, "descriptor was packed without gradient buffers");
+  if (!adam || !adam->step_state) return fail(PGSAG_INVALID_ARGUMENT, "null Adam configuration or step state");
+  if (!(adam->b1 >= 0.f && adam->b1 < 1.f && adam->b2 >= 0.f && adam->b2 < 1.f))
+    return fail(PGSAG_INVALID_ARGUMENT, "betas must be in [0, 1)");
+  if ((uintptr_t)adam->step_state & 3u) return fail(PGSAG_INVALID_ARGUMENT, "step state must be 4-byte aligned");
+  if (adam->m_offset == 0 || adam->v_offset == 0 || adam->m_offset == adam->v_offset)
+    return fail(PGSAG_INVALID_ARGUMENT, "moment offsets must be non-zero and distinct");
+  AdamArgs A{};
+  A.lr = adam->lr;
+  A.b1 = adam->b1;
+  A.b2 = adam->b2;
+  A.eps = adam->eps;
+  A.coef = reinterpret_cast<const float *>(adam->step_state + 1);
+  A.m_off = adam->m_offset;
+  A.v_off = adam->v_offset;
+  A.enabled = 1;
+  A.write_grads = adam->write_grads ? 1 : 0;
+  launch_adam_coef(adam->step_state, adam->b1, adam->b2, static_cast<hipStream_t>(stream));
+  return run_backward(h, dev_desc, workspace, A, stream, events);
 }
 
 int pgsag_binning(const void *host_desc, const void *dev_desc, void *workspace, size_t workspace_bytes,

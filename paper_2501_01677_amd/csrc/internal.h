@@ -185,7 +185,16 @@ void launch_emit(const void *d_desc, const Header &h, void *ws, hipStream_t s);
 void launch_tile_sort(const void *d_desc, const Header &h, void *ws, hipStream_t s);
 void launch_composite(const void *d_desc, const Header &h, void *ws, hipStream_t s);
 void launch_backward_composite(const void *d_desc, const Header &h, void *ws, hipStream_t s);
-void launch_backward_preprocess(const void *d_desc, const Header &h, void *ws, hipStream_t s);
+// Adam folded into the backward projection (a disabled instance writes the
+// plain gradients).  coef: the step's bias corrections (two floats).
+struct AdamArgs {
+  float lr, b1, b2, eps;
+  const float *coef;
+  int64_t m_off, v_off;  // moments at (gradient pointer + offset) floats
+  int32_t enabled, write_grads;
+};
+void launch_backward_preprocess(const void *d_desc, const Header &h, void *ws, const AdamArgs &adam, hipStream_t s);
+void launch_adam_coef(int32_t *state, float b1, float b2, hipStream_t s);
 void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
                  int32_t step, int32_t *state, hipStream_t s);
 void launch_loss(const void *d_desc, const void *h_desc, void *ws, const pgsag_loss_config &lc,

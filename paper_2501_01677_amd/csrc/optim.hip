@@ -165,6 +165,10 @@ void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float 
   }
 }
 
+void launch_adam_coef(int32_t *state, float b1, float b2, hipStream_t s) {
+  hipLaunchKernelGGL(adam_coef_kernel, dim3(1), dim3(64), 0, s, state, b1, b2);
+}
+
 void launch_load_stats(const void *d_desc, const Header &h, const void *ws, int r, const float *pixel_weight,
                        float *out, hipStream_t s) {
   double *sums = reinterpret_cast<double *>(static_cast<char *>(const_cast<void *>(ws)) + h.ws.stats) + 8 * r;

@@ -334,8 +334,30 @@ __global__ void __launch_bounds__(256) preprocess_kernel(const void *__restrict_
 
 // ------------------------------------------------------------ backward
 
-template <int D>
-__global__ void __launch_bounds__(256) backward_preprocess_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+// Final value of one raw-parameter gradient: stored, and with Adam enabled
+// also used to update that parameter and its moments in place.
+template <bool ADAM>
+__device__ __forceinline__ void put_grad(float *gp, const float *param, uint64_t idx, float g, const AdamArgs &A,
+                                         float c1, float c2) {
+  if constexpr (!ADAM) {
+    gp[idx] = g;
+    return;
+  }
+  if (A.write_grads) gp[idx] = g;
+  float *pm = gp + A.m_off, *pv = gp + A.v_off;
+  float *pp = const_cast<float *>(param);
+  float m = pm[idx], v = pv[idx], p = pp[idx];
+  m = A.b1 * m + (1.f - A.b1) * g;
+  v = A.b2 * v + (1.f - A.b2) * g * g;
+  p -= A.lr * (m * c1) / (sqrtf(v * c2) + A.eps);
+  pm[idx] = m;
+  pv[idx] = v;
+  pp[idx] = p;
+}
+
+template <int D, bool ADAM>
+__global__ void __launch_bounds__(256) backward_preprocess_kernel(const void *__restrict__ desc, void *__restrict__ ws,
+                                                                  AdamArgs A) {
   constexpr int K = (D + 1) * (D + 1);
   const Header &h = *header(desc);
   const DevSet *Sp;
@@ -489,23 +511,26 @@ __global__ void __launch_bounds__(256) backward_preprocess_kernel(const void *__
   // expressions below then give exact zeros: all lanes share one store
   // sequence, so each gradient cache line is written once (a separate
   // zero-writing branch made every line of a mixed wave be written twice).
-  if (gm) for (int k = 0; k < 3; ++k) gm[k * n + i] = gmean[k];
-  if (gl) for (int k = 0; k < 3; ++k) gl[k * n + i] = gs[k] * g.s[k];
+  const float c1 = ADAM ? A.coef[0] : 1.f, c2 = ADAM ? A.coef[1] : 1.f;
+  if (gm)
+    for (int k = 0; k < 3; ++k) put_grad<ADAM>(gm, S.means, k * n + i, gmean[k], A, c1, c2);
+  if (gl)
+    for (int k = 0; k < 3; ++k) put_grad<ADAM>(gl, S.log_scales, k * n + i, gs[k] * g.s[k], A, c1, c2);
   if (gq) {
     float gw, gx, gy, gz;
     quat_rot_vjp(g.qw, g.qx, g.qy, g.qz, gM, gw, gx, gy, gz);
     // through q / |q|
     const float dot = gw * g.qw + gx * g.qx + gy * g.qy + gz * g.qz;
     const float inv = 1.f / g.qn;
-    gq[i] = (gw - dot * g.qw) * inv;
-    gq[n + i] = (gx - dot * g.qx) * inv;
-    gq[2 * n + i] = (gy - dot * g.qy) * inv;
-    gq[3 * n + i] = (gz - dot * g.qz) * inv;
+    put_grad<ADAM>(gq, S.quats, i, (gw - dot * g.qw) * inv, A, c1, c2);
+    put_grad<ADAM>(gq, S.quats, n + i, (gx - dot * g.qx) * inv, A, c1, c2);
+    put_grad<ADAM>(gq, S.quats, 2 * n + i, (gy - dot * g.qy) * inv, A, c1, c2);
+    put_grad<ADAM>(gq, S.quats, 3 * n + i, (gz - dot * g.qz) * inv, A, c1, c2);
   }
-  if (go_) go_[i] = go * g.o * (1.f - g.o);
+  if (go_) put_grad<ADAM>(go_, S.logits, i, go * g.o * (1.f - g.o), A, c1, c2);
   if (gsh_) {
 #pragma unroll
-    for (int j = 0; j < 3 * K; ++j) gsh_[j * n + i] = gsh[j];
+    for (int j = 0; j < 3 * K; ++j) put_grad<ADAM>(gsh_, S.sh, j * n + i, gsh[j], A, c1, c2);
   }
 }
 
@@ -518,15 +543,23 @@ void launch_preprocess(const void *d_desc, const Header &h, void *ws, hipStream_
   if (h.deg_blocks[3]) hipLaunchKernelGGL(preprocess_kernel<3>, dim3(h.deg_blocks[3]), dim3(256), 0, s, d_desc, ws);
 }
 
-void launch_backward_preprocess(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
+template <bool ADAM>
+void launch_bwd_pre(const void *d_desc, const Header &h, void *ws, const AdamArgs &A, hipStream_t s) {
   if (h.deg_blocks[0])
-    hipLaunchKernelGGL(backward_preprocess_kernel<0>, dim3(h.deg_blocks[0]), dim3(256), 0, s, d_desc, ws);
+    hipLaunchKernelGGL((backward_preprocess_kernel<0, ADAM>), dim3(h.deg_blocks[0]), dim3(256), 0, s, d_desc, ws, A);
   if (h.deg_blocks[1])
-    hipLaunchKernelGGL(backward_preprocess_kernel<1>, dim3(h.deg_blocks[1]), dim3(256), 0, s, d_desc, ws);
+    hipLaunchKernelGGL((backward_preprocess_kernel<1, ADAM>), dim3(h.deg_blocks[1]), dim3(256), 0, s, d_desc, ws, A);
   if (h.deg_blocks[2])
-    hipLaunchKernelGGL(backward_preprocess_kernel<2>, dim3(h.deg_blocks[2]), dim3(256), 0, s, d_desc, ws);
+    hipLaunchKernelGGL((backward_preprocess_kernel<2, ADAM>), dim3(h.deg_blocks[2]), dim3(256), 0, s, d_desc, ws, A);
   if (h.deg_blocks[3])
-    hipLaunchKernelGGL(backward_preprocess_kernel<3>, dim3(h.deg_blocks[3]), dim3(256), 0, s, d_desc, ws);
+    hipLaunchKernelGGL((backward_preprocess_kernel<3, ADAM>), dim3(h.deg_blocks[3]), dim3(256), 0, s, d_desc, ws, A);
+}
+
+void launch_backward_preprocess(const void *d_desc, const Header &h, void *ws, const AdamArgs &A, hipStream_t s) {
+  if (A.enabled)
+    launch_bwd_pre<true>(d_desc, h, ws, A, s);
+  else
+    launch_bwd_pre<false>(d_desc, h, ws, A, s);
 }
 
 }  // namespace pgsag

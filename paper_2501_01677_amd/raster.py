@@ -244,6 +244,22 @@ class Batch:
                                         self._events(events)), "pgsag_backward")
         return self.grads
 
+    def backward_adam(self, lr, state, m_offset, v_offset, b1=0.9, b2=0.999, eps=1e-8, write_grads=False,
+                      stream=None, events=None):
+        """Backward pass with the Adam update of every parameter folded in:
+        parameters updated in place, moments at the gradient tensors' storage
+        plus m_offset / v_offset floats, step count in ``state``."""
+        if not self.want_grads:
+            raise RuntimeError("batch was built without gradients")
+        cfg = A.AdamConfig()
+        cfg.lr, cfg.b1, cfg.b2, cfg.eps = lr, b1, b2, eps
+        cfg.step_state = state.data_ptr()
+        cfg.m_offset, cfg.v_offset = int(m_offset), int(v_offset)
+        cfg.write_grads = int(bool(write_grads))
+        A.check(self.lib.pgsag_backward_adam(self.host_desc, _p(self.dev_desc), _p(self.workspace),
+                                             int(self.info.workspace_bytes), C.byref(cfg), _stream(stream),
+                                             self._events(events)), "pgsag_backward_adam")
+
     def binning(self, stream=None):
         A.check(self.lib.pgsag_binning(self.host_desc, _p(self.dev_desc), _p(self.workspace),
                                        int(self.info.workspace_bytes), _stream(stream)), "pgsag_binning")
@@ -384,21 +400,31 @@ def _param_sizes(n, sh_degree):
 class Trainer:
     """One optimisation step over a batch of renders: forward, the loss of
     Sec. 4.2-4.3 against ground-truth images, backward, and one fused Adam
-    update over every raw parameter of every set.  Parameters, gradients and
-    Adam moments live in four flat device buffers (one Adam launch); the
-    per-set tensors are views into them.  ``step`` is capturable: ``capture``
+    update over every raw parameter of every set.  Parameters live in one
+    flat device buffer, gradients and Adam moments in three equal slices of
+    another; the per-set tensors are views into them.  With ``fused`` (the
+    default) the update runs inside the backward projection kernel
+    (pgsag_backward_adam; the gradients are then stored only with
+    ``keep_grads``), otherwise as a separate fused Adam launch.  ``step`` is capturable: ``capture``
     records it once into a HIP graph and ``replay`` runs it."""
 
     def __init__(self, sets, renders, gt, cfg: RenderConfig | None = None, lc: LossConfig | None = None,
-                 lr=1e-3, betas=(0.9, 0.999), eps=1e-8, pair_capacity=None, device="cuda"):
+                 lr=1e-3, betas=(0.9, 0.999), eps=1e-8, pair_capacity=None, device="cuda", fused=True,
+                 keep_grads=False):
         total = 0
         for s in sets:
             for _, shp in _param_sizes(int(s["means"].shape[1]), int(s["sh_degree"])):
                 total += int(np.prod(shp))
+        self.total = total
+        self.fused = fused
+        self.keep_grads = keep_grads
         self.P = torch.empty(total, dtype=torch.float32, device=device)
-        self.G = torch.zeros(total, dtype=torch.float32, device=device)
-        self.m = torch.zeros_like(self.P)
-        self.v = torch.zeros_like(self.P)
+        # gradients, first and second moments: three equal slices of one
+        # buffer, so the fused update finds the moments at fixed offsets
+        self.GMV = torch.zeros(3 * total, dtype=torch.float32, device=device)
+        self.G = self.GMV[:total]
+        self.m = self.GMV[total:2 * total]
+        self.v = self.GMV[2 * total:]
         self.state = torch.zeros(4, dtype=torch.int32, device=device)
         self.params, grads = [], []
         off = 0
@@ -430,9 +456,13 @@ class Trainer:
         b = self.batch
         b.forward(stream=stream, check_overflow=False)
         b.loss(self.gt, self.lc, out=self.loss_out, stream=stream)
-        b.backward(stream=stream)
-        adam_step_device(self.P, self.G, self.m, self.v, self.lr, self.state, self.betas[0], self.betas[1],
-                         self.eps, stream=stream)
+        if self.fused:
+            b.backward_adam(self.lr, self.state, self.total, 2 * self.total, self.betas[0], self.betas[1], self.eps,
+                            write_grads=self.keep_grads, stream=stream)
+        else:
+            b.backward(stream=stream)
+            adam_step_device(self.P, self.G, self.m, self.v, self.lr, self.state, self.betas[0], self.betas[1],
+                             self.eps, stream=stream)
         return self.loss_out
 
     def capture(self):

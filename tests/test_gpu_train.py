@@ -62,12 +62,12 @@ def _oracle_step_grads(sc, gts, refs, olc):
     return total, losses
 
 
-def _trainer(sc, gts, lc, lr=1e-3):
+def _trainer(sc, gts, lc, lr=1e-3, **kw):
     dev = [gaussians_to_device(s) for s in sc.sets]
     renders = [dict(set=rd.set_index, camera=rd.camera, mask=torch.from_numpy(np.ascontiguousarray(rd.mask)).cuda())
                for rd in sc.renders]
     gt = [torch.from_numpy(g).cuda() for g in gts]
-    t = Trainer(dev, renders, gt, RenderConfig(tile=16), lc, lr=lr)
+    t = Trainer(dev, renders, gt, RenderConfig(tile=16), lc, lr=lr, **kw)
     t.fit()
     return t
 
@@ -78,7 +78,7 @@ def test_training_step_gradient_matches_oracle_chain():
     lc = LossConfig(lambda_normal=0.2, normal_norm=2, lambda_load=0.41)
     olc = ol.LossConfig(lambda_normal=0.2, normal_norm=2, lambda_load=0.41)
     ref, losses = _oracle_step_grads(sc, gts, refs, olc)
-    t = _trainer(sc, gts, lc, lr=0.0)
+    t = _trainer(sc, gts, lc, lr=0.0, keep_grads=True)
     out = t.step().cpu().numpy()
     torch.cuda.synchronize()
     # the geometric terms (the load term is a value of the binning only)
@@ -136,3 +136,28 @@ def test_device_step_adam_matches_host_step():
     assert int(st[0]) == 2
     for x, y in ((P[0], P[1]), (M[0], M[1]), (V[0], V[1])):
         np.testing.assert_allclose(y.cpu().numpy(), x.cpu().numpy(), rtol=1e-6, atol=1e-9)
+
+
+@pytest.mark.parametrize("keep_grads", [False, True])
+def test_adam_folded_into_backward_matches_separate_update(keep_grads):
+    print(f"[case] fused backward+Adam keep_grads={keep_grads}", flush=True)
+    sc, gts, _ = _prepared_scene(403)
+    lc = LossConfig(lambda_load=0.41)
+    a = _trainer(sc, gts, lc, fused=False)
+    b = _trainer(sc, gts, lc, fused=True, keep_grads=keep_grads)
+    for _ in range(3):
+        la = a.step().clone()
+        lb = b.step().clone()
+        np.testing.assert_allclose(lb.cpu().numpy(), la.cpu().numpy(), rtol=1e-5, atol=1e-7)
+    torch.cuda.synchronize()
+    assert int(a.state[0]) == 3 and int(b.state[0]) == 3
+    for x, y in ((a.P, b.P), (a.m, b.m), (a.v, b.v)):
+        d = np.abs(x.cpu().numpy() - y.cpu().numpy())
+        # the same FP32 update; gradients differ only by float-atomic order
+        assert np.mean(d <= 1e-6 + 1e-5 * np.abs(x.cpu().numpy())) > 0.999
+        assert d.max() <= 6e-3
+    gb = b.G.cpu().numpy()
+    if keep_grads:
+        np.testing.assert_allclose(gb, a.G.cpu().numpy(), rtol=1e-3, atol=1e-5 * np.abs(a.G.cpu().numpy()).max())
+    else:
+        assert not np.any(gb), "gradients must not be stored without keep_grads"
