@@ -221,7 +221,8 @@ __device__ void forward_tile(const void *__restrict__ desc, const Header &h, voi
       const float ex = lane_exponent(e, abc, g.L);
       const bool pass = !done && ex >= l2min;
       {  // the wave's list is culled to its block: evaluate without a branch
-        const float a = fminf(amax, __builtin_amdgcn_exp2f(ex));
+        // exp2 >= 0: the median of (x, 0, amax) is min(x, amax) in one instruction
+        const float a = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(ex), 0.f, amax);
         const float Tn = Tr * (1.f - a);
         const bool stop = pass && Tn < tmin;
         const bool blend = pass && !stop;
@@ -406,7 +407,7 @@ __device__ void backward_tile(const void *__restrict__ desc, const Header &h, vo
         const bool contrib = idx <= last && ex >= l2min;
         if (__ballot(contrib) == 0ull) continue;
         const float raw = __builtin_amdgcn_exp2f(ex);
-        const float a = fminf(amax, raw);
+        const float a = __builtin_amdgcn_fmed3f(raw, 0.f, amax);  // min(raw, amax), raw >= 0
         const float4 r0 = srec[cur.k][0], r1 = srec[cur.k][1], r2 = srec[cur.k][2], r3 = srec[cur.k][3];
         const float f[7] = {r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
         const float iom = __builtin_amdgcn_rcpf(1.f - a);  // 1 / (1 - alpha), alpha <= 0.99
