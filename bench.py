@@ -320,9 +320,10 @@ def train_step_bench(torch, steps):
 
 
 def batched_speedup(torch, steps=5, scale=1.0):
-    """Batched graph-captured step vs the per-sub-region launch loop on 16
-    sub-regions x 4 views at 1600x1200 (one Batch per sub-region, launched
-    one after another, no graph)."""
+    """Batched graph-captured step (autotuned launch configuration) vs the
+    per-sub-region launch loop on 16 sub-regions x 4 views at 1600x1200 (one
+    Batch per sub-region, 16x16 tiles, launched one after another, no
+    graph)."""
     import scenes
     from paper_2501_01677_amd.raster import RenderConfig
     sc = scenes.config4(scale=scale)
@@ -353,20 +354,29 @@ def batched_speedup(torch, steps=5, scale=1.0):
     out = dict(workload="16 sub-regions x 4 views, 1600x1200, %d Gaussians" % sum(s.n for s in sc.sets),
                loop_ms=round(t_loop * 1e3, 3))
     masked = sum(int(rd.mask.sum()) for rd in sc.renders)
-    best = None
-    for name, cfg in (("graph", RenderConfig(tile=16)),
-                      ("persistent_graph", RenderConfig(tile=16, persistent=True, queue_chunk=4,
-                                                        workgroups_per_cu=8))):
-        bb = build_batch(sc, cfg, torch)
-        fill_gouts(bb, sc, 4000, torch)
-        _, stage = timed_steps(bb, 2, 1, torch)
-        dt = _graph_time(bb, torch, steps)
-        out[name + "_ms"] = round(dt * 1e3, 3)
-        out[name + "_stages_ms"] = {k: round(v, 3) for k, v in stage.items()}
-        best = dt if best is None else min(best, dt)
-        del bb.workspace
-        del bb
-        torch.cuda.empty_cache()
+    # one batch for all sub-regions and views; the launch configuration is
+    # picked by the autotuner (captured fwd+bwd step timed per candidate)
+    from paper_2501_01677_amd.autotune import Autotuner
+    bb = build_batch(sc, RenderConfig(tile=16), torch)
+    fill_gouts(bb, sc, 4000, torch)
+    gouts = [{k: v.clone() for k, v in g.items()} for g in bb.gout]
+    tuner = Autotuner(steps=steps)
+    cfg, times = tuner.best(bb.sets, bb.renders, gouts)
+    del bb.workspace
+    del bb
+    torch.cuda.empty_cache()
+    out["autotune_ms"] = {k: round(v * 1e3, 3) for k, v in times.items()}
+    bb = build_batch(sc, cfg, torch)
+    fill_gouts(bb, sc, 4000, torch)
+    _, stage = timed_steps(bb, 2, 1, torch)
+    best = _graph_time(bb, torch, steps)
+    out["graph_ms"] = round(best * 1e3, 3)
+    out["graph_config"] = {"tile": cfg.tile, "persistent": cfg.persistent, "queue_chunk": cfg.queue_chunk,
+                           "workgroups_per_cu": cfg.workgroups_per_cu}
+    out["graph_stages_ms"] = {k: round(v, 3) for k, v in stage.items()}
+    del bb.workspace
+    del bb
+    torch.cuda.empty_cache()
     out["speedup"] = round(t_loop / best, 3)
     out["batched_mpix_s"] = round(masked / best / 1e6, 1)
     return out

@@ -138,3 +138,15 @@ def test_adam_rejects_bad_arguments_without_touching_memory():
     assert L.pgsag_adam_step(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 1, None) == A.INVALID_ARGUMENT
     p = C.c_void_p(0x1000)
     assert L.pgsag_adam_step(p, p, p, p, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == A.INVALID_ARGUMENT
+
+
+def test_autotune_shape_key_buckets():
+    import torch
+    from paper_2501_01677_amd.autotune import shape_key
+    cam = type("Cam", (), dict(width=64, height=32))()
+    sets = [dict(means=torch.zeros(3, 1000), sh_degree=2), dict(means=torch.zeros(3, 3000), sh_degree=1)]
+    mask = torch.zeros(32, 64, dtype=torch.uint8)
+    mask[:, :16] = 1
+    renders = [dict(set=0, camera=cam, mask=mask), dict(set=1, camera=cam, mask=None)]
+    # 512 + 2048 masked pixels, 4000 Gaussians, max SH degree 2
+    assert shape_key(sets, renders) == "r2-px11-n11-sh2"
