@@ -118,13 +118,19 @@ def timed_steps(batch, steps, warmup, torch, events=True):
         raise RuntimeError("pair capacity overflow inside the timed region")
     stage = {}
     if ev is not None:
+        per_step = np.zeros((steps, A.NUM_STAGES))
         for s, name in enumerate(A.STAGES):
-            tot = 0.0
             for k in range(steps):
                 base = 2 * A.NUM_STAGES * k
-                tot += ev.elapsed_ms(base + 2 * s, base + 2 * s + 1)
-            stage[name] = tot / steps
+                per_step[k, s] = ev.elapsed_ms(base + 2 * s, base + 2 * s + 1)
+            stage[name] = float(per_step[:, s].mean())
         ev.close()
+        # forward = stages 0-5, backward = 6-7 (the order of pgsag_stage)
+        fwd, bwd = per_step[:, :6].sum(1), per_step[:, 6:].sum(1)
+        tot = fwd + bwd
+        q = lambda x: {"p10": round(float(np.percentile(x, 10)), 4), "p50": round(float(np.median(x)), 4),
+                       "p90": round(float(np.percentile(x, 90)), 4)}
+        stage["_summary"] = {"forward_ms": q(fwd), "backward_ms": q(bwd), "step_kernels_ms": q(tot)}
     return wall, stage
 
 
@@ -369,6 +375,7 @@ def batched_speedup(torch, steps=5, scale=1.0):
     bb = build_batch(sc, cfg, torch)
     fill_gouts(bb, sc, 4000, torch)
     _, stage = timed_steps(bb, 2, 1, torch)
+    stage.pop("_summary", None)
     best = _graph_time(bb, torch, steps)
     out["graph_ms"] = round(best * 1e3, 3)
     out["graph_config"] = {"tile": cfg.tile, "persistent": cfg.persistent, "queue_chunk": cfg.queue_chunk,
@@ -415,6 +422,7 @@ def main():
     ms_wall = min(ms_eager, ms_graph)
     masked = int(sc.renders[0].mask.sum())
     value = masked / (ms_wall * 1e-3) / 1e6
+    summary = stage.pop("_summary", None)
     dom, roof = roofline(stage, batch, sc, torch, args.tile)
     log("[bench] forward+loss+backward")
     ms_loss, _ = with_loss_time(batch, gt, torch, args.steps)
@@ -443,6 +451,8 @@ def main():
                                "fwd+bwd with fixed dL/dout",
                    "masked_pixels": masked, "tile": args.tile, "pairs": int(batch.status().pairs_needed)},
         "stages_ms": {k: round(v, 4) for k, v in stage.items()},
+        "step_event_ms": summary,
+        "device": {"name": torch.cuda.get_device_name(0), "hip": torch.version.hip, "torch": torch.__version__},
         "with_loss": {"ms_per_step": round(ms_loss, 4), "mpix_s": round(masked / (ms_loss * 1e-3) / 1e6, 2),
                       "note": "same step with the loss kernels in the graph (ground truth: the render of the "
                               "generating scene)"},
