@@ -30,7 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+# the same without packed FP32 (this build disables packed FP32 code generation)
+FP32_SINGLE_ISSUE_TFLOPS = 78.6
 
 # Algorithmic FP32 operations per blended (pixel, Gaussian) pair, counted
 # from the arithmetic of the method (see the kernel docs):
@@ -147,7 +149,8 @@ def roofline(stage, batch, scene, torch, tile):
         return dom, dict(bound="alu", achieved=round(ach, 3), peak=FP32_VECTOR_PEAK_TFLOPS,
                          unit="TFLOP/s", frac=round(ach / FP32_VECTOR_PEAK_TFLOPS, 4), traffic=traffic,
                          kernel=dom, blends_per_launch=int(blends),
-                         flops_per_blend=per)
+                         flops_per_blend=per, peak_single_issue=FP32_SINGLE_ISSUE_TFLOPS,
+                         frac_single_issue=round(ach / FP32_SINGLE_ISSUE_TFLOPS, 4))
     nbytes = algorithmic_bytes(dom, batch, scene)
     ach = nbytes / t / 1e9
     return dom, dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -189,6 +192,21 @@ def algorithmic_bytes(stage, batch, scene):
     if stage == "backward_preprocess":
         return n * P + nrec * 52 + n * P
     return float("nan")
+
+
+def tile_lists(batch, torch):
+    """Per-tile list lengths over tiles holding masked pixels: the workload
+    each compositing workgroup walks, whose spread is the thread-waiting
+    cost the balance-load term targets."""
+    n = int(batch.info.n_tiles)
+    rg = batch.view("ranges", torch.int32, n, 2).cpu().numpy().astype(np.int64)
+    cnt = batch.view("tile_count", torch.int32, n).cpu().numpy()
+    ln = (rg[:, 1] - rg[:, 0])[cnt > 0]
+    if ln.size == 0:
+        return None
+    return {"active_tiles": int(ln.size), "mean": round(float(ln.mean()), 1),
+            "p50": int(np.median(ln)), "p99": int(np.percentile(ln, 99)), "max": int(ln.max()),
+            "max_over_mean": round(float(ln.max() / max(ln.mean(), 1e-9)), 2)}
 
 
 def cpu_baseline(scene, sample=4096, seed=7):
@@ -423,6 +441,7 @@ def main():
     masked = int(sc.renders[0].mask.sum())
     value = masked / (ms_wall * 1e-3) / 1e6
     summary = stage.pop("_summary", None)
+    lists = tile_lists(batch, torch)
     dom, roof = roofline(stage, batch, sc, torch, args.tile)
     log("[bench] forward+loss+backward")
     ms_loss, _ = with_loss_time(batch, gt, torch, args.steps)
@@ -452,6 +471,7 @@ def main():
                    "masked_pixels": masked, "tile": args.tile, "pairs": int(batch.status().pairs_needed)},
         "stages_ms": {k: round(v, 4) for k, v in stage.items()},
         "step_event_ms": summary,
+        "tile_lists": lists,
         "device": {"name": torch.cuda.get_device_name(0), "hip": torch.version.hip, "torch": torch.__version__},
         "with_loss": {"ms_per_step": round(ms_loss, 4), "mpix_s": round(masked / (ms_loss * 1e-3) / 1e6, 2),
                       "note": "same step with the loss kernels in the graph (ground truth: the render of the "
