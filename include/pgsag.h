@@ -179,7 +179,7 @@ typedef struct pgsag_layout {
   uint64_t pair_record; /* uint32 [capacity] sorted pair record ids */
   uint64_t pixel_T;    /* float [n_pixels] final transmittance */
   uint64_t pixel_last; /* int32 [n_pixels] last blended pair index, -1 none */
-  uint64_t grad2d;     /* float [n_records][16] 2D gradients */
+  uint64_t grad2d;     /* float [n_records][16] per-record pixel sums of the backward compositing pass */
   uint64_t end;
 } pgsag_layout;
 

@@ -428,13 +428,17 @@ __device__ void backward_tile(const void *__restrict__ desc, const Header &h, vo
         // dalpha/dq = -alpha / 2 (zero on the clamped side of alpha_max)
         const float gate = (contrib && raw <= amax) ? dLda : 0.f;
         const float dx = fx - r0.x, dy = fy - r0.y;
-        const float dLdq = -0.5f * a * gate;
-        v[G_O] = gate * a * r3.y;
-        v[G_MX] = -2.f * dLdq * (r0.z * dx + r0.w * dy);
-        v[G_MY] = -2.f * dLdq * (r0.w * dx + r1.x * dy);
-        v[G_CA] = dLdq * dx * dx;
-        v[G_CB] = 2.f * dLdq * dx * dy;
-        v[G_CC] = dLdq * dy * dy;
+        // moments only: the record's conic and 1/o are applied once per
+        // record after the reduction (see G2Field)
+        const float ag = a * gate;
+        const float dLdq = -0.5f * ag;
+        const float qx = dLdq * dx, qy = dLdq * dy;
+        v[G_SO] = ag;
+        v[G_SX] = qx;
+        v[G_SY] = qy;
+        v[G_SXX] = qx * dx;
+        v[G_SXY] = qx * dy;
+        v[G_SYY] = qy * dy;
         v[13] = v[14] = v[15] = 0.f;
         const float tot = wave_reduce16(v);
         const int which = (lane >> 2) & 15;

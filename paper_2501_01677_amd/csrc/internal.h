@@ -34,9 +34,14 @@ enum RecField {
   R_LOG2O = 15                     // log2(opacity)
 };
 
-// 2D-gradient slot layout (floats).
+// 2D-gradient slot layout (floats): per record, sums over the blended
+// pixels p of dL/dq_p times the offset moments (d = p - mean2d), of
+// dL/dalpha_p alpha_p on the unclamped side, and of the feature gradients.
+// The record's conic (a, b, c) and 1/o are applied once per record by the
+// backward projection:  dL/dmean = -2 [a b; b c] (S_x, S_y),
+// dL/d(a, b, c) = (S_xx, 2 S_xy, S_yy),  dL/do = S_o / o.
 enum G2Field {
-  G_MX = 0, G_MY = 1, G_CA = 2, G_CB = 3, G_CC = 4, G_O = 5,
+  G_SX = 0, G_SY = 1, G_SXX = 2, G_SXY = 3, G_SYY = 4, G_SO = 5,
   G_R = 6, G_G = 7, G_B = 8, G_NX = 9, G_NY = 10, G_NZ = 11, G_D = 12
 };
 

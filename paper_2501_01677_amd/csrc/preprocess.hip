@@ -386,8 +386,14 @@ __global__ void __launch_bounds__(256) backward_preprocess_kernel(const void *__
     const uint64_t r = rd.record_offset + (uint64_t)i;
     if (nact[r] == 0) continue;
     const float4 a0 = g2[r * 4 + 0], a1 = g2[r * 4 + 1], a2 = g2[r * 4 + 2], a3 = g2[r * 4 + 3];
-    const float d_mx = a0.x, d_my = a0.y, d_ca = a0.z, d_cb = a0.w;
-    const float d_cc = a1.x, d_o = a1.y;
+    // the pixel sums of the compositing pass times the record's conic and
+    // 1/o (as blended: the record's stored values)
+    const float4 q0 = rec4[r * 4 + 0];
+    const float inv_o = rec4[r * 4 + 3].y;
+    const float d_mx = -2.f * (q0.z * a0.x + q0.w * a0.y);
+    const float d_my = -2.f * (q0.w * a0.x + rec4[r * 4 + 1].x * a0.y);
+    const float d_ca = a0.z, d_cb = 2.f * a0.w;
+    const float d_cc = a1.x, d_o = a1.y * inv_o;
     const float d_col[3] = {a1.z, a1.w, a2.x};
     float d_n[3] = {a2.y, a2.z, a2.w};
     const float d_d = a3.x;
