@@ -102,3 +102,66 @@ def test_facade_forward_sampled_pixels():
     assert not bad, bad
     assert check_unmasked_zero(gpu, rd.mask)
     assert ref["n_contrib"].mean() > 5
+
+
+def test_batched_subregions_sampled_pixels_and_crop_gradients():
+    """The 16 sub-region x 4 view batch (5.4M Gaussians, 1600x1200) in one
+    persistent launch with 8-tile queue chunks (the configuration the
+    autotuner picks for it): 256 seeded pixels of six renders against the
+    oracle, and the gradient of a loss on one 32x32 crop of the largest
+    sub-region's render (every other render gets dL/dout = 0)."""
+    print("[case] batched 16x4 samples + crop gradient", flush=True)
+    sc = scenes.config4()
+    b = device_scene(sc, RenderConfig(tile=16, persistent=True, queue_chunk=8, workgroups_per_cu=8))
+    b.forward()
+    b.fit_capacity(1.1)
+    b.forward(check_overflow=False)
+    torch.cuda.synchronize()
+    big = int(np.argmax([s.n for s in sc.sets]))
+    rds = [r for r, rd in enumerate(sc.renders) if rd.set_index == big][:2] + [0, 13, 38, 63]
+    for r in rds:
+        rd = sc.renders[r]
+        pix = scenes.sample_pixels(23 + r, rd, 256)
+        ref = oc.render(sc.sets[rd.set_index], rd.camera, rd.mask, CFG, pixels=pix)
+        gpu = outputs_numpy(b, r)
+        bad = compare_images(gpu, ref, rd)
+        assert not bad, (r, bad)
+    r = rds[0]
+    rd = sc.renders[r]
+    gs = sc.sets[rd.set_index]
+    H, W = rd.camera.height, rd.camera.width
+    (v0, u0, s), = scenes.crop_windows(29, rd, count=1, size=32)
+    sel = np.zeros((H, W), bool)
+    sel[v0:v0 + s, u0:u0 + s] = True
+    sel &= rd.mask.astype(bool)
+    cp = np.argwhere(sel)
+    fw = oc.render(gs, rd.camera, rd.mask, CFG, pixels=cp)
+    sel[cp[fw["unsafe"], 0], cp[fw["unsafe"], 1]] = False
+    gouts = []
+    for q, rq in enumerate(sc.renders):
+        if q == r:
+            g = scenes.grad_outputs(6, rq, scale={"depth": 0.05})
+            g = {k: (v * sel).astype(np.float32) for k, v in g.items()}
+            gsel = g
+        else:
+            g = {k: np.zeros_like(v) for k, v in scenes.grad_outputs(0, rq).items()}
+        gouts.append({k: torch.from_numpy(v).cuda() for k, v in g.items()})
+    b.backward(gouts)
+    torch.cuda.synchronize()
+    ref = oc.render_grad(gs, rd.camera, rd.mask, CFG, gsel, pixels=np.argwhere(sel))
+    dec = op.decide(gs, rd.camera, CFG)
+    ex = (dec.colour_min < 1e-5) | (dec.clamp_margin < 1e-5) | (dec.flip_margin < 1e-5)
+    touched = np.zeros(gs.n, bool)
+    for k in PARAMS:
+        got = b.grads[rd.set_index][k].cpu().numpy()
+        ok, ratio, rel = grad_tolerance_check(got, ref[k], exclude=ex)
+        assert ok, (k, ratio, rel)
+        touched |= np.abs(ref[k]).reshape(-1, gs.n).max(0) > 0
+    assert touched.sum() > 20
+    for k in PARAMS:
+        got = b.grads[rd.set_index][k].cpu().numpy().reshape(-1, gs.n)
+        assert np.all(got[:, ~touched & ~ex] == 0), k
+    # the other sub-regions received no upstream gradient at all
+    for s_idx in range(len(sc.sets)):
+        if s_idx != rd.set_index:
+            assert not torch.any(b.grads[s_idx]["means"]), s_idx
