@@ -193,7 +193,9 @@ __device__ void forward_tile(const void *__restrict__ desc, const Header &h, voi
   const DevRender &rd = *g.rd;
   const int W = rd.cam.W;
   const uint64_t pix = (uint64_t)g.py * W + g.px;
-  const bool masked = g.inside && (rd.mask == nullptr || rd.mask[pix] != 0);
+  // a tile without masked pixels only writes its zeros (no mask reads)
+  const bool active = ws_ptr<const uint32_t>(ws, h.ws.tile_count)[tile] != 0;
+  const bool masked = active && g.inside && (rd.mask == nullptr || rd.mask[pix] != 0);
   const uint2 rg = ws_ptr<uint2>(ws, h.ws.ranges)[tile];
   const float4 *rec4 = ws_ptr<float4>(ws, h.ws.rec);
   const float amax = h.cfg.alpha_max, tmin = h.cfg.t_min;
@@ -325,6 +327,8 @@ __device__ void backward_tile(const void *__restrict__ desc, const Header &h, vo
                               float4 (*srec)[4], float4 *sabc, uint32_t *sid, Entry (*lists)[batch_of<T>()],
                               int *smax, const uint32_t *__restrict__ vals) {
   constexpr int NT = batch_of<T>();
+  // nothing to do for a tile without masked pixels (uniform over the workgroup)
+  if (ws_ptr<const uint32_t>(ws, h.ws.tile_count)[tile] == 0) return;
   TileGeom g;
   tile_geom<T>(desc, h, tile, g);
   const DevRender &rd = *g.rd;
