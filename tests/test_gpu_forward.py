@@ -125,12 +125,15 @@ def _emit_reference_inputs(b, sc, tile):
     return grids, offs, np.concatenate(active)
 
 
-@pytest.mark.parametrize("n,seed", [(300, 1), (40_000, 2)])
-def test_binning_bit_exact_on_synthetic_rects(n, seed):
-    print(f"[case] binning n={n}", flush=True)
+@pytest.mark.parametrize("n,seed,wide", [(300, 1, False), (40_000, 2, False), (3_000, 3, True)])
+def test_binning_bit_exact_on_synthetic_rects(n, seed, wide):
+    """wide: rectangles up to 48 x 14 tiles, so emission also takes its path
+    for rectangles too large to stage (more than 8 rows or 32 columns)."""
+    print(f"[case] binning n={n} wide={wide}", flush=True)
     tile = 16
-    sc = scenes.small_scene(50 + seed, n=n, width=300, height=200, sh_degree=0, n_views=2)
-    b = device_scene(sc, RenderConfig(tile=tile), pair_capacity=64 * n)
+    W, H = (1100, 300) if wide else (300, 200)
+    sc = scenes.small_scene(50 + seed, n=n, width=W, height=H, sh_degree=0, n_views=2)
+    b = device_scene(sc, RenderConfig(tile=tile), pair_capacity=(700 if wide else 64) * n)
     rng = np.random.default_rng(seed)
     nrec = int(b.info.n_records)
     grids, offs, active = _emit_reference_inputs(b, sc, tile)
@@ -141,8 +144,8 @@ def test_binning_bit_exact_on_synthetic_rects(n, seed):
         k = int(m.sum())
         x0 = rng.integers(0, tx, k)
         y0 = rng.integers(0, ty, k)
-        x1 = np.minimum(tx, x0 + rng.integers(0, 5, k))
-        y1 = np.minimum(ty, y0 + rng.integers(0, 4, k))
+        x1 = np.minimum(tx, x0 + rng.integers(0, 49 if wide else 5, k))
+        y1 = np.minimum(ty, y0 + rng.integers(0, 15 if wide else 4, k))
         rects[m] = np.stack([x0, y0, x1, y1], 1)
     depth = rng.integers(0, 2000, nrec).astype(np.uint32) * np.uint32(1 << 20)  # ties and high bits
     depth[::7] = rng.integers(0, 2 ** 32, len(depth[::7]), dtype=np.uint64).astype(np.uint32)
