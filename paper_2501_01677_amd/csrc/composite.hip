@@ -19,9 +19,11 @@
 // The backward pass walks the same list back to front from the tile's
 // largest last-blended index, recovering each pixel's transmittance before a
 // fragment as T_i = T_{i+1} / (1 - alpha_i) from the saved final T, keeps the
-// suffix sums of the blended features, and reduces the 13 per-fragment 2D
-// gradients across the wave (VALU lane exchanges only) before one float
-// atomic per value per wave (13 lanes of one instruction, one cache line).
+// suffix sums of the blended features, and buffers each contributing
+// fragment's two per-pixel weights (alpha T and dL/dq) in LDS.  Every 8
+// records the wave reduces them over its 64 pixels as one small matrix
+// product on the matrix cores (the 13 per-record sums: 7 feature gradients
+// and 6 moments of dL/dq), then adds each sum with one float atomic.
 // It builds its lists with the same code as the forward pass, so it takes
 // the forward's decisions.
 //
@@ -286,46 +288,100 @@ __device__ __forceinline__ float dpp(float x) {
   return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), CTRL, 0xf, 0xf, false));
 }
 
-// Sum of v[0..15] over the 64 lanes of a wave by recursive halving, using
-// only VALU lane exchanges: permlane32/16 swaps for lane distance 32 and 16,
-// DPP row rotate by 8, half-row mirror and quad permutations below that.
-// Each step keeps half of the values per lane and adds the partner lane's
-// copy of them.  Afterwards lane L holds the total of value (L >> 2) & 15.
-__device__ __forceinline__ float wave_reduce16(const float v[16]) {
-  const int lane = threadIdx.x & 63;
-  float w8[8], w4[4], w2[2];
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Per-wave LDS of the backward pass's per-record reduction.  For up to 8
+// contributing records the wave buffers every pixel's colour weight
+// w = alpha T (rows 0..7) and dL/dq (rows 8..15); columns are the wave's 64
+// pixels, stored in 4-float granules XOR-swizzled by (row & 7) so that the
+// matrix-layout reads of a flush spread over the banks.  Record slot b's id
+// and centre offset from the block centre are kept in registers of lane b.
+struct WaveAcc {
+  float a[16][64];
+};
+
+// Feature slot n of a pixel in the per-record reduction: the 7 output
+// gradients (slots 0..6), then monomials of the pixel's offset (x, y) from
+// the block centre: slot 8: 1, 9: x, 10: y, 11: xy, 12: x^2, 13: y^2,
+// 14: x, 15: y (slot 7 is zero).
+__device__ __forceinline__ float feature_slot(int n, float g, float x, float y) {
+  const int ex = (n == 9 || n == 11 || n == 14) ? 1 : (n == 12 ? 2 : 0);
+  const int ey = (n == 10 || n == 11 || n == 15) ? 1 : (n == 13 ? 2 : 0);
+  const float px = ex == 0 ? 1.f : (ex == 1 ? x : x * x);
+  const float py = ey == 0 ? 1.f : (ey == 1 ? y : y * y);
+  return n < 7 ? g : (n == 7 ? 0.f : px * py);
+}
+
+// Reduces the buffered records over the wave's pixels on the matrix cores:
+// C = F^T A^T with A the 16 x 64 buffer and F[p][n] = feature slot n of
+// pixel p, in sixteen 16x16x4 FP32 MFMA steps (pixel p of step 4t + j and
+// lane group kk being 16t + 4kk + j; bf holds the F operands).  Lane
+// (j, kk) receives slots 4kk..4kk+3 of buffered row j: for rows 0..7 (colour
+// weights of record j) slots 0..6 are its 7 feature gradients; for rows
+// 8..15 (dL/dq of record j - 8) slots 8..13 are the raw moments R_1, R_x,
+// R_y, R_xy, R_xx, R_yy about the block centre, which are moved to the
+// record's centre with its offset (cx, cy) from the block centre:
+//   sum u dx = R_x - cx R_1,  sum u dx dy = R_xy - cx R_y - cy R_x + cx cy R_1,
+//   sum u dx^2 = R_xx - 2 cx R_x + cx^2 R_1  (lane group 3 takes R_1 from
+// group 2), and sum(alpha gate) = -2 R_1.  Every valid nonzero value of the
+// first nb records is then added to its slot.
+__device__ __forceinline__ void flush_records(WaveAcc &acc, int nb, const float (&bf)[16], uint32_t fields,
+                                              uint32_t isid, float icx, float icy, float *__restrict__ g2) {
+  const int lane = threadIdx.x & 63, j = lane & 15, kk = lane >> 4;
+  floatx4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    // lanes 0..31 keep v[s], lanes 32..63 keep v[8 + s]
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[s]), __float_as_uint(v[8 + s]), false, false);
-    w8[s] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  for (int t = 0; t < 4; ++t) {
+    const float4 av = *reinterpret_cast<const float4 *>(&acc.a[j][((4 * t + kk) ^ (j & 7)) << 2]);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * t + 0], av.x, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * t + 1], av.y, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * t + 2], av.z, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * t + 3], av.w, c, 0, 0, 0);
   }
+  const int b = j & 7;  // buffered record
+  const float cx = __shfl(icx, b, 64), cy = __shfl(icy, b, 64);
+  // lane group 3 needs R_1 (slot 8, held in c[0] by group 2)
+  const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(c[0]), __float_as_uint(c[0]), false, false);
+  const float r1 = __uint_as_float(sw[0]);
+  // group 2 holds R_1, R_x, R_y, R_xy; group 3 R_xx, R_yy (then R_x, R_y);
+  // groups 0 and 1 pass through (branch-free, per-lane 0/1 factors)
+  const float s2 = kk == 2 ? 1.f : 0.f, s3 = kk == 3 ? 1.f : 0.f;
+  const float cx2 = s2 * cx, cy2 = s2 * cy, cx3 = s3 * cx, cy3 = s3 * cy;
+  float o[4];
+  o[0] = fmaf(-3.f * s2, c[0], c[0]) + cx3 * fmaf(cx, r1, -2.f * c[2]);
+  o[1] = c[1] - cx2 * c[0] + cy3 * fmaf(cy, r1, -2.f * c[3]);
+  o[2] = c[2] - cy2 * c[0];
+  o[3] = c[3] - cx2 * fmaf(-cy, c[0], c[2]) - cy2 * c[1];
+  // The sums go out record-major: staged as 8 rows of 16 fields in the
+  // buffer (free once read), then each atomic instruction covers 4 records,
+  // so that a record's 13 additions fall in one instruction and cache line.
+  // Slots of the other row type go to the unused field 15.
+  float *stage = &acc.a[0][0];
+  const uint32_t fl = ((kk < 2) == (j < 8)) ? fields : 0x0f0f0f0fu;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    // lanes with bit 4 clear keep w8[s], the others w8[4 + s]
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w8[s]), __float_as_uint(w8[4 + s]), false, false);
-    w4[s] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  for (int r = 0; r < 4; ++r) stage[b * 16 + ((fl >> (8 * r)) & 0xffu)] = o[r];
+  __builtin_amdgcn_wave_barrier();
+  const int rb = lane >> 4, f = lane & 15;
+  const float v0 = stage[rb * 16 + f], v1 = stage[(4 + rb) * 16 + f];
+  const uint32_t id0 = __shfl(isid, rb, 64), id1 = __shfl(isid, 4 + rb, 64);
+  if (f < 13) {
+    if (rb < nb && v0 != 0.f) unsafeAtomicAdd(g2 + (uint64_t)id0 * kG2 + f, v0);
+    if (4 + rb < nb && v1 != 0.f) unsafeAtomicAdd(g2 + (uint64_t)id1 * kG2 + f, v1);
   }
-  {
-    const bool hi = lane & 8;  // partner: lane ^ 8 (row rotate by 8)
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const float mine = hi ? w4[2 + s] : w4[s];
-      const float send = hi ? w4[s] : w4[2 + s];
-      w2[s] = mine + dpp<0x128>(send);
-    }
-  }
-  const bool hi = lane & 4;  // partner: mirrored lane in the same 8-lane half row
-  float x = (hi ? w2[1] : w2[0]) + dpp<0x141>(hi ? w2[0] : w2[1]);
-  x += dpp<0x4e>(x);  // quad permutation: lane ^ 2
-  x += dpp<0xb1>(x);  // quad permutation: lane ^ 1
-  return x;
+}
+
+// G2 fields of this lane's output slots 4kk..4kk+3 in flush_records, one
+// byte each (15: no output).
+__device__ __forceinline__ uint32_t slot_fields(int kk) {
+  return kk == 0 ? (G_R | G_G << 8 | G_B << 16 | (uint32_t)G_NX << 24)
+         : kk == 1 ? (G_NY | G_NZ << 8 | G_D << 16 | 15u << 24)
+         : kk == 2 ? (G_SO | G_SX << 8 | G_SY << 16 | (uint32_t)G_SXY << 24)
+                   : (G_SXX | G_SYY << 8 | 0x0f0fu << 16);
 }
 
 template <int T>
-__device__ void backward_tile(const void *__restrict__ desc, const Header &h, void *__restrict__ ws, uint32_t tile,
+__device__ __forceinline__ void backward_tile(const void *__restrict__ desc, const Header &h, void *__restrict__ ws, uint32_t tile,
                               float4 (*srec)[4], float4 *sabc, uint32_t *sid, Entry (*lists)[batch_of<T>()],
-                              int *smax, const uint32_t *__restrict__ vals) {
+                              WaveAcc *accs, int *smax, const uint32_t *__restrict__ vals) {
   constexpr int NT = batch_of<T>();
   // nothing to do for a tile without masked pixels (uniform over the workgroup)
   if (ws_ptr<const uint32_t>(ws, h.ws.tile_count)[tile] == 0) return;
@@ -394,6 +450,28 @@ __device__ void backward_tile(const void *__restrict__ desc, const Header &h, vo
   if (maxlast < (int)rg.x) return;  // uniform: no pixel blended anything
   const uint32_t end = (uint32_t)maxlast + 1;
   const int lane = threadIdx.x & 63;
+  // the features of the reduction (see flush_records), fixed for the tile:
+  // the output gradients of the other pixels come through the wave's buffer
+  WaveAcc &acc = accs[threadIdx.x >> 6];
+#pragma unroll
+  for (int c = 0; c < 7; ++c) acc.a[c][lane] = gch[c];
+  __builtin_amdgcn_wave_barrier();
+  float bf[16];
+  {
+    const int n = lane & 15, kk = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int p = ((i >> 2) << 4) + (kk << 2) + (i & 3);
+      bf[i] = feature_slot(n, acc.a[n < 7 ? n : 0][p], (float)(p & 7) - 3.5f, (float)(p >> 3) - 3.5f);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  const float bcx = g.ox + 3.5f, bcy = g.oy + 3.5f;  // block centre
+  const uint32_t fields = slot_fields(lane >> 4);
+  const int sw = lane & 3, gr = lane >> 2;
+  int nb = 0;  // buffered records (uniform)
+  uint32_t isid = 0u;  // lane b < nb: id and centre offset of buffered record b
+  float icx = 0.f, icy = 0.f;
   for (int64_t bend = end; bend > (int64_t)rg.x; bend -= NT) {
     const uint32_t bstart = (uint32_t)max((int64_t)rg.x, bend - NT);
     const int cnt = (int)((uint32_t)bend - bstart);
@@ -402,54 +480,61 @@ __device__ void backward_tile(const void *__restrict__ desc, const Header &h, vo
     __syncthreads();
     if (__ballot(last >= (int32_t)bstart) != 0ull) {
       const int len = build_list(srec, cnt, g.ox, g.oy, l2min, list);
+      // back to front; the next entry and its coefficients are loaded while
+      // this one is evaluated
+      Entry e = list[len > 0 ? len - 1 : 0];
+      float4 abc = sabc[len > 0 ? e.k : 0];
       for (int t = len - 1; t >= 0; --t) {
-        const Entry cur = list[t];
-        const int32_t idx = (int32_t)(bstart + cur.k);
+        const Entry en = list[t > 0 ? t - 1 : 0];
+        const float4 abcn = sabc[en.k];
+        const int32_t idx = (int32_t)(bstart + e.k);
         // Every lane evaluates the fragment (the wave executes it anyway when
         // any lane contributes); lanes that do not contribute get zero weight.
-        const float ex = lane_exponent(cur, sabc[cur.k], g.L);
+        const float ex = lane_exponent(e, abc, g.L);
         const bool contrib = idx <= last && ex >= l2min;
-        if (__ballot(contrib) == 0ull) continue;
-        const float raw = __builtin_amdgcn_exp2f(ex);
-        const float a = __builtin_amdgcn_fmed3f(raw, 0.f, amax);  // min(raw, amax), raw >= 0
-        const float4 r0 = srec[cur.k][0], r1 = srec[cur.k][1], r2 = srec[cur.k][2], r3 = srec[cur.k][3];
-        const float f[7] = {r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
-        const float iom = __builtin_amdgcn_rcpf(1.f - a);  // 1 / (1 - alpha), alpha <= 0.99
-        const float Tp = Tr * iom;
-        const float w = contrib ? a * Tp : 0.f;
-        // dL/dalpha = sum_c g_c (T f_c - S_c / (1 - alpha)) + g_alpha T_final / (1 - alpha)
-        float Gf = 0.f;
-        float v[16];
+        if (__ballot(contrib) != 0ull) {
+          const float4 r0 = srec[e.k][0], r1 = srec[e.k][1], r2 = srec[e.k][2], r3 = srec[e.k][3];
+          const uint32_t rid = sid[e.k];
+          const float raw = __builtin_amdgcn_exp2f(ex);
+          const float a = __builtin_amdgcn_fmed3f(raw, 0.f, amax);  // min(raw, amax), raw >= 0
+          const float f[7] = {r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
+          const float iom = __builtin_amdgcn_rcpf(1.f - a);  // 1 / (1 - alpha), alpha <= 0.99
+          const float Tp = Tr * iom;
+          const float w = contrib ? a * Tp : 0.f;
+          // dL/dalpha = sum_c g_c (T f_c - S_c / (1 - alpha)) + g_alpha T_final / (1 - alpha)
+          float Gf = 0.f;
 #pragma unroll
-        for (int c = 0; c < 7; ++c) {
-          Gf = fmaf(gch[c], f[c], Gf);
-          v[6 + c] = w * gch[c];
+          for (int c = 0; c < 7; ++c) Gf = fmaf(gch[c], f[c], Gf);
+          const float dLda = Tp * Gf + (ga * Tf - GS) * iom;
+          GS = contrib ? fmaf(w, Gf, GS) : GS;
+          Tr = contrib ? Tp : Tr;
+          // alpha = o G with G = exp(-q/2): dalpha/do = G = alpha / o,
+          // dalpha/dq = -alpha / 2 (zero on the clamped side of alpha_max)
+          const float gate = (contrib && raw <= amax) ? dLda : 0.f;
+          // buffer w and dL/dq; the record's sums over the wave's pixels are
+          // formed on the matrix cores once 8 records are buffered
+          const int col = ((gr ^ nb) << 2) | sw;
+          acc.a[nb][col] = w;
+          acc.a[8 + nb][col] = -0.5f * a * gate;
+          const bool mine = lane == nb;
+          isid = mine ? rid : isid;
+          icx = mine ? r0.x - bcx : icx;
+          icy = mine ? r0.y - bcy : icy;
+          if (++nb == 8) {
+            __builtin_amdgcn_wave_barrier();
+            flush_records(acc, 8, bf, fields, isid, icx, icy, g2);
+            __builtin_amdgcn_wave_barrier();
+            nb = 0;
+          }
         }
-        const float dLda = Tp * Gf + (ga * Tf - GS) * iom;
-        GS = contrib ? fmaf(w, Gf, GS) : GS;
-        Tr = contrib ? Tp : Tr;
-        // alpha = o G with G = exp(-q/2): dalpha/do = G = alpha / o,
-        // dalpha/dq = -alpha / 2 (zero on the clamped side of alpha_max)
-        const float gate = (contrib && raw <= amax) ? dLda : 0.f;
-        const float dx = fx - r0.x, dy = fy - r0.y;
-        // moments only: the record's conic and 1/o are applied once per
-        // record after the reduction (see G2Field)
-        const float ag = a * gate;
-        const float dLdq = -0.5f * ag;
-        const float qx = dLdq * dx, qy = dLdq * dy;
-        v[G_SO] = ag;
-        v[G_SX] = qx;
-        v[G_SY] = qy;
-        v[G_SXX] = qx * dx;
-        v[G_SXY] = qx * dy;
-        v[G_SYY] = qy * dy;
-        v[13] = v[14] = v[15] = 0.f;
-        const float tot = wave_reduce16(v);
-        const int which = (lane >> 2) & 15;
-        if ((lane & 3) == 0 && which < 13 && tot != 0.f)
-          unsafeAtomicAdd(g2 + (uint64_t)sid[cur.k] * kG2 + which, tot);
+        e = en;
+        abc = abcn;
       }
     }
+  }
+  if (nb > 0) {
+    __builtin_amdgcn_wave_barrier();
+    flush_records(acc, nb, bf, fields, isid, icx, icy, g2);
   }
 }
 
@@ -484,19 +569,22 @@ __global__ void __launch_bounds__(T *T) forward_kernel(const void *__restrict__ 
   }
 }
 
+// At most 4 of these workgroups fit a CU's LDS: registers are sized for 4
+// waves per SIMD.
 template <int T>
-__global__ void __launch_bounds__(T *T) backward_kernel(const void *__restrict__ desc, void *__restrict__ ws,
+__global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(4))) backward_kernel(const void *__restrict__ desc, void *__restrict__ ws,
                                                          const uint32_t *__restrict__ vals) {
   constexpr int NT = batch_of<T>();
   __shared__ float4 srec[NT][4];
   __shared__ float4 sabc[NT];
   __shared__ uint32_t sid[NT];
   __shared__ Entry lists[T * T / 64][NT];
+  __shared__ WaveAcc accs[T * T / 64];
   __shared__ int smax;
   __shared__ uint32_t s_item;
   const Header &h = *header(desc);
   if (!h.cfg.persistent) {
-    backward_tile<T>(desc, h, ws, blockIdx.x, srec, sabc, sid, lists, &smax, vals);
+    backward_tile<T>(desc, h, ws, blockIdx.x, srec, sabc, sid, lists, accs, &smax, vals);
     return;
   }
   uint32_t *ctr = ws_ptr<uint32_t>(ws, h.ws.status) + S_QUEUE_BWD;
@@ -512,7 +600,7 @@ __global__ void __launch_bounds__(T *T) backward_kernel(const void *__restrict__
     const uint32_t stop = min(ntiles, base + chunk);
     for (uint32_t it = base; it < stop; ++it) {
       __syncthreads();
-      backward_tile<T>(desc, h, ws, queue[it], srec, sabc, sid, lists, &smax, vals);
+      backward_tile<T>(desc, h, ws, queue[it], srec, sabc, sid, lists, accs, &smax, vals);
     }
   }
 }
