@@ -295,7 +295,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // w = alpha T (rows 0..7) and dL/dq (rows 8..15); columns are the wave's 64
 // pixels, stored in 4-float granules XOR-swizzled by (row & 7) so that the
 // matrix-layout reads of a flush spread over the banks.  Record slot b's id
-// and centre offset from the block centre are kept in registers of lane b.
+// and 2D mean are kept in registers of lane b.
 struct WaveAcc {
   float a[16][64];
 };
@@ -326,7 +326,8 @@ __device__ __forceinline__ float feature_slot(int n, float g, float x, float y) 
 // group 2), and sum(alpha gate) = -2 R_1.  Every valid nonzero value of the
 // first nb records is then added to its slot.
 __device__ __forceinline__ void flush_records(WaveAcc &acc, int nb, const float (&bf)[16], uint32_t fields,
-                                              uint32_t isid, float icx, float icy, float *__restrict__ g2) {
+                                              uint32_t isid, float icx, float icy, float bcx, float bcy,
+                                              float *__restrict__ g2) {
   const int lane = threadIdx.x & 63, j = lane & 15, kk = lane >> 4;
   floatx4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -338,7 +339,7 @@ __device__ __forceinline__ void flush_records(WaveAcc &acc, int nb, const float 
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * t + 3], av.w, c, 0, 0, 0);
   }
   const int b = j & 7;  // buffered record
-  const float cx = __shfl(icx, b, 64), cy = __shfl(icy, b, 64);
+  const float cx = __shfl(icx, b, 64) - bcx, cy = __shfl(icy, b, 64) - bcy;
   // lane group 3 needs R_1 (slot 8, held in c[0] by group 2)
   const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(c[0]), __float_as_uint(c[0]), false, false);
   const float r1 = __uint_as_float(sw[0]);
@@ -468,9 +469,8 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
   __builtin_amdgcn_wave_barrier();
   const float bcx = g.ox + 3.5f, bcy = g.oy + 3.5f;  // block centre
   const uint32_t fields = slot_fields(lane >> 4);
-  const int sw = lane & 3, gr = lane >> 2;
   int nb = 0;  // buffered records (uniform)
-  uint32_t isid = 0u;  // lane b < nb: id and centre offset of buffered record b
+  uint32_t isid = 0u;  // lane b < nb: id and 2D mean of buffered record b
   float icx = 0.f, icy = 0.f;
   for (int64_t bend = end; bend > (int64_t)rg.x; bend -= NT) {
     const uint32_t bstart = (uint32_t)max((int64_t)rg.x, bend - NT);
@@ -513,16 +513,17 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
           const float gate = (contrib && raw <= amax) ? dLda : 0.f;
           // buffer w and dL/dq; the record's sums over the wave's pixels are
           // formed on the matrix cores once 8 records are buffered
-          const int col = ((gr ^ nb) << 2) | sw;
+          // granule (lane >> 2) of row nb lands at (lane >> 2) ^ nb
+          const int col = lane ^ (nb << 2);
           acc.a[nb][col] = w;
           acc.a[8 + nb][col] = -0.5f * a * gate;
           const bool mine = lane == nb;
           isid = mine ? rid : isid;
-          icx = mine ? r0.x - bcx : icx;
-          icy = mine ? r0.y - bcy : icy;
+          icx = mine ? r0.x : icx;
+          icy = mine ? r0.y : icy;
           if (++nb == 8) {
             __builtin_amdgcn_wave_barrier();
-            flush_records(acc, 8, bf, fields, isid, icx, icy, g2);
+            flush_records(acc, 8, bf, fields, isid, icx, icy, bcx, bcy, g2);
             __builtin_amdgcn_wave_barrier();
             nb = 0;
           }
@@ -534,7 +535,7 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
   }
   if (nb > 0) {
     __builtin_amdgcn_wave_barrier();
-    flush_records(acc, nb, bf, fields, isid, icx, icy, g2);
+    flush_records(acc, nb, bf, fields, isid, icx, icy, bcx, bcy, g2);
   }
 }
 
