@@ -315,7 +315,17 @@ def train_step_bench(torch, steps):
     start = [gaussians_to_device(scenes.perturbed(55, s)) for s in sc.sets]
     renders = [dict(set=rd.set_index, camera=rd.camera, mask=torch.from_numpy(np.ascontiguousarray(rd.mask)).cuda())
                for rd in sc.renders]
-    t = Trainer(start, renders, gt, RenderConfig(tile=16), LossConfig(lambda_load=0.41), lr=1e-3)
+    # backward reduction picked by timing both on this batch shape
+    from paper_2501_01677_amd.autotune import Autotuner
+    tb = build_batch(sc, RenderConfig(tile=16), torch)
+    fill_gouts(tb, sc, 5000, torch)
+    gouts = [{k: v.clone() for k, v in g.items()} for g in tb.gout]
+    tuner = Autotuner(candidates=(RenderConfig(tile=16), RenderConfig(tile=16, bwd_reduce=1)), steps=2)
+    cfg, times = tuner.best(tb.sets, tb.renders, gouts)
+    del tb.workspace
+    del tb, gouts
+    torch.cuda.empty_cache()
+    t = Trainer(start, renders, gt, cfg, LossConfig(lambda_load=0.41), lr=1e-3)
     del start
     t.fit(1.2)
     for _ in range(2):
@@ -335,7 +345,8 @@ def train_step_bench(torch, steps):
     loss = t.loss_out.cpu().numpy().tolist()
     res = dict(workload="10M Gaussians SH3, 2 views 5472x3648, box-silhouette masks; forward + loss "
                         "(masked L1 + 0.01 boundary-aware normal L1, 0.41 balance-load) + backward + Adam",
-               ms_per_step=round(dt * 1e3, 3), masked_pixels=masked,
+               ms_per_step=round(dt * 1e3, 3), masked_pixels=masked, bwd_reduce=cfg.bwd_reduce,
+               reduce_ms={k: round(v * 1e3, 3) for k, v in times.items()},
                mpix_s=round(masked / dt / 1e6, 1), params=int(t.P.numel()),
                pairs=int(t.batch.status().pairs_needed), loss=[[round(x, 6) for x in r] for r in loss])
     del t
@@ -346,16 +357,29 @@ def train_step_bench(torch, steps):
 def batched_speedup(torch, steps=5, scale=1.0):
     """Batched graph-captured step (autotuned launch configuration) vs the
     per-sub-region launch loop on 16 sub-regions x 4 views at 1600x1200 (one
-    Batch per sub-region, 16x16 tiles, launched one after another, no
-    graph)."""
+    Batch per sub-region, 16x16 tiles and the tuned backward reduction,
+    launched one after another, no graph)."""
     import scenes
     from paper_2501_01677_amd.raster import RenderConfig
     sc = scenes.config4(scale=scale)
+    masked = sum(int(rd.mask.sum()) for rd in sc.renders)
+    # one batch for all sub-regions and views; the launch configuration is
+    # picked by the autotuner (captured fwd+bwd step timed per candidate)
+    from paper_2501_01677_amd.autotune import Autotuner
+    bb = build_batch(sc, RenderConfig(tile=16), torch)
+    fill_gouts(bb, sc, 4000, torch)
+    gouts = [{k: v.clone() for k, v in g.items()} for g in bb.gout]
+    tuner = Autotuner(steps=steps)
+    cfg, times = tuner.best(bb.sets, bb.renders, gouts)
+    del bb.workspace
+    del bb, gouts
+    torch.cuda.empty_cache()
+    # the loop: one Batch per sub-region with the same backward reduction
     loops = []
     for k, s in enumerate(sc.sets):
         sub = scenes.Scene([s], [scenes.Render(0, rd.camera, rd.mask) for rd in sc.renders
                                  if rd.set_index == k])
-        b = build_batch(sub, RenderConfig(tile=16), torch)
+        b = build_batch(sub, RenderConfig(tile=16, bwd_reduce=cfg.bwd_reduce), torch)
         fill_gouts(b, sub, 4000 + k, torch)
         b.forward()
         b.fit_capacity(1.1)
@@ -377,18 +401,6 @@ def batched_speedup(torch, steps=5, scale=1.0):
     torch.cuda.empty_cache()
     out = dict(workload="16 sub-regions x 4 views, 1600x1200, %d Gaussians" % sum(s.n for s in sc.sets),
                loop_ms=round(t_loop * 1e3, 3))
-    masked = sum(int(rd.mask.sum()) for rd in sc.renders)
-    # one batch for all sub-regions and views; the launch configuration is
-    # picked by the autotuner (captured fwd+bwd step timed per candidate)
-    from paper_2501_01677_amd.autotune import Autotuner
-    bb = build_batch(sc, RenderConfig(tile=16), torch)
-    fill_gouts(bb, sc, 4000, torch)
-    gouts = [{k: v.clone() for k, v in g.items()} for g in bb.gout]
-    tuner = Autotuner(steps=steps)
-    cfg, times = tuner.best(bb.sets, bb.renders, gouts)
-    del bb.workspace
-    del bb
-    torch.cuda.empty_cache()
     out["autotune_ms"] = {k: round(v * 1e3, 3) for k, v in times.items()}
     bb = build_batch(sc, cfg, torch)
     fill_gouts(bb, sc, 4000, torch)
@@ -397,7 +409,7 @@ def batched_speedup(torch, steps=5, scale=1.0):
     best = _graph_time(bb, torch, steps)
     out["graph_ms"] = round(best * 1e3, 3)
     out["graph_config"] = {"tile": cfg.tile, "persistent": cfg.persistent, "queue_chunk": cfg.queue_chunk,
-                           "workgroups_per_cu": cfg.workgroups_per_cu}
+                           "workgroups_per_cu": cfg.workgroups_per_cu, "bwd_reduce": cfg.bwd_reduce}
     out["graph_stages_ms"] = {k: round(v, 3) for k, v in stage.items()}
     del bb.workspace
     del bb

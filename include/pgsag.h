@@ -150,7 +150,15 @@ typedef struct pgsag_config {
   float logit_min;  /* float32(-ln 254) */
   float depth_guard; /* 1e-6 */
   float bg[3];      /* 0, 0, 0 */
-  int32_t reserved;
+  /* How the backward compositing pass sums each record's 13 per-pixel
+     gradient terms over a wave (same sums, different speed):
+     0: matrix cores -- the wave buffers 8 records' per-pixel weights in LDS
+        and contracts them with the pixels' features in FP32 MFMA steps
+        (fewer instructions per record; best for long tile lists);
+     1: lane exchanges -- each record is reduced at once across the wave
+        (less work per tile, twice the resident workgroups; best for short
+        tile lists).  Any other value is an error. */
+  int32_t bwd_reduce;
 } pgsag_config;
 
 typedef struct pgsag_plan_info {

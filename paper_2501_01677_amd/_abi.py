@@ -53,7 +53,7 @@ class Config(C.Structure):
                 ("workgroups_per_cu", C.c_int32), ("alpha_min", C.c_float), ("t_min", C.c_float),
                 ("alpha_max", C.c_float), ("dilation", C.c_float), ("z_near", C.c_float),
                 ("fov_clamp", C.c_float), ("logit_min", C.c_float), ("depth_guard", C.c_float),
-                ("bg", C.c_float * 3), ("reserved", C.c_int32)]
+                ("bg", C.c_float * 3), ("bwd_reduce", C.c_int32)]
 
 
 class PlanInfo(C.Structure):

@@ -2,10 +2,11 @@
 
 The rendered values do not depend on the launch configuration (every pixel
 blends the same records in the same order whatever the tile size, queue
-chunk or workgroup count), only the speed does.  For a batch shape the tuner
-times the captured forward + backward step of each candidate configuration
--- tile size T in {8, 16, 32}, plain or persistent launch, queue chunk and
-persistent workgroups per CU -- and keeps the fastest.  Results are cached
+chunk or workgroup count; the two backward reductions form the same sums in
+a different order), only the speed does.  For a batch shape the tuner times
+the captured forward + backward step of each candidate configuration -- tile
+size T in {8, 16, 32}, plain or persistent launch, queue chunk, persistent
+workgroups per CU and backward reduction -- and keeps the fastest.  Results are cached
 per shape bucket: (number of renders, log2 of the masked pixels, log2 of the
 Gaussians, SH degree), optionally persisted to a JSON file.
 """
@@ -19,16 +20,17 @@ import torch
 
 from .raster import Batch, RenderConfig
 
-DEFAULT_CANDIDATES = (
-    RenderConfig(tile=16),
-    RenderConfig(tile=8),
-    RenderConfig(tile=32),
-    RenderConfig(tile=16, persistent=True, queue_chunk=2, workgroups_per_cu=8),
-    RenderConfig(tile=16, persistent=True, queue_chunk=4, workgroups_per_cu=8),
-    RenderConfig(tile=16, persistent=True, queue_chunk=8, workgroups_per_cu=8),
-    RenderConfig(tile=16, persistent=True, queue_chunk=16, workgroups_per_cu=8),
-    RenderConfig(tile=8, persistent=True, queue_chunk=8, workgroups_per_cu=8),
-)
+DEFAULT_CANDIDATES = tuple(
+    RenderConfig(tile=t, persistent=p, queue_chunk=q, workgroups_per_cu=w, bwd_reduce=r)
+    for (t, p, q, w) in ((16, False, 1, 4), (8, False, 1, 4), (32, False, 1, 4),
+                         (16, True, 4, 8), (16, True, 8, 8), (16, True, 16, 8))
+    for r in (0, 1))
+
+
+def config_name(cfg):
+    """Short label of a launch configuration, e.g. T16-p8x8-r1."""
+    return (f"T{cfg.tile}" + (f"-p{cfg.queue_chunk}x{cfg.workgroups_per_cu}" if cfg.persistent else "")
+            + f"-r{cfg.bwd_reduce}")
 
 
 def shape_key(sets, renders):
@@ -97,8 +99,7 @@ class Autotuner:
                     for k, v in g.items():
                         b.gout[r][k].copy_(v.reshape(b.gout[r][k].shape))
             t = _step_time(b, self.steps)
-            name = (f"T{cfg.tile}" + (f"-p{cfg.queue_chunk}x{cfg.workgroups_per_cu}" if cfg.persistent else ""))
-            times[name] = t
+            times[config_name(cfg)] = t
             if t < best_t:
                 best_cfg, best_t = cfg, t
             del b

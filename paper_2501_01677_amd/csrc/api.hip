@@ -50,6 +50,8 @@ int validate(const pgsag_config *cfg, const pgsag_gaussians *sets, int32_t n_set
     return fail(PGSAG_INVALID_ARGUMENT, "tile must be 8, 16 or 32 (got %d)", cfg->tile);
   if (n_sets < 1 || n_renders < 1) return fail(PGSAG_INVALID_ARGUMENT, "need at least one set and one render");
   if (n_renders > 4096) return fail(PGSAG_UNSUPPORTED, "at most 4096 renders per batch");
+  if (cfg->bwd_reduce != 0 && cfg->bwd_reduce != 1)
+    return fail(PGSAG_INVALID_ARGUMENT, "bwd_reduce must be 0 or 1 (got %d)", cfg->bwd_reduce);
   if (cfg->persistent && (cfg->queue_chunk < 1 || cfg->queue_chunk > 64))
     return fail(PGSAG_INVALID_ARGUMENT, "queue_chunk must be in 1..64");
   if (cfg->persistent && (cfg->workgroups_per_cu < 1 || cfg->workgroups_per_cu > 16))

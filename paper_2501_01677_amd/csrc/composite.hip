@@ -30,6 +30,8 @@
 // In persistent mode a grid of (CUs x occupancy) workgroups pulls chunks of
 // tiles from an LPT-ordered queue with an atomic counter; every workgroup
 // leaves once the counter passes the end of the queue.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace pgsag {
@@ -288,6 +290,42 @@ __device__ __forceinline__ float dpp(float x) {
   return __uint_as_float(__builtin_amdgcn_update_dpp(0u, __float_as_uint(x), CTRL, 0xf, 0xf, false));
 }
 
+// Sum of v[0..15] over the 64 lanes of a wave by recursive halving, using
+// only VALU lane exchanges: permlane32/16 swaps for lane distance 32 and 16,
+// DPP row rotate by 8, half-row mirror and quad permutations below that.
+// Each step keeps half of the values per lane and adds the partner lane's
+// copy of them.  Afterwards lane L holds the total of value (L >> 2) & 15.
+__device__ __forceinline__ float wave_reduce16(const float v[16]) {
+  const int lane = threadIdx.x & 63;
+  float w8[8], w4[4], w2[2];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    // lanes 0..31 keep v[s], lanes 32..63 keep v[8 + s]
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[s]), __float_as_uint(v[8 + s]), false, false);
+    w8[s] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    // lanes with bit 4 clear keep w8[s], the others w8[4 + s]
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w8[s]), __float_as_uint(w8[4 + s]), false, false);
+    w4[s] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  {
+    const bool hi = lane & 8;  // partner: lane ^ 8 (row rotate by 8)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const float mine = hi ? w4[2 + s] : w4[s];
+      const float send = hi ? w4[s] : w4[2 + s];
+      w2[s] = mine + dpp<0x128>(send);
+    }
+  }
+  const bool hi = lane & 4;  // partner: mirrored lane in the same 8-lane half row
+  float x = (hi ? w2[1] : w2[0]) + dpp<0x141>(hi ? w2[0] : w2[1]);
+  x += dpp<0x4e>(x);  // quad permutation: lane ^ 2
+  x += dpp<0xb1>(x);  // quad permutation: lane ^ 1
+  return x;
+}
+
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // Per-wave LDS of the backward pass's per-record reduction.  For up to 8
@@ -379,7 +417,13 @@ __device__ __forceinline__ uint32_t slot_fields(int kk) {
                    : (G_SXX | G_SYY << 8 | 0x0f0fu << 16);
 }
 
-template <int T>
+// MM: the per-record sums are formed on the matrix cores from LDS-buffered
+// weights (flush_records); otherwise every record is reduced across the wave
+// at once with lane exchanges (wave_reduce16) and added by one atomic
+// instruction.  Same sums, different speed: the matrix-core form spends
+// fewer instructions per record, the lane-exchange form less per tile and
+// fewer registers and LDS (twice the resident workgroups).
+template <int T, bool MM>
 __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, const Header &h, void *__restrict__ ws, uint32_t tile,
                               float4 (*srec)[4], float4 *sabc, uint32_t *sid, Entry (*lists)[batch_of<T>()],
                               WaveAcc *accs, int *smax, const uint32_t *__restrict__ vals) {
@@ -454,19 +498,19 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
   // the features of the reduction (see flush_records), fixed for the tile:
   // the output gradients of the other pixels come through the wave's buffer
   WaveAcc &acc = accs[threadIdx.x >> 6];
-#pragma unroll
-  for (int c = 0; c < 7; ++c) acc.a[c][lane] = gch[c];
-  __builtin_amdgcn_wave_barrier();
   float bf[16];
-  {
+  if constexpr (MM) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) acc.a[c][lane] = gch[c];
+    __builtin_amdgcn_wave_barrier();
     const int n = lane & 15, kk = lane >> 4;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int p = ((i >> 2) << 4) + (kk << 2) + (i & 3);
       bf[i] = feature_slot(n, acc.a[n < 7 ? n : 0][p], (float)(p & 7) - 3.5f, (float)(p >> 3) - 3.5f);
     }
+    __builtin_amdgcn_wave_barrier();
   }
-  __builtin_amdgcn_wave_barrier();
   const float bcx = g.ox + 3.5f, bcy = g.oy + 3.5f;  // block centre
   const uint32_t fields = slot_fields(lane >> 4);
   int nb = 0;  // buffered records (uniform)
@@ -480,60 +524,110 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
     __syncthreads();
     if (__ballot(last >= (int32_t)bstart) != 0ull) {
       const int len = build_list(srec, cnt, g.ox, g.oy, l2min, list);
-      // back to front; the next entry and its coefficients are loaded while
-      // this one is evaluated
-      Entry e = list[len > 0 ? len - 1 : 0];
-      float4 abc = sabc[len > 0 ? e.k : 0];
-      for (int t = len - 1; t >= 0; --t) {
-        const Entry en = list[t > 0 ? t - 1 : 0];
-        const float4 abcn = sabc[en.k];
-        const int32_t idx = (int32_t)(bstart + e.k);
-        // Every lane evaluates the fragment (the wave executes it anyway when
-        // any lane contributes); lanes that do not contribute get zero weight.
-        const float ex = lane_exponent(e, abc, g.L);
-        const bool contrib = idx <= last && ex >= l2min;
-        if (__ballot(contrib) != 0ull) {
-          const float4 r0 = srec[e.k][0], r1 = srec[e.k][1], r2 = srec[e.k][2], r3 = srec[e.k][3];
-          const uint32_t rid = sid[e.k];
+      if constexpr (!MM) {
+        for (int t = len - 1; t >= 0; --t) {
+          const Entry cur = list[t];
+          const int32_t idx = (int32_t)(bstart + cur.k);
+          // Every lane evaluates the fragment (the wave executes it anyway when
+          // any lane contributes); lanes that do not contribute get zero weight.
+          const float ex = lane_exponent(cur, sabc[cur.k], g.L);
+          const bool contrib = idx <= last && ex >= l2min;
+          if (__ballot(contrib) == 0ull) continue;
           const float raw = __builtin_amdgcn_exp2f(ex);
           const float a = __builtin_amdgcn_fmed3f(raw, 0.f, amax);  // min(raw, amax), raw >= 0
+          const float4 r0 = srec[cur.k][0], r1 = srec[cur.k][1], r2 = srec[cur.k][2], r3 = srec[cur.k][3];
           const float f[7] = {r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
           const float iom = __builtin_amdgcn_rcpf(1.f - a);  // 1 / (1 - alpha), alpha <= 0.99
           const float Tp = Tr * iom;
           const float w = contrib ? a * Tp : 0.f;
           // dL/dalpha = sum_c g_c (T f_c - S_c / (1 - alpha)) + g_alpha T_final / (1 - alpha)
           float Gf = 0.f;
+          float v[16];
 #pragma unroll
-          for (int c = 0; c < 7; ++c) Gf = fmaf(gch[c], f[c], Gf);
+          for (int c = 0; c < 7; ++c) {
+            Gf = fmaf(gch[c], f[c], Gf);
+            v[6 + c] = w * gch[c];
+          }
           const float dLda = Tp * Gf + (ga * Tf - GS) * iom;
           GS = contrib ? fmaf(w, Gf, GS) : GS;
           Tr = contrib ? Tp : Tr;
           // alpha = o G with G = exp(-q/2): dalpha/do = G = alpha / o,
           // dalpha/dq = -alpha / 2 (zero on the clamped side of alpha_max)
           const float gate = (contrib && raw <= amax) ? dLda : 0.f;
-          // buffer w and dL/dq; the record's sums over the wave's pixels are
-          // formed on the matrix cores once 8 records are buffered
-          // granule (lane >> 2) of row nb lands at (lane >> 2) ^ nb
-          const int col = lane ^ (nb << 2);
-          acc.a[nb][col] = w;
-          acc.a[8 + nb][col] = -0.5f * a * gate;
-          const bool mine = lane == nb;
-          isid = mine ? rid : isid;
-          icx = mine ? r0.x : icx;
-          icy = mine ? r0.y : icy;
-          if (++nb == 8) {
-            __builtin_amdgcn_wave_barrier();
-            flush_records(acc, 8, bf, fields, isid, icx, icy, bcx, bcy, g2);
-            __builtin_amdgcn_wave_barrier();
-            nb = 0;
-          }
+          const float dx = fx - r0.x, dy = fy - r0.y;
+          // moments only: the record's conic and 1/o are applied once per
+          // record after the reduction (see G2Field)
+          const float ag = a * gate;
+          const float dLdq = -0.5f * ag;
+          const float qx = dLdq * dx, qy = dLdq * dy;
+          v[G_SO] = ag;
+          v[G_SX] = qx;
+          v[G_SY] = qy;
+          v[G_SXX] = qx * dx;
+          v[G_SXY] = qx * dy;
+          v[G_SYY] = qy * dy;
+          v[13] = v[14] = v[15] = 0.f;
+          const float tot = wave_reduce16(v);
+          const int which = (lane >> 2) & 15;
+          if ((lane & 3) == 0 && which < 13 && tot != 0.f)
+            unsafeAtomicAdd(g2 + (uint64_t)sid[cur.k] * kG2 + which, tot);
         }
-        e = en;
-        abc = abcn;
+      } else {
+        // back to front; the next entry and its coefficients are loaded while
+        // this one is evaluated
+        Entry e = list[len > 0 ? len - 1 : 0];
+        float4 abc = sabc[len > 0 ? e.k : 0];
+        for (int t = len - 1; t >= 0; --t) {
+          const Entry en = list[t > 0 ? t - 1 : 0];
+          const float4 abcn = sabc[en.k];
+          const int32_t idx = (int32_t)(bstart + e.k);
+          // Every lane evaluates the fragment (the wave executes it anyway when
+          // any lane contributes); lanes that do not contribute get zero weight.
+          const float ex = lane_exponent(e, abc, g.L);
+          const bool contrib = idx <= last && ex >= l2min;
+          if (__ballot(contrib) != 0ull) {
+            const float4 r0 = srec[e.k][0], r1 = srec[e.k][1], r2 = srec[e.k][2], r3 = srec[e.k][3];
+            const uint32_t rid = sid[e.k];
+            const float raw = __builtin_amdgcn_exp2f(ex);
+            const float a = __builtin_amdgcn_fmed3f(raw, 0.f, amax);  // min(raw, amax), raw >= 0
+            const float f[7] = {r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
+            const float iom = __builtin_amdgcn_rcpf(1.f - a);  // 1 / (1 - alpha), alpha <= 0.99
+            const float Tp = Tr * iom;
+            const float w = contrib ? a * Tp : 0.f;
+            // dL/dalpha = sum_c g_c (T f_c - S_c / (1 - alpha)) + g_alpha T_final / (1 - alpha)
+            float Gf = 0.f;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) Gf = fmaf(gch[c], f[c], Gf);
+            const float dLda = Tp * Gf + (ga * Tf - GS) * iom;
+            GS = contrib ? fmaf(w, Gf, GS) : GS;
+            Tr = contrib ? Tp : Tr;
+            // alpha = o G with G = exp(-q/2): dalpha/do = G = alpha / o,
+            // dalpha/dq = -alpha / 2 (zero on the clamped side of alpha_max)
+            const float gate = (contrib && raw <= amax) ? dLda : 0.f;
+            // buffer w and dL/dq; the record's sums over the wave's pixels
+            // are formed on the matrix cores once 8 records are buffered
+            // (granule (lane >> 2) of row nb lands at (lane >> 2) ^ nb)
+            const int col = lane ^ (nb << 2);
+            acc.a[nb][col] = w;
+            acc.a[8 + nb][col] = -0.5f * a * gate;
+            const bool mine = lane == nb;
+            isid = mine ? rid : isid;
+            icx = mine ? r0.x : icx;
+            icy = mine ? r0.y : icy;
+            if (++nb == 8) {
+              __builtin_amdgcn_wave_barrier();
+              flush_records(acc, 8, bf, fields, isid, icx, icy, bcx, bcy, g2);
+              __builtin_amdgcn_wave_barrier();
+              nb = 0;
+            }
+          }
+          e = en;
+          abc = abcn;
+        }
       }
     }
   }
-  if (nb > 0) {
+  if (MM && nb > 0) {
     __builtin_amdgcn_wave_barrier();
     flush_records(acc, nb, bf, fields, isid, icx, icy, bcx, bcy, g2);
   }
@@ -570,22 +664,23 @@ __global__ void __launch_bounds__(T *T) forward_kernel(const void *__restrict__ 
   }
 }
 
-// At most 4 of these workgroups fit a CU's LDS: registers are sized for 4
-// waves per SIMD.
-template <int T>
-__global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(4))) backward_kernel(const void *__restrict__ desc, void *__restrict__ ws,
+// With MM at most 4 of these workgroups fit a CU's LDS: registers are then
+// sized for 4 waves per SIMD.
+template <int T, bool MM>
+__global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(MM ? 4 : 1))) backward_kernel(const void *__restrict__ desc, void *__restrict__ ws,
                                                          const uint32_t *__restrict__ vals) {
   constexpr int NT = batch_of<T>();
   __shared__ float4 srec[NT][4];
   __shared__ float4 sabc[NT];
   __shared__ uint32_t sid[NT];
   __shared__ Entry lists[T * T / 64][NT];
-  __shared__ WaveAcc accs[T * T / 64];
+  __shared__ std::conditional_t<MM, WaveAcc, uint32_t> accs_[T * T / 64];
+  WaveAcc *accs = reinterpret_cast<WaveAcc *>(accs_);
   __shared__ int smax;
   __shared__ uint32_t s_item;
   const Header &h = *header(desc);
   if (!h.cfg.persistent) {
-    backward_tile<T>(desc, h, ws, blockIdx.x, srec, sabc, sid, lists, accs, &smax, vals);
+    backward_tile<T, MM>(desc, h, ws, blockIdx.x, srec, sabc, sid, lists, accs, &smax, vals);
     return;
   }
   uint32_t *ctr = ws_ptr<uint32_t>(ws, h.ws.status) + S_QUEUE_BWD;
@@ -601,7 +696,7 @@ __global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(4))) 
     const uint32_t stop = min(ntiles, base + chunk);
     for (uint32_t it = base; it < stop; ++it) {
       __syncthreads();
-      backward_tile<T>(desc, h, ws, queue[it], srec, sabc, sid, lists, accs, &smax, vals);
+      backward_tile<T, MM>(desc, h, ws, queue[it], srec, sabc, sid, lists, accs, &smax, vals);
     }
   }
 }
@@ -622,7 +717,10 @@ template <int T>
 void launch_bwd_t(const void *d, const Header &h, void *ws, hipStream_t s) {
   const uint32_t *vals = ws_ptr<uint32_t>(ws, h.ws.sorted_val);
   const unsigned grid = h.cfg.persistent ? persistent_grid(h) : (unsigned)h.n_tiles;
-  hipLaunchKernelGGL(HIP_KERNEL_NAME(backward_kernel<T>), dim3(grid), dim3(T * T), 0, s, d, ws, vals);
+  if (h.cfg.bwd_reduce == 0)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(backward_kernel<T, true>), dim3(grid), dim3(T * T), 0, s, d, ws, vals);
+  else
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(backward_kernel<T, false>), dim3(grid), dim3(T * T), 0, s, d, ws, vals);
 }
 
 }  // namespace

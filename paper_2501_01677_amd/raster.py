@@ -38,6 +38,7 @@ class RenderConfig:
     logit_min: float = float(np.float32(-math.log(254.0)))
     depth_guard: float = 1e-6
     bg: tuple = (0.0, 0.0, 0.0)
+    bwd_reduce: int = 0  # 0: matrix-core per-record sums, 1: wave lane exchanges
 
     def to_c(self) -> A.Config:
         c = A.Config()
@@ -47,6 +48,7 @@ class RenderConfig:
                   "depth_guard"):
             setattr(c, k, getattr(self, k))
         c.bg = (C.c_float * 3)(*self.bg)
+        c.bwd_reduce = int(self.bwd_reduce)
         return c
 
 

@@ -40,7 +40,7 @@ STRUCTS = {
     "pgsag_outputs": (A.Outputs, ["rgb", "alpha", "n_contrib"]),
     "pgsag_grad_outputs": (A.GradOutputs, ["rgb", "alpha"]),
     "pgsag_render": (A.Render, ["set", "cam", "mask", "out", "gout"]),
-    "pgsag_config": (A.Config, ["tile", "alpha_min", "logit_min", "depth_guard", "bg"]),
+    "pgsag_config": (A.Config, ["tile", "alpha_min", "logit_min", "depth_guard", "bg", "bwd_reduce"]),
     "pgsag_adam_config": (A.AdamConfig, ["lr", "step_state", "m_offset", "v_offset", "write_grads"]),
     "pgsag_loss_config": (A.LossConfig, ["lambda_rgb", "lambda_load", "normal_norm", "normal_eps", "reserved"]),
     "pgsag_plan_info": (A.PlanInfo, ["workspace_bytes", "pair_capacity", "tile_bits"]),
@@ -96,6 +96,13 @@ def test_plan_sizes_and_validation():
     assert L.pgsag_plan(C.byref(cfg), gs, 1, rs, 1, 5000, C.byref(info)) == A.INVALID_ARGUMENT
     assert b"tile" in L.pgsag_last_error()
     cfg.tile = 16
+    # unknown backward reduction
+    cfg.bwd_reduce = 2
+    assert L.pgsag_plan(C.byref(cfg), gs, 1, rs, 1, 5000, C.byref(info)) == A.INVALID_ARGUMENT
+    assert b"bwd_reduce" in L.pgsag_last_error()
+    cfg.bwd_reduce = 1
+    assert L.pgsag_plan(C.byref(cfg), gs, 1, rs, 1, 5000, C.byref(info)) == A.OK
+    cfg.bwd_reduce = 0
     # bad SH degree, bad set index, zero capacity, bad image
     gs[0].sh_degree = 4
     assert L.pgsag_plan(C.byref(cfg), gs, 1, rs, 1, 5000, C.byref(info)) == A.INVALID_ARGUMENT

@@ -73,23 +73,26 @@ GRAD_SCENES = {
 }
 
 
+@pytest.mark.parametrize("reduce", [0, 1])
 @pytest.mark.parametrize("tile", [8, 16])
 @pytest.mark.parametrize("name", sorted(GRAD_SCENES))
-def test_gradients_match_oracle(name, tile):
-    print(f"[case] backward {name} tile={tile}", flush=True)
+def test_gradients_match_oracle(name, tile, reduce):
+    """Both backward reductions (matrix cores, lane exchanges) against the oracle."""
+    print(f"[case] backward {name} tile={tile} reduce={reduce}", flush=True)
     sc = GRAD_SCENES[name]()
-    b = device_scene(sc, RenderConfig(tile=tile))
+    b = device_scene(sc, RenderConfig(tile=tile, bwd_reduce=reduce))
     b.forward()
     gouts = _gouts(sc, 1000)
     b.backward([{k: torch.from_numpy(v).cuda() for k, v in g.items()} for g in gouts])
     torch.cuda.synchronize()
-    _check_grads(sc, b, gouts, (name, tile))
+    _check_grads(sc, b, gouts, (name, tile, reduce))
 
 
-def test_persistent_backward_matches_oracle():
-    print("[case] backward persistent", flush=True)
+@pytest.mark.parametrize("reduce", [0, 1])
+def test_persistent_backward_matches_oracle(reduce):
+    print(f"[case] backward persistent reduce={reduce}", flush=True)
     sc = GRAD_SCENES["two-views-sh2"]()
-    b = device_scene(sc, RenderConfig(tile=16, persistent=True, queue_chunk=3))
+    b = device_scene(sc, RenderConfig(tile=16, persistent=True, queue_chunk=3, bwd_reduce=reduce))
     b.forward()
     gouts = _gouts(sc, 2000)
     b.backward([{k: torch.from_numpy(v).cuda() for k, v in g.items()} for g in gouts])
