@@ -43,6 +43,10 @@ constexpr float kHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
 // workgroups resident per CU).
 template <int T>
 constexpr int batch_of() { return T == 8 ? 64 : 128; }
+// Backward batches: 96 records with the matrix-core reduction at T = 16 (its
+// per-wave buffers leave room for 5 workgroups per CU only then).
+template <int T, bool MM>
+constexpr int bwd_batch_of() { return MM && T == 16 ? 96 : batch_of<T>(); }
 
 struct Entry {   // one record in one wave's list (16 bytes)
   float F, D, E;
@@ -425,9 +429,9 @@ __device__ __forceinline__ uint32_t slot_fields(int kk) {
 // fewer registers and LDS (twice the resident workgroups).
 template <int T, bool MM>
 __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, const Header &h, void *__restrict__ ws, uint32_t tile,
-                              float4 (*srec)[4], float4 *sabc, uint32_t *sid, Entry (*lists)[batch_of<T>()],
+                              float4 (*srec)[4], float4 *sabc, uint32_t *sid, Entry (*lists)[bwd_batch_of<T, MM>()],
                               WaveAcc *accs, int *smax, const uint32_t *__restrict__ vals) {
-  constexpr int NT = batch_of<T>();
+  constexpr int NT = bwd_batch_of<T, MM>();
   // nothing to do for a tile without masked pixels (uniform over the workgroup)
   if (ws_ptr<const uint32_t>(ws, h.ws.tile_count)[tile] == 0) return;
   TileGeom g;
@@ -664,12 +668,14 @@ __global__ void __launch_bounds__(T *T) forward_kernel(const void *__restrict__ 
   }
 }
 
-// With MM at most 4 of these workgroups fit a CU's LDS: registers are then
-// sized for 4 waves per SIMD.
+// Registers sized for the occupancy the LDS allows with MM: 5 workgroups
+// per CU at T = 16 (96-record batches, 30.6 KB; 96 VGPRs, the per-tile
+// constants spill to scratch outside the record loop), 4 waves per SIMD
+// otherwise.
 template <int T, bool MM>
-__global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(MM ? 4 : 1))) backward_kernel(const void *__restrict__ desc, void *__restrict__ ws,
+__global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(MM ? (T == 16 ? 5 : 4) : 1))) backward_kernel(const void *__restrict__ desc, void *__restrict__ ws,
                                                          const uint32_t *__restrict__ vals) {
-  constexpr int NT = batch_of<T>();
+  constexpr int NT = bwd_batch_of<T, MM>();
   __shared__ float4 srec[NT][4];
   __shared__ float4 sabc[NT];
   __shared__ uint32_t sid[NT];
