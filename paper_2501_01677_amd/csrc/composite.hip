@@ -123,19 +123,21 @@ __device__ __forceinline__ int build_list(const float4 (*srec)[4], int cnt, floa
 }
 
 // Exponent of an entry at this lane: F + D lx + E ly + A lx^2 + B lx ly + C ly^2
-// with (A, B, C) = -log2(e)/2 (a, 2b, c).  One instruction sequence shared by
+// with (A, B, C) = -log2(e)/2 (a, 2b, c), in Horner form
+//     F + lx (D + A lx + B ly) + ly (E + C ly)
+// (five FMAs on the lane's two offsets).  One instruction sequence shared by
 // the forward and backward kernels.
 struct LaneOffsets {
-  float lx, ly, lxx, lxy, lyy;
+  float lx, ly;
 };
 
 __device__ __forceinline__ float lane_exponent(const Entry &e, const float4 &abc, const LaneOffsets &L) {
 #pragma clang fp contract(off)
-  float v = __builtin_fmaf(e.E, L.ly, e.F);
-  v = __builtin_fmaf(e.D, L.lx, v);
-  v = __builtin_fmaf(abc.z, L.lyy, v);
-  v = __builtin_fmaf(abc.y, L.lxy, v);
-  v = __builtin_fmaf(abc.x, L.lxx, v);
+  float u = __builtin_fmaf(abc.x, L.lx, e.D);
+  u = __builtin_fmaf(abc.y, L.ly, u);
+  const float w = __builtin_fmaf(abc.z, L.ly, e.E);
+  float v = __builtin_fmaf(L.lx, u, e.F);
+  v = __builtin_fmaf(L.ly, w, v);
   return v;
 }
 
@@ -166,9 +168,6 @@ __device__ __forceinline__ void tile_geom(const void *desc, const Header &h, uin
   g.oy = by + 0.5f;
   g.L.lx = (float)lx;
   g.L.ly = (float)ly;
-  g.L.lxx = (float)(lx * lx);
-  g.L.lxy = (float)(lx * ly);
-  g.L.lyy = (float)(ly * ly);
 }
 
 // Stages batch records [j0, j1) into LDS: the raw 64-byte records and the
