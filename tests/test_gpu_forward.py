@@ -125,10 +125,12 @@ def _emit_reference_inputs(b, sc, tile):
     return grids, offs, np.concatenate(active)
 
 
-@pytest.mark.parametrize("n,seed,wide", [(300, 1, False), (40_000, 2, False), (3_000, 3, True)])
+@pytest.mark.parametrize("n,seed,wide", [(300, 1, False), (40_000, 2, False), (3_000, 3, True), (8_000, 4, True)])
 def test_binning_bit_exact_on_synthetic_rects(n, seed, wide):
     """wide: rectangles up to 48 x 14 tiles, so emission also takes its path
-    for rectangles too large to stage (more than 8 rows or 32 columns)."""
+    for rectangles too large to stage (more than 8 rows or 32 columns).  The
+    pair capacities (64 n or 700 n) select both radix chunk sizes (1024, and
+    2048 from two million keys)."""
     print(f"[case] binning n={n} wide={wide}", flush=True)
     tile = 16
     W, H = (1100, 300) if wide else (300, 200)
