@@ -104,15 +104,18 @@ def test_facade_forward_sampled_pixels():
     assert ref["n_contrib"].mean() > 5
 
 
-def test_batched_subregions_sampled_pixels_and_crop_gradients():
+@pytest.mark.parametrize("reduce", [1, 0])
+def test_batched_subregions_sampled_pixels_and_crop_gradients(reduce):
     """The 16 sub-region x 4 view batch (5.4M Gaussians, 1600x1200) in one
-    persistent launch with 8-tile queue chunks (the configuration the
-    autotuner picks for it): 256 seeded pixels of six renders against the
+    persistent launch with 8-tile queue chunks and the lane-exchange backward
+    reduction (the configuration the autotuner picks for it), and with the
+    matrix-core reduction: 256 seeded pixels of six renders against the
     oracle, and the gradient of a loss on one 32x32 crop of the largest
     sub-region's render (every other render gets dL/dout = 0)."""
-    print("[case] batched 16x4 samples + crop gradient", flush=True)
+    print(f"[case] batched 16x4 samples + crop gradient reduce={reduce}", flush=True)
     sc = scenes.config4()
-    b = device_scene(sc, RenderConfig(tile=16, persistent=True, queue_chunk=8, workgroups_per_cu=8))
+    b = device_scene(sc, RenderConfig(tile=16, persistent=True, queue_chunk=8, workgroups_per_cu=8,
+                                      bwd_reduce=reduce))
     b.forward()
     b.fit_capacity(1.1)
     b.forward(check_overflow=False)
