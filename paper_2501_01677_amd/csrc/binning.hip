@@ -96,6 +96,39 @@ __device__ inline uint32_t count_span(const uint8_t *m, int x0, int x1) {
   return c;
 }
 
+// Masked pixels of the (tile x, pixel row) spans of one tile row, for masks
+// whose rows start on 4-byte boundaries: each thread counts 4 spans per
+// round with all their word loads issued together.  WPT = tile / 4 words per
+// span; a span ends early at the image edge (W is a multiple of 4 here).
+template <int WPT>
+__device__ void count_row_spans(const uint8_t *mask, int W, int tx_n, int y0, int rows, uint32_t *cnt) {
+  const int items = tx_n * rows;
+  for (int it0 = 0; it0 < items; it0 += 4 * (int)blockDim.x) {
+    uint32_t cc[4];
+    int xx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int it = it0 + u * (int)blockDim.x + (int)threadIdx.x;
+      cc[u] = 0;
+      xx[u] = 0;
+      if (it < items) {
+        const int x = it % tx_n, y = y0 + it / tx_n;
+        const int a = x * WPT * 4, nw = min(WPT, (W - a) >> 2);
+        const uint32_t *m = reinterpret_cast<const uint32_t *>(mask + (uint64_t)y * W + a);
+        uint32_t w[WPT];
+#pragma unroll
+        for (int k = 0; k < WPT; ++k) w[k] = k < nw ? m[k] : 0u;
+#pragma unroll
+        for (int k = 0; k < WPT; ++k) cc[u] += nonzero_bytes(w[k]);
+        xx[u] = x;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (cc[u]) atomicAdd(&cnt[xx[u]], cc[u]);
+  }
+}
+
 // One workgroup per global tile row: masked (or, without a mask, in-image)
 // pixels of every tile of the row, and the row prefix of active flags
 // rowsat[ty][x] = number of active tiles among tiles 0..x-1 of row ty.
@@ -116,6 +149,10 @@ __global__ void __launch_bounds__(256) tile_mask_kernel(const void *__restrict__
   if (rd.mask == nullptr) {
     for (int x = threadIdx.x; x < tx_n; x += blockDim.x)
       cnt[x] = (uint32_t)((min(W, (x + 1) * tile) - x * tile) * rows);
+  } else if ((W & 3) == 0 && ((uintptr_t)rd.mask & 3u) == 0) {
+    if (tile == 8) count_row_spans<2>(rd.mask, W, tx_n, y0, rows, cnt);
+    else if (tile == 16) count_row_spans<4>(rd.mask, W, tx_n, y0, rows, cnt);
+    else count_row_spans<8>(rd.mask, W, tx_n, y0, rows, cnt);
   } else {
     // one work item per (tile, pixel row): count a tile-wide span
     for (int it = threadIdx.x; it < tx_n * rows; it += blockDim.x) {

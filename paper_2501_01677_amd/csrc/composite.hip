@@ -19,13 +19,14 @@
 // The backward pass walks the same list back to front from the tile's
 // largest last-blended index, recovering each pixel's transmittance before a
 // fragment as T_i = T_{i+1} / (1 - alpha_i) from the saved final T, keeps the
-// suffix sums of the blended features, and buffers each contributing
-// fragment's two per-pixel weights (alpha T and dL/dq) in LDS.  Every 8
-// records the wave reduces them over its 64 pixels as one small matrix
-// product on the matrix cores (the 13 per-record sums: 7 feature gradients
-// and 6 moments of dL/dq), then adds each sum with one float atomic.
-// It builds its lists with the same code as the forward pass, so it takes
-// the forward's decisions.
+// suffix sums of the blended features, and forms each contributing record's
+// 13 sums over the wave's 64 pixels (7 feature gradients and 6 moments of
+// dL/dq) in one of two ways, chosen at launch: either the wave buffers the
+// records' two per-pixel weights (alpha T and dL/dq) in LDS and reduces 8
+// records at a time as one small matrix product on the matrix cores, or it
+// reduces every record at once with lane exchanges.  Each sum is then added
+// with one float atomic.  It builds its lists with the same code as the
+// forward pass, so it takes the forward's decisions.
 //
 // In persistent mode a grid of (CUs x occupancy) workgroups pulls chunks of
 // tiles from an LPT-ordered queue with an atomic counter; every workgroup

@@ -112,6 +112,32 @@ def test_records_depth_keys_and_support_rects():
     assert checked > 300
 
 
+@pytest.mark.parametrize("tile", [8, 16, 32])
+@pytest.mark.parametrize("W,H", [(300, 70), (70, 45), (1100, 40)])
+def test_tile_counts_and_row_prefixes_bit_exact(W, H, tile):
+    """Masked pixels per tile and the per-row prefix of active tiles, against
+    the oracle's counts; widths that are multiples of 4 take the word-wise
+    span counting, the others the byte-wise one."""
+    print(f"[case] tile mask {W}x{H} tile={tile}", flush=True)
+    sc = scenes.small_scene(300 + W + tile, n=40, width=W, height=H, sh_degree=0, n_views=2)
+    b = device_scene(sc, RenderConfig(tile=tile), want_grads=False)
+    b.forward()
+    torch.cuda.synchronize()
+    tc = _u32(b.view("tile_count", torch.int32, int(b.info.n_tiles)))
+    toff = soff = 0
+    sat_len = sum((t[0] + 1) * (t[1] + 1) for t in (ob.tile_grid(W, H, tile) for _ in sc.renders))
+    sat = _u32(b.view("sat", torch.int32, sat_len))
+    for rd in sc.renders:
+        tx, ty = ob.tile_grid(W, H, tile)
+        want = ob.tile_mask_counts(rd.mask, W, H, tile)
+        assert np.array_equal(tc[toff:toff + tx * ty], want)
+        act = (want.reshape(ty, tx) > 0).astype(np.uint32)
+        rows = np.concatenate([np.zeros((ty, 1), np.uint32), np.cumsum(act, 1, dtype=np.uint32)], 1)
+        assert np.array_equal(sat[soff:soff + ty * (tx + 1)].reshape(ty, tx + 1), rows)
+        toff += tx * ty
+        soff += (tx + 1) * (ty + 1)
+
+
 def _emit_reference_inputs(b, sc, tile):
     """Per-render tile grids, offsets and active flags from the masks."""
     grids, offs, active = [], [], []
