@@ -498,6 +498,17 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
   const int maxlast = *smax;
   if (maxlast < (int)rg.x) return;  // uniform: no pixel blended anything
   const uint32_t end = (uint32_t)maxlast + 1;
+  // With MM, the largest last-blended index of this wave's pixels: records
+  // past it contribute to none of them and stay out of the wave's lists.
+  // (The lane-exchange form keeps every record of the tile's range; the
+  // limit costs it a wave of occupancy.)
+  int32_t wlast = maxlast;
+  if constexpr (MM) {
+    wlast = last;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, __shfl_xor(wlast, o, 64));
+    wlast = __builtin_amdgcn_readfirstlane(wlast);  // uniform: keep it scalar
+  }
   const int lane = threadIdx.x & 63;
   // the features of the reduction (see flush_records), fixed for the tile:
   // the output gradients of the other pixels come through the wave's buffer
@@ -526,8 +537,8 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
     __syncthreads();
     stage_batch<NT>(rec4, vals, bstart, (uint32_t)bend, srec, sabc, sid);
     __syncthreads();
-    if (__ballot(last >= (int32_t)bstart) != 0ull) {
-      const int len = build_list(srec, cnt, g.ox, g.oy, l2min, list);
+    if (MM ? wlast >= (int32_t)bstart : __ballot(last >= (int32_t)bstart) != 0ull) {
+      const int len = build_list(srec, MM ? min(cnt, wlast - (int32_t)bstart + 1) : cnt, g.ox, g.oy, l2min, list);
       if constexpr (!MM) {
         for (int t = len - 1; t >= 0; --t) {
           const Entry cur = list[t];
