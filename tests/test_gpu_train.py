@@ -62,23 +62,26 @@ def _oracle_step_grads(sc, gts, refs, olc):
     return total, losses
 
 
-def _trainer(sc, gts, lc, lr=1e-3, **kw):
+def _trainer(sc, gts, lc, lr=1e-3, cfg=None, **kw):
     dev = [gaussians_to_device(s) for s in sc.sets]
     renders = [dict(set=rd.set_index, camera=rd.camera, mask=torch.from_numpy(np.ascontiguousarray(rd.mask)).cuda())
                for rd in sc.renders]
     gt = [torch.from_numpy(g).cuda() for g in gts]
-    t = Trainer(dev, renders, gt, RenderConfig(tile=16), lc, lr=lr, **kw)
+    t = Trainer(dev, renders, gt, cfg or RenderConfig(tile=16), lc, lr=lr, **kw)
     t.fit()
     return t
 
 
-def test_training_step_gradient_matches_oracle_chain():
-    print("[case] train step gradient", flush=True)
+@pytest.mark.parametrize("reduce", [0, 1])
+def test_training_step_gradient_matches_oracle_chain(reduce):
+    """Loss, backward and the raw-parameter gradients of one training step
+    against the oracle's chain, under both backward reductions."""
+    print(f"[case] train step gradient reduce={reduce}", flush=True)
     sc, gts, refs = _prepared_scene(401)
     lc = LossConfig(lambda_normal=0.2, normal_norm=2, lambda_load=0.41)
     olc = ol.LossConfig(lambda_normal=0.2, normal_norm=2, lambda_load=0.41)
     ref, losses = _oracle_step_grads(sc, gts, refs, olc)
-    t = _trainer(sc, gts, lc, lr=0.0, keep_grads=True)
+    t = _trainer(sc, gts, lc, lr=0.0, cfg=RenderConfig(tile=16, bwd_reduce=reduce), keep_grads=True)
     out = t.step().cpu().numpy()
     torch.cuda.synchronize()
     # the geometric terms (the load term is a value of the binning only)
