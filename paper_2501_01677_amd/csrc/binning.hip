@@ -843,6 +843,9 @@ __global__ void queue_key_kernel(const void *__restrict__ desc, void *__restrict
   const uint32_t m = ws_ptr<uint32_t>(ws, h.ws.tile_count)[t];
   ws_ptr<uint32_t>(ws, h.ws.qkey[0])[t] = lpt_bucket(m, rg.y - rg.x);
   ws_ptr<uint32_t>(ws, h.ws.qval0)[t] = (uint32_t)t;
+  // tiles with work (masked pixels and pairs): they lead the LPT queue
+  const uint64_t busy = __ballot(m > 0 && rg.y > rg.x);
+  if ((threadIdx.x & 63) == 0 && busy) atomicAdd(status_of(ws, h) + S_NQUEUE, (uint32_t)__popcll(busy));
 }
 
 inline unsigned blocks_for(uint64_t n, unsigned bs = 256) { return (unsigned)((n + bs - 1) / bs); }

@@ -648,6 +648,16 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
   }
 }
 
+// Tiles per queue pop in persistent mode: the configured chunk, reduced
+// when there are fewer than two chunks of tiles with work per workgroup (the
+// queue leads with the longest tiles, so large pops would hand the few busy
+// tiles to a few workgroups).
+__device__ __forceinline__ uint32_t queue_chunk_for(const Header &h, void *ws) {
+  const uint32_t busy = ws_ptr<const uint32_t>(ws, h.ws.status)[S_NQUEUE];
+  const uint32_t fit = busy / (2u * gridDim.x);
+  return max(1u, min((uint32_t)h.cfg.queue_chunk, fit));
+}
+
 template <int T>
 __global__ void __launch_bounds__(T *T) forward_kernel(const void *__restrict__ desc, void *__restrict__ ws,
                                                         const uint32_t *__restrict__ vals) {
@@ -663,7 +673,7 @@ __global__ void __launch_bounds__(T *T) forward_kernel(const void *__restrict__ 
   }
   uint32_t *ctr = ws_ptr<uint32_t>(ws, h.ws.status) + S_QUEUE_FWD;
   const uint32_t *queue = ws_ptr<uint32_t>(ws, h.ws.queue);
-  const uint32_t chunk = (uint32_t)h.cfg.queue_chunk;
+  const uint32_t chunk = queue_chunk_for(h, ws);
   const uint32_t ntiles = (uint32_t)h.n_tiles;
   for (;;) {
     __syncthreads();
@@ -702,7 +712,7 @@ __global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(MM ? 
   }
   uint32_t *ctr = ws_ptr<uint32_t>(ws, h.ws.status) + S_QUEUE_BWD;
   const uint32_t *queue = ws_ptr<uint32_t>(ws, h.ws.queue);
-  const uint32_t chunk = (uint32_t)h.cfg.queue_chunk;
+  const uint32_t chunk = queue_chunk_for(h, ws);
   const uint32_t ntiles = (uint32_t)h.n_tiles;
   for (;;) {
     __syncthreads();
