@@ -74,7 +74,7 @@ GRAD_SCENES = {
 
 
 @pytest.mark.parametrize("reduce", [0, 1])
-@pytest.mark.parametrize("tile", [8, 16])
+@pytest.mark.parametrize("tile", [8, 16, 32])
 @pytest.mark.parametrize("name", sorted(GRAD_SCENES))
 def test_gradients_match_oracle(name, tile, reduce):
     """Both backward reductions (matrix cores, lane exchanges) against the oracle."""
