@@ -315,12 +315,15 @@ def train_step_bench(torch, steps):
     start = [gaussians_to_device(scenes.perturbed(55, s)) for s in sc.sets]
     renders = [dict(set=rd.set_index, camera=rd.camera, mask=torch.from_numpy(np.ascontiguousarray(rd.mask)).cuda())
                for rd in sc.renders]
-    # backward reduction picked by timing both on this batch shape
+    # launch configuration (plain or persistent, backward reduction) picked
+    # by timing the captured fwd+bwd step on this batch shape
     from paper_2501_01677_amd.autotune import Autotuner
     tb = build_batch(sc, RenderConfig(tile=16), torch)
     fill_gouts(tb, sc, 5000, torch)
     gouts = [{k: v.clone() for k, v in g.items()} for g in tb.gout]
-    tuner = Autotuner(candidates=(RenderConfig(tile=16), RenderConfig(tile=16, bwd_reduce=1)), steps=2)
+    cands = tuple(RenderConfig(tile=16, persistent=p, queue_chunk=8 if p else 1, workgroups_per_cu=8 if p else 4,
+                               bwd_reduce=r) for p in (False, True) for r in (0, 1))
+    tuner = Autotuner(candidates=cands, steps=2)
     cfg, times = tuner.best(tb.sets, tb.renders, gouts)
     del tb.workspace
     del tb, gouts
@@ -345,8 +348,10 @@ def train_step_bench(torch, steps):
     loss = t.loss_out.cpu().numpy().tolist()
     res = dict(workload="10M Gaussians SH3, 2 views 5472x3648, box-silhouette masks; forward + loss "
                         "(masked L1 + 0.01 boundary-aware normal L1, 0.41 balance-load) + backward + Adam",
-               ms_per_step=round(dt * 1e3, 3), masked_pixels=masked, bwd_reduce=cfg.bwd_reduce,
-               reduce_ms={k: round(v * 1e3, 3) for k, v in times.items()},
+               ms_per_step=round(dt * 1e3, 3), masked_pixels=masked,
+               config={"tile": cfg.tile, "persistent": cfg.persistent, "queue_chunk": cfg.queue_chunk,
+                       "workgroups_per_cu": cfg.workgroups_per_cu, "bwd_reduce": cfg.bwd_reduce},
+               autotune_ms={k: round(v * 1e3, 3) for k, v in times.items()},
                mpix_s=round(masked / dt / 1e6, 1), params=int(t.P.numel()),
                pairs=int(t.batch.status().pairs_needed), loss=[[round(x, 6) for x in r] for r in loss])
     del t
