@@ -247,11 +247,23 @@ __device__ inline bool locate(const void *desc, const DevSet *&S, int64_t &i) {
   return i < S->n;
 }
 
-// Active tiles of a tile rectangle from the per-row prefix of active flags.
+// Active tiles of a tile rectangle from the per-row prefix of active flags;
+// four rows' loads are issued together.
 __device__ inline uint32_t count_active(const uint32_t *rowsat, uint32_t pitch, uint32_t x0, uint32_t y0, uint32_t x1,
                                         uint32_t y1) {
   uint32_t c = 0;
-  for (uint32_t y = y0; y < y1; ++y) c += rowsat[y * pitch + x1] - rowsat[y * pitch + x0];
+  uint32_t y = y0;
+  for (; y + 4 <= y1; y += 4) {
+    uint32_t hi[4], lo[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      hi[k] = rowsat[(y + k) * pitch + x1];
+      lo[k] = rowsat[(y + k) * pitch + x0];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c += hi[k] - lo[k];
+  }
+  for (; y < y1; ++y) c += rowsat[y * pitch + x1] - rowsat[y * pitch + x0];
   return c;
 }
 
