@@ -157,3 +157,21 @@ def test_autotune_shape_key_buckets():
     renders = [dict(set=0, camera=cam, mask=mask), dict(set=1, camera=cam, mask=None)]
     # 512 + 2048 masked pixels, 4000 Gaussians, max SH degree 2
     assert shape_key(sets, renders) == "r2-px11-n11-sh2"
+
+
+def test_default_loss_weights_are_the_papers():
+    """The default boundary weight (Sec. 4.2, after Eq. 8) and normal-loss
+    weight lambda_4 (Sec. 4.3, Eq. 10) of the C library, the binding and the
+    oracle equal the constants the paper prints (tests/golden).  The
+    balance-load weight lambda (Eq. 11) is off by default; training passes it."""
+    import json
+    from oracle import losses as ol
+    from paper_2501_01677_amd.raster import LossConfig
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")
+    k = json.load(open(path))
+    lc = A.LossConfig()
+    A.lib().pgsag_default_loss_config(C.byref(lc))
+    for cfg in (lc, LossConfig(), ol.LossConfig()):
+        assert np.float32(cfg.boundary_weight) == np.float32(k["boundary_weight"]["value"])
+        assert np.float32(cfg.lambda_normal) == np.float32(k["lambda4"]["value"])
+        assert cfg.lambda_load == 0.0
