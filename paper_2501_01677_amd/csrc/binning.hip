@@ -58,15 +58,16 @@ __device__ inline uint32_t wave_inclusive_scan(uint32_t v) {
 
 // Exclusive scan of one value per thread across a 256-thread block; returns
 // the exclusive prefix and writes the block total to *total.
+template <int NW = 4>  // waves in the workgroup
 __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *total) {
-  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t wsum[NW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t inc = wave_inclusive_scan(v);
   if (lane == 63) wsum[wave] = inc;
   __syncthreads();
   uint32_t off = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < 4; ++w) {
+  for (int w = 0; w < NW; ++w) {
     const uint32_t s = wsum[w];
     if (w < wave) off += s;
     tot += s;
@@ -132,7 +133,8 @@ __device__ void count_row_spans(const uint8_t *mask, int W, int tx_n, int y0, in
 // One workgroup per global tile row: masked (or, without a mask, in-image)
 // pixels of every tile of the row, and the row prefix of active flags
 // rowsat[ty][x] = number of active tiles among tiles 0..x-1 of row ty.
-__global__ void __launch_bounds__(256) tile_mask_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+constexpr int kMaskBlock = 1024;  // threads per tile row: its spans load in one round at 1080p
+__global__ void __launch_bounds__(kMaskBlock) tile_mask_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
   const Header &h = *header(desc);
   const uint32_t row = blockIdx.x;
   const int r = upper_index(row_starts_of(desc), h.n_renders, row);
@@ -193,7 +195,7 @@ __global__ void __launch_bounds__(256) tile_mask_kernel(const void *__restrict__
       v = cnt[x] > 0 ? 1u : 0u;
     }
     uint32_t tot;
-    const uint32_t ex = block_exclusive_scan(v, &tot);
+    const uint32_t ex = block_exclusive_scan<kMaskBlock / 64>(v, &tot);
     if (x < tx_n) rs[x + 1] = running + ex + v;
     running += tot;
   }
@@ -860,7 +862,7 @@ void launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t s) {
 }
 
 void launch_tile_mask(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
-  hipLaunchKernelGGL(tile_mask_kernel, dim3(h.n_tile_rows), dim3(256), 0, s, d_desc, ws);
+  hipLaunchKernelGGL(tile_mask_kernel, dim3(h.n_tile_rows), dim3(kMaskBlock), 0, s, d_desc, ws);
 }
 
 void launch_recount(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
