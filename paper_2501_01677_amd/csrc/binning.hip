@@ -395,7 +395,8 @@ __device__ inline PassPlan plan_pass(const uint32_t *hist, uint64_t n, int pass,
   if (!dynamic) return pp;
   int np = 0, before = 0;
   for (int p = 0; p < passes; ++p) {
-    const int trivial = __syncthreads_or(n > 0 && hist[p * kRadixBins + threadIdx.x] == n);
+    const int trivial =
+        __syncthreads_or(n > 0 && threadIdx.x < kRadixBins && hist[p * kRadixBins + threadIdx.x] == n);
     if (!trivial) {
       if (p < pass) ++before;
       ++np;
@@ -438,14 +439,17 @@ __global__ void __launch_bounds__(256) chunk_count_kernel(const uint32_t *keys0,
 // Pass part 2: per digit, exclusive scan of its chunk counts along the
 // chunks, offset by the digit's base (exclusive scan of the digit totals):
 // table[d][c] becomes the output position of chunk c's first key of digit d.
-// One workgroup per digit; up to 8192 chunks per round are loaded at once
-// (coalesced), scanned through LDS as 256 contiguous segments, and stored.
-constexpr int kScanRound = 32;  // 256-chunk tiles per round
-__global__ void __launch_bounds__(256) chunk_scan_kernel(const uint32_t *n_dev, uint64_t n_bound, int pass,
-                                                         int passes, int dynamic, const uint32_t *hist,
-                                                         uint32_t *table, uint32_t nb_bound, uint32_t chunk) {
+// One workgroup of 1024 threads per digit; up to 8192 chunks per round are
+// loaded at once (coalesced), scanned through LDS as 1024 contiguous
+// segments, and stored.
+constexpr int kScanRound = 32;      // entries loaded per round: kScanRound x 256
+constexpr int kDigitScanBlock = 1024;  // threads per digit (few entries per thread)
+__global__ void __launch_bounds__(kDigitScanBlock) chunk_scan_kernel(const uint32_t *n_dev, uint64_t n_bound, int pass,
+                                                                     int passes, int dynamic, const uint32_t *hist,
+                                                                     uint32_t *table, uint32_t nb_bound, uint32_t chunk) {
+  constexpr int NW = kDigitScanBlock / 64;
   __shared__ uint32_t seg[kScanRound * kScanBlock];
-  __shared__ uint32_t red[4];
+  __shared__ uint32_t red[NW];
   const uint64_t n = bounded_count(n_dev, n_bound);
   const PassPlan pp = plan_pass(hist, n, pass, passes, dynamic);
   if (pp.skip) return;
@@ -458,21 +462,22 @@ __global__ void __launch_bounds__(256) chunk_scan_kernel(const uint32_t *n_dev, 
   for (int o = 32; o > 0; o >>= 1) b += __shfl_xor(b, o, 64);
   if (lane == 0) red[wave] = b;
   __syncthreads();
-  uint32_t run = red[0] + red[1] + red[2] + red[3];
+  uint32_t run = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) run += red[w];
   uint32_t *row = table + (uint64_t)d * nb_bound;
   for (uint32_t c0 = 0; c0 < nb; c0 += kScanRound * kScanBlock) {
     const uint32_t m = min((uint32_t)(kScanRound * kScanBlock), nb - c0);
-    const uint32_t J = (m + kScanBlock - 1) / kScanBlock;  // entries per thread segment
-#pragma unroll 8
+    const uint32_t J = (m + kDigitScanBlock - 1) / kDigitScanBlock;  // entries per thread segment
     for (uint32_t j = 0; j < J; ++j) {
-      const uint32_t c = j * kScanBlock + tid;
+      const uint32_t c = j * kDigitScanBlock + tid;
       seg[c] = c < m ? row[c0 + c] : 0u;
     }
     __syncthreads();
     uint32_t sum = 0;
     for (uint32_t j = 0; j < J; ++j) sum += seg[tid * J + j];
     uint32_t tot;
-    const uint32_t ex = block_exclusive_scan(sum, &tot);
+    const uint32_t ex = block_exclusive_scan<NW>(sum, &tot);
     uint32_t acc = run + ex;
     for (uint32_t j = 0; j < J; ++j) {
       const uint32_t v = seg[tid * J + j];
@@ -481,7 +486,7 @@ __global__ void __launch_bounds__(256) chunk_scan_kernel(const uint32_t *n_dev, 
     }
     __syncthreads();
     for (uint32_t j = 0; j < J; ++j) {
-      const uint32_t c = j * kScanBlock + tid;
+      const uint32_t c = j * kDigitScanBlock + tid;
       if (c < m) row[c0 + c] = seg[c];
     }
     run += tot;
@@ -605,8 +610,8 @@ void radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint64_t n_bound, const ui
     else
       hipLaunchKernelGGL(chunk_count_kernel<kRadixItems>, dim3(nb), dim3(256), 0, s, keys[0], keys[1], n_dev,
                          n_bound, p, passes, dbits, dynamic, hist, table, nb);
-    hipLaunchKernelGGL(chunk_scan_kernel, dim3(1u << dbits), dim3(256), 0, s, n_dev, n_bound, p, passes, dynamic,
-                       hist, table, nb, chunk);
+    hipLaunchKernelGGL(chunk_scan_kernel, dim3(1u << dbits), dim3(kDigitScanBlock), 0, s, n_dev, n_bound, p, passes,
+                       dynamic, hist, table, nb, chunk);
     if (big)
       hipLaunchKernelGGL(chunk_scatter_kernel<2 * kRadixItems>, dim3(nb), dim3(256), 0, s, keys[0], vals[0], keys[1],
                          vals[1], n_dev, n_bound, p, passes, dbits, dynamic, hist, table, nb, st, cur_word);
