@@ -309,7 +309,9 @@ __device__ uint64_t lookback64(uint64_t *st, uint32_t vid, uint64_t agg, uint32_
 
 // Records with at least one active tile, in record order, as (depth key,
 // record id) -> vis_key[0], vis_val[0]; the count goes to the status word.
-__global__ void __launch_bounds__(256) compact_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+constexpr int kCompactBlock = 1024;                         // threads per 4096-record chunk
+constexpr int kCompactItems = kScanChunk / kCompactBlock;  // consecutive records per thread
+__global__ void __launch_bounds__(kCompactBlock) compact_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
   const Header &h = *header(desc);
   uint32_t *st = status_of(ws, h);
   const uint64_t n = h.n_records;
@@ -317,17 +319,17 @@ __global__ void __launch_bounds__(256) compact_kernel(const void *__restrict__ d
   const uint32_t vid = virtual_block(st + S_CTR_COMPACT);
   if (vid >= nb) return;
   const uint32_t *nact = ws_ptr<uint32_t>(ws, h.ws.nact);
-  const uint64_t base = (uint64_t)vid * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
-  uint32_t f[kScanItems];
+  const uint64_t base = (uint64_t)vid * kScanChunk + (uint64_t)threadIdx.x * kCompactItems;
+  uint32_t f[kCompactItems];
   uint32_t ts = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
+  for (int k = 0; k < kCompactItems; ++k) {
     const uint64_t i = base + k;
     f[k] = (i < n && nact[i] > 0) ? 1u : 0u;
     ts += f[k];
   }
   uint32_t tot;
-  const uint32_t ex = block_exclusive_scan(ts, &tot);
+  const uint32_t ex = block_exclusive_scan<kCompactBlock / 64>(ts, &tot);
   __shared__ uint64_t s_prefix;
   if (threadIdx.x < 64) {
     const uint64_t p = lookback64(ws_ptr<uint64_t>(ws, h.ws.lb_compact), vid, tot, st + S_ERROR);
@@ -341,11 +343,12 @@ __global__ void __launch_bounds__(256) compact_kernel(const void *__restrict__ d
   uint32_t *vo = ws_ptr<uint32_t>(ws, h.ws.vis_val[0]);
   // digit histograms of the depth keys for the radix passes
   __shared__ uint32_t hs[kDepthPasses][kRadixBins];
-  for (int p = 0; p < kDepthPasses; ++p) hs[p][threadIdx.x] = 0;
+  if (threadIdx.x < kRadixBins)
+    for (int p = 0; p < kDepthPasses; ++p) hs[p][threadIdx.x] = 0;
   __syncthreads();
   uint64_t pos = prefix + ex;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
+  for (int k = 0; k < kCompactItems; ++k) {
     const uint64_t i = base + k;
     const uint32_t key = f[k] ? dkey[i] : 0u;
     if (f[k]) {
@@ -358,8 +361,9 @@ __global__ void __launch_bounds__(256) compact_kernel(const void *__restrict__ d
   }
   __syncthreads();
   uint32_t *dh = ws_ptr<uint32_t>(ws, h.ws.dhist);
-  for (int p = 0; p < kDepthPasses; ++p)
-    if (hs[p][threadIdx.x]) atomicAdd(&dh[p * kRadixBins + threadIdx.x], hs[p][threadIdx.x]);
+  if (threadIdx.x < kRadixBins)
+    for (int p = 0; p < kDepthPasses; ++p)
+      if (hs[p][threadIdx.x]) atomicAdd(&dh[p * kRadixBins + threadIdx.x], hs[p][threadIdx.x]);
 }
 
 // ------------------------------------------------------- radix sort
@@ -626,7 +630,7 @@ void radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint64_t n_bound, const ui
 
 // Exclusive scan of the active-tile counts of the depth-sorted visible
 // records -> pair_off[], and the pair total / overflow in the status word.
-__global__ void __launch_bounds__(256) pair_scan_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+__global__ void __launch_bounds__(kCompactBlock) pair_scan_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
   const Header &h = *header(desc);
   uint32_t *st = status_of(ws, h);
   const uint64_t nvis = st[S_NVIS];
@@ -635,17 +639,17 @@ __global__ void __launch_bounds__(256) pair_scan_kernel(const void *__restrict__
   if (vid >= nb) return;
   const uint32_t *order = ws_ptr<uint32_t>(ws, h.ws.vis_val[st[S_DEPTH_CUR] ? 1 : 0]);
   const uint32_t *nact = ws_ptr<uint32_t>(ws, h.ws.nact);
-  const uint64_t base = (uint64_t)vid * kScanChunk + (uint64_t)threadIdx.x * kScanItems;
-  uint32_t cnt[kScanItems];
+  const uint64_t base = (uint64_t)vid * kScanChunk + (uint64_t)threadIdx.x * kCompactItems;
+  uint32_t cnt[kCompactItems];
   uint32_t ts = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
+  for (int k = 0; k < kCompactItems; ++k) {
     const uint64_t i = base + k;
     cnt[k] = i < nvis ? nact[order[i]] : 0u;
     ts += cnt[k];
   }
   uint32_t tot;
-  const uint32_t ex = block_exclusive_scan(ts, &tot);
+  const uint32_t ex = block_exclusive_scan<kCompactBlock / 64>(ts, &tot);
   __shared__ uint64_t s_prefix;
   if (threadIdx.x < 64) {
     const uint64_t p = lookback64(ws_ptr<uint64_t>(ws, h.ws.lb_emit), vid, tot, st + S_ERROR);
@@ -664,7 +668,7 @@ __global__ void __launch_bounds__(256) pair_scan_kernel(const void *__restrict__
   uint32_t *off = ws_ptr<uint32_t>(ws, h.ws.pair_off);
   uint64_t o = prefix + ex;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
+  for (int k = 0; k < kCompactItems; ++k) {
     const uint64_t i = base + k;
     if (i < nvis) off[i] = (uint32_t)(o < cap ? o : cap);
     o += cnt[k];
@@ -878,7 +882,7 @@ void launch_recount(const void *d_desc, const Header &h, void *ws, hipStream_t s
 void launch_depth_sort(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
   if (h.n_records == 0) return;
   uint32_t *st = ws_ptr<uint32_t>(ws, h.ws.status);
-  hipLaunchKernelGGL(compact_kernel, dim3((unsigned)chunks_of(h.n_records)), dim3(256), 0, s, d_desc, ws);
+  hipLaunchKernelGGL(compact_kernel, dim3((unsigned)chunks_of(h.n_records)), dim3(kCompactBlock), 0, s, d_desc, ws);
   uint32_t *keys[2] = {ws_ptr<uint32_t>(ws, h.ws.vis_key[0]), ws_ptr<uint32_t>(ws, h.ws.vis_key[1])};
   uint32_t *vals[2] = {ws_ptr<uint32_t>(ws, h.ws.vis_val[0]), ws_ptr<uint32_t>(ws, h.ws.vis_val[1])};
   radix_sort(keys, vals, h.n_records, st + S_NVIS, 32, 1, 1, ws_ptr<uint32_t>(ws, h.ws.dhist),
@@ -887,7 +891,7 @@ void launch_depth_sort(const void *d_desc, const Header &h, void *ws, hipStream_
 
 void launch_emit(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
   if (h.n_records == 0) return;
-  hipLaunchKernelGGL(pair_scan_kernel, dim3((unsigned)chunks_of(h.n_records)), dim3(256), 0, s, d_desc, ws);
+  hipLaunchKernelGGL(pair_scan_kernel, dim3((unsigned)chunks_of(h.n_records)), dim3(kCompactBlock), 0, s, d_desc, ws);
   hipLaunchKernelGGL(emit_kernel, dim3(blocks_for(h.n_records)), dim3(256), 0, s, d_desc, ws);
 }
 
