@@ -825,16 +825,28 @@ __global__ void __launch_bounds__(256) emit_kernel(const void *__restrict__ desc
 
 // ------------------------------------------------------------ ranges
 
+// Tile ranges from the tile-sorted pair keys: every thread takes 4
+// consecutive pairs and marks where a tile's run starts and ends.
+constexpr int kRangeItems = 4;
 __global__ void __launch_bounds__(256) ranges_kernel(const void *__restrict__ desc, void *__restrict__ ws,
                                                      const uint32_t *__restrict__ tiles) {
   const Header &h = *header(desc);
   const uint32_t np = status_of(ws, h)[S_NPAIRS];
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= np) return;
+  const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRangeItems;
+  if (i0 >= np) return;
   uint2 *ranges = ws_ptr<uint2>(ws, h.ws.ranges);
-  const uint32_t t = tiles[i];
-  if (i == 0 || tiles[i - 1] != t) ranges[t].x = (uint32_t)i;
-  if (i + 1 == np || tiles[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+  uint32_t t[kRangeItems + 2];  // tiles[i0 - 1 .. i0 + kRangeItems]
+  t[0] = i0 > 0 ? tiles[i0 - 1] : 0xffffffffu;
+#pragma unroll
+  for (int k = 0; k <= kRangeItems; ++k) t[k + 1] = i0 + k < np ? tiles[i0 + k] : 0xffffffffu;
+#pragma unroll
+  for (int k = 0; k < kRangeItems; ++k) {
+    const uint64_t i = i0 + k;
+    if (i >= np) break;
+    const uint32_t tk = t[k + 1];
+    if (t[k] != tk) ranges[tk].x = (uint32_t)i;
+    if (t[k + 2] != tk) ranges[tk].y = (uint32_t)(i + 1);
+  }
 }
 
 // ------------------------------------------------------------- queue
@@ -902,7 +914,8 @@ void launch_tile_sort(const void *d_desc, const Header &h, void *ws, hipStream_t
   radix_sort(keys, vals, h.pair_capacity, st + S_NPAIRS, (int)h.tile_bits, 0, 1, ws_ptr<uint32_t>(ws, h.ws.thist),
              ws_ptr<uint32_t>(ws, h.ws.rtable), st, -1, s);
   const uint32_t *sorted_tiles = ws_ptr<uint32_t>(ws, h.ws.sorted_key);
-  hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for(h.pair_capacity)), dim3(256), 0, s, d_desc, ws, sorted_tiles);
+  hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for((h.pair_capacity + kRangeItems - 1) / kRangeItems)), dim3(256), 0, s,
+                     d_desc, ws, sorted_tiles);
   if (h.cfg.persistent) {
     // LPT queue: one stable radix pass on the length bucket, so tiles of a
     // bucket keep their (render, row-major) order and stay spatially close
