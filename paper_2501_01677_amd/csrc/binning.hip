@@ -413,27 +413,28 @@ __device__ inline PassPlan plan_pass(const uint32_t *hist, uint64_t n, int pass,
   return pp;
 }
 
-// Pass part 1: digit counts of every chunk -> table[digit][chunk].  RI keys
-// per thread: chunks of 256 RI keys.
-template <int RI>
-__global__ void __launch_bounds__(256) chunk_count_kernel(const uint32_t *keys0, const uint32_t *keys1,
-                                                          const uint32_t *n_dev, uint64_t n_bound, int pass,
-                                                          int passes, int dbits, int dynamic, const uint32_t *hist,
-                                                          uint32_t *table, uint32_t nb_bound) {
+// Pass part 1: digit counts of every chunk -> table[digit][chunk].  NW
+// waves of RI keys per thread: chunks of 64 NW RI keys.
+template <int RI, int NW>
+__global__ void __launch_bounds__(64 * NW) chunk_count_kernel(const uint32_t *keys0, const uint32_t *keys1,
+                                                              const uint32_t *n_dev, uint64_t n_bound, int pass,
+                                                              int passes, int dbits, int dynamic, const uint32_t *hist,
+                                                              uint32_t *table, uint32_t nb_bound) {
+  constexpr int NT = 64 * NW;
   __shared__ uint32_t hs[kRadixBins];
   const uint64_t n = bounded_count(n_dev, n_bound);
   const PassPlan pp = plan_pass(hist, n, pass, passes, dynamic);
   if (pp.skip) return;
   const uint32_t c = blockIdx.x;
-  hs[threadIdx.x] = 0;
+  if (threadIdx.x < kRadixBins) hs[threadIdx.x] = 0;
   __syncthreads();
   const uint32_t *kin = pp.parity ? keys1 : keys0;
   const int shift = dbits * pass;
   const uint32_t dmask = (1u << dbits) - 1u;
-  const uint64_t base = (uint64_t)c * (RI * kScanBlock);
+  const uint64_t base = (uint64_t)c * (RI * NT);
 #pragma unroll
   for (int r = 0; r < RI; ++r) {
-    const uint64_t i = base + (uint64_t)r * kScanBlock + threadIdx.x;
+    const uint64_t i = base + (uint64_t)r * NT + threadIdx.x;
     if (i < n) atomicAdd(&hs[(kin[i] >> shift) & dmask], 1u);
   }
   __syncthreads();
@@ -498,23 +499,25 @@ __global__ void __launch_bounds__(kDigitScanBlock) chunk_scan_kernel(const uint3
   }
 }
 
-// Pass part 3: stable scatter (chunks of 256 RI keys).  Each wave ranks its own contiguous quarter
-// of the chunk, 64 keys at a time, against wave-private running counts (no
-// workgroup barriers); waves are ordered by index and chunks by the table.
-template <int RI>
-__global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uint32_t *vals0, uint32_t *keys1,
-                                                            uint32_t *vals1, const uint32_t *n_dev,
-                                                            uint64_t n_bound, int pass, int passes, int dbits,
-                                                            int dynamic, const uint32_t *hist, const uint32_t *table,
-                                                            uint32_t nb_bound, uint32_t *st, int cur_word) {
-  __shared__ uint32_t wrun[4][kRadixBins];  // per-wave running digit counts
-  __shared__ uint32_t woff[4][kRadixBins];  // output position of each wave's first key of a digit
+// Pass part 3: stable scatter (chunks of 64 NW RI keys).  Each wave ranks
+// its own contiguous 1/NW of the chunk, 64 keys at a time, against
+// wave-private running counts (no workgroup barriers); waves are ordered by
+// index and chunks by the table.
+template <int RI, int NW>
+__global__ void __launch_bounds__(64 * NW) chunk_scatter_kernel(uint32_t *keys0, uint32_t *vals0, uint32_t *keys1,
+                                                                uint32_t *vals1, const uint32_t *n_dev,
+                                                                uint64_t n_bound, int pass, int passes, int dbits,
+                                                                int dynamic, const uint32_t *hist,
+                                                                const uint32_t *table, uint32_t nb_bound, uint32_t *st,
+                                                                int cur_word) {
+  __shared__ uint32_t wrun[NW][kRadixBins];  // per-wave running digit counts
+  __shared__ uint32_t woff[NW][kRadixBins];  // output position of each wave's first key of a digit
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t n = bounded_count(n_dev, n_bound);
   const PassPlan pp = plan_pass(hist, n, pass, passes, dynamic);
   const uint32_t c = blockIdx.x;
   if (c == 0 && tid == 0 && cur_word >= 0) st[cur_word] = (uint32_t)pp.final_parity;
-  constexpr int CH = RI * kScanBlock;
+  constexpr int CH = RI * 64 * NW;
   if (pp.skip || (uint64_t)c * CH >= n) return;
   const uint32_t *kin = pp.parity ? keys1 : keys0;
   const uint32_t *vin = pp.parity ? vals1 : vals0;
@@ -522,10 +525,11 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
   uint32_t *vout = pp.parity ? vals0 : vals1;
   const int shift = dbits * pass;
   const uint32_t dmask = (1u << dbits) - 1u;
-  for (int w = 0; w < 4; ++w) wrun[w][tid] = 0;
+  if (tid < kRadixBins)
+    for (int w = 0; w < NW; ++w) wrun[w][tid] = 0;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint64_t qbase = (uint64_t)c * CH + (uint64_t)wave * (CH / 4);
+  const uint64_t qbase = (uint64_t)c * CH + (uint64_t)wave * (CH / NW);
   uint32_t kk[RI], rk[RI];
 #pragma unroll
   for (int r = 0; r < RI; ++r) {
@@ -556,15 +560,24 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
   __shared__ uint32_t gbase[kRadixBins];   // output position of each digit's run
   __shared__ uint32_t skey[CH], sval[CH];
   {
-    const uint32_t c0 = wrun[0][tid], c1 = wrun[1][tid], c2 = wrun[2][tid], c3 = wrun[3][tid];
+    uint32_t cw[NW], tot_d = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      cw[w] = tid < kRadixBins ? wrun[w][tid] : 0u;
+      tot_d += cw[w];
+    }
     uint32_t tot;
-    const uint32_t cb = block_exclusive_scan(c0 + c1 + c2 + c3, &tot);
-    cbase[tid] = cb;
-    gbase[tid] = (uint32_t)tid <= dmask ? table[(uint64_t)tid * nb_bound + c] : 0u;
-    woff[0][tid] = cb;
-    woff[1][tid] = cb + c0;
-    woff[2][tid] = cb + c0 + c1;
-    woff[3][tid] = cb + c0 + c1 + c2;
+    const uint32_t cb = block_exclusive_scan<NW>(tot_d, &tot);
+    if (tid < kRadixBins) {
+      cbase[tid] = cb;
+      gbase[tid] = (uint32_t)tid <= dmask ? table[(uint64_t)tid * nb_bound + c] : 0u;
+      uint32_t o = cb;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        woff[w][tid] = o;
+        o += cw[w];
+      }
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -579,7 +592,7 @@ __global__ void __launch_bounds__(256) chunk_scatter_kernel(uint32_t *keys0, uin
   __syncthreads();
   const uint64_t cstart = (uint64_t)c * CH;
   const uint32_t cnt = (uint32_t)min((uint64_t)CH, n - cstart);
-  for (uint32_t i = tid; i < cnt; i += kScanBlock) {
+  for (uint32_t i = tid; i < cnt; i += 64 * NW) {
     const uint32_t key = skey[i];
     const uint32_t d = (key >> shift) & dmask;
     const uint32_t pos = gbase[d] + (i - cbase[d]);
@@ -607,21 +620,22 @@ void radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint64_t n_bound, const ui
     unsigned hb = nb < 2048 ? nb : 2048;
     hipLaunchKernelGGL(digit_hist_kernel, dim3(hb), dim3(256), 0, s, keys[0], n_dev, n_bound, passes, dbits, hist);
   }
+  // eight waves per chunk: each ranks 64 RI keys of the chunk
   for (int p = 0; p < passes; ++p) {
     if (big)
-      hipLaunchKernelGGL(chunk_count_kernel<2 * kRadixItems>, dim3(nb), dim3(256), 0, s, keys[0], keys[1], n_dev,
+      hipLaunchKernelGGL((chunk_count_kernel<kRadixItems, 8>), dim3(nb), dim3(512), 0, s, keys[0], keys[1], n_dev,
                          n_bound, p, passes, dbits, dynamic, hist, table, nb);
     else
-      hipLaunchKernelGGL(chunk_count_kernel<kRadixItems>, dim3(nb), dim3(256), 0, s, keys[0], keys[1], n_dev,
+      hipLaunchKernelGGL((chunk_count_kernel<kRadixItems / 2, 8>), dim3(nb), dim3(512), 0, s, keys[0], keys[1], n_dev,
                          n_bound, p, passes, dbits, dynamic, hist, table, nb);
     hipLaunchKernelGGL(chunk_scan_kernel, dim3(1u << dbits), dim3(kDigitScanBlock), 0, s, n_dev, n_bound, p, passes,
                        dynamic, hist, table, nb, chunk);
     if (big)
-      hipLaunchKernelGGL(chunk_scatter_kernel<2 * kRadixItems>, dim3(nb), dim3(256), 0, s, keys[0], vals[0], keys[1],
+      hipLaunchKernelGGL((chunk_scatter_kernel<kRadixItems, 8>), dim3(nb), dim3(512), 0, s, keys[0], vals[0], keys[1],
                          vals[1], n_dev, n_bound, p, passes, dbits, dynamic, hist, table, nb, st, cur_word);
     else
-      hipLaunchKernelGGL(chunk_scatter_kernel<kRadixItems>, dim3(nb), dim3(256), 0, s, keys[0], vals[0], keys[1],
-                         vals[1], n_dev, n_bound, p, passes, dbits, dynamic, hist, table, nb, st, cur_word);
+      hipLaunchKernelGGL((chunk_scatter_kernel<kRadixItems / 2, 8>), dim3(nb), dim3(512), 0, s, keys[0], vals[0],
+                         keys[1], vals[1], n_dev, n_bound, p, passes, dbits, dynamic, hist, table, nb, st, cur_word);
   }
 }
 
