@@ -698,15 +698,20 @@ __global__ void __launch_bounds__(kCompactBlock) pair_scan_kernel(const void *__
 // spread of rectangle sizes.  The digit histograms of the emitted tile ids
 // (for the tile sort) are accumulated on the way.
 constexpr uint32_t kSegRows = 8;  // rectangle rows staged per record in emission
-__global__ void __launch_bounds__(256) emit_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+// 16 waves per workgroup: the workgroup's digit histogram goes to the global
+// one once per 1024 records (these few hundred words take every workgroup's
+// atomics).
+constexpr int kEmitBlock = 1024;
+__global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
   const Header &h = *header(desc);
   const uint32_t *st = status_of(ws, h);
   __shared__ uint32_t hs[4][kRadixBins];
-  __shared__ uint32_t s_seg[4][64][kSegRows];  // per wave, per owner record: row bits of its rectangle
+  __shared__ uint32_t s_seg[kEmitBlock / 64][64][kSegRows];  // per wave, per owner record: row bits of its rectangle
   const int passes = tile_passes(h.tile_bits);
   const int tdb = digit_bits_for(h.tile_bits);
   const uint32_t tmask = (1u << tdb) - 1u;
-  for (int q = 0; q < 4; ++q) hs[q][threadIdx.x] = 0;
+  if (threadIdx.x < kRadixBins)
+    for (int q = 0; q < 4; ++q) hs[q][threadIdx.x] = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const uint32_t nvis = st[S_NVIS];
@@ -833,8 +838,9 @@ __global__ void __launch_bounds__(256) emit_kernel(const void *__restrict__ desc
   }
   __syncthreads();
   uint32_t *th = ws_ptr<uint32_t>(ws, h.ws.thist);
-  for (int q = 0; q < passes; ++q)
-    if (hs[q][threadIdx.x]) atomicAdd(&th[q * kRadixBins + threadIdx.x], hs[q][threadIdx.x]);
+  if (threadIdx.x < kRadixBins)
+    for (int q = 0; q < passes; ++q)
+      if (hs[q][threadIdx.x]) atomicAdd(&th[q * kRadixBins + threadIdx.x], hs[q][threadIdx.x]);
 }
 
 // ------------------------------------------------------------ ranges
@@ -918,7 +924,7 @@ void launch_depth_sort(const void *d_desc, const Header &h, void *ws, hipStream_
 void launch_emit(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
   if (h.n_records == 0) return;
   hipLaunchKernelGGL(pair_scan_kernel, dim3((unsigned)chunks_of(h.n_records)), dim3(kCompactBlock), 0, s, d_desc, ws);
-  hipLaunchKernelGGL(emit_kernel, dim3(blocks_for(h.n_records)), dim3(256), 0, s, d_desc, ws);
+  hipLaunchKernelGGL(emit_kernel, dim3(blocks_for(h.n_records, kEmitBlock)), dim3(kEmitBlock), 0, s, d_desc, ws);
 }
 
 void launch_tile_sort(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
