@@ -491,24 +491,27 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
     }
     GS = Tf * (gch[0] * h.cfg.bg[0] + gch[1] * h.cfg.bg[1] + gch[2] * h.cfg.bg[2]);
   }
-  if (threadIdx.x == 0) *smax = -1;
-  __syncthreads();
-  if (last >= 0) atomicMax(smax, last);
-  __syncthreads();
-  const int maxlast = *smax;
-  if (maxlast < (int)rg.x) return;  // uniform: no pixel blended anything
-  const uint32_t end = (uint32_t)maxlast + 1;
-  // With MM, the largest last-blended index of this wave's pixels: records
-  // past it contribute to none of them and stay out of the wave's lists.
-  // (The lane-exchange form keeps every record of the tile's range; the
-  // limit costs it a wave of occupancy.)
-  int32_t wlast = maxlast;
+  // the tile's largest last-blended index (with MM from a wave maximum by
+  // lane exchanges and one LDS atomic per wave; the lane-exchange form keeps
+  // per-lane atomics, whose registers it cannot spare)
+  int32_t wlast = last;
   if constexpr (MM) {
-    wlast = last;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, __shfl_xor(wlast, o, 64));
     wlast = __builtin_amdgcn_readfirstlane(wlast);  // uniform: keep it scalar
   }
+  if (threadIdx.x == 0) *smax = -1;
+  __syncthreads();
+  if ((!MM || (threadIdx.x & 63) == 0) && wlast >= 0) atomicMax(smax, wlast);
+  __syncthreads();
+  const int maxlast = *smax;
+  if (maxlast < (int)rg.x) return;  // uniform: no pixel blended anything
+  const uint32_t end = (uint32_t)maxlast + 1;
+  // With MM, records past the wave's own largest last-blended index
+  // contribute to none of its pixels and stay out of its lists.  (The
+  // lane-exchange form keeps every record of the tile's range; the limit
+  // costs it a wave of occupancy.)
+  if constexpr (!MM) wlast = maxlast;
   const int lane = threadIdx.x & 63;
   // the features of the reduction (see flush_records), fixed for the tile:
   // the output gradients of the other pixels come through the wave's buffer
