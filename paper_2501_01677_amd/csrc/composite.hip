@@ -495,14 +495,12 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
   // lane exchanges and one LDS atomic per wave; the lane-exchange form keeps
   // per-lane atomics, whose registers it cannot spare)
   int32_t wlast = last;
-  if constexpr (MM) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, __shfl_xor(wlast, o, 64));
-    wlast = __builtin_amdgcn_readfirstlane(wlast);  // uniform: keep it scalar
-  }
+  for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, __shfl_xor(wlast, o, 64));
+  wlast = __builtin_amdgcn_readfirstlane(wlast);  // uniform: keep it scalar
   if (threadIdx.x == 0) *smax = -1;
   __syncthreads();
-  if ((!MM || (threadIdx.x & 63) == 0) && wlast >= 0) atomicMax(smax, wlast);
+  if ((threadIdx.x & 63) == 0 && wlast >= 0) atomicMax(smax, wlast);
   __syncthreads();
   const int maxlast = *smax;
   if (maxlast < (int)rg.x) return;  // uniform: no pixel blended anything
@@ -697,7 +695,7 @@ __global__ void __launch_bounds__(T *T) forward_kernel(const void *__restrict__ 
 // constants spill to scratch outside the record loop), 4 waves per SIMD
 // otherwise.
 template <int T, bool MM>
-__global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(MM ? (T == 16 ? 5 : 4) : 1))) backward_kernel(const void *__restrict__ desc, void *__restrict__ ws,
+__global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(MM ? (T == 16 ? 5 : 4) : 8))) backward_kernel(const void *__restrict__ desc, void *__restrict__ ws,
                                                          const uint32_t *__restrict__ vals) {
   constexpr int NT = bwd_batch_of<T, MM>();
   __shared__ float4 srec[NT][4];
