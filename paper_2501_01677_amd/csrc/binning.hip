@@ -347,6 +347,7 @@ __global__ void __launch_bounds__(kCompactBlock) compact_kernel(const void *__re
     for (int p = 0; p < kDepthPasses; ++p) hs[p][threadIdx.x] = 0;
   __syncthreads();
   uint64_t pos = prefix + ex;
+  const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int k = 0; k < kCompactItems; ++k) {
     const uint64_t i = base + k;
@@ -357,7 +358,22 @@ __global__ void __launch_bounds__(kCompactBlock) compact_kernel(const void *__re
       ++pos;
     }
     if (f[k])
-      for (int p = 0; p < kDepthPasses; ++p) atomicAdd(&hs[p][(key >> (kRadixBits * p)) & (kRadixBins - 1)], 1u);
+      for (int p = 0; p < kDepthPasses - 1; ++p)
+        atomicAdd(&hs[p][(key >> (kRadixBits * p)) & (kRadixBins - 1)], 1u);
+    // The top digit (sign and high exponent bits) is usually the same for
+    // the whole wave: then one lane adds the wave's count instead of every
+    // lane hitting the same LDS word.
+    const uint32_t top = key >> (kRadixBits * (kDepthPasses - 1));
+    const uint64_t act = __ballot(f[k]);
+    if (act) {
+      const uint32_t ref = __shfl(top, __ffsll((unsigned long long)act) - 1, 64);
+      const bool uniform = __ballot(f[k] && top != ref) == 0ull;
+      if (uniform) {
+        if (lane == __ffsll((unsigned long long)act) - 1) atomicAdd(&hs[kDepthPasses - 1][ref], (uint32_t)__popcll(act));
+      } else if (f[k]) {
+        atomicAdd(&hs[kDepthPasses - 1][top], 1u);
+      }
+    }
   }
   __syncthreads();
   uint32_t *dh = ws_ptr<uint32_t>(ws, h.ws.dhist);
