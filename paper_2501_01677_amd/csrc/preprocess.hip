@@ -367,6 +367,40 @@ __device__ __forceinline__ void put_grad(float *gp, const float *param, uint64_t
   pp[idx] = p;
 }
 
+// The same for G parameters at idx + k * stride. With Adam, every
+// parameter and moment of the group is loaded before any is stored: the
+// stores may alias later loads as far as the compiler knows, so one
+// parameter at a time would cost a memory round trip each.
+template <bool ADAM, int G>
+__device__ __forceinline__ void put_grads(float *gp, const float *param, uint64_t idx, uint64_t stride, const float *g,
+                                          const AdamArgs &A, float c1, float c2) {
+  if constexpr (!ADAM) {
+#pragma unroll
+    for (int k = 0; k < G; ++k) gp[idx + k * stride] = g[k];
+    return;
+  }
+  float *pm = gp + A.m_off, *pv = gp + A.v_off;
+  float *pp = const_cast<float *>(param);
+  float m[G], v[G], p[G];
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    m[k] = pm[idx + k * stride];
+    v[k] = pv[idx + k * stride];
+    p[k] = pp[idx + k * stride];
+  }
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    const uint64_t e = idx + k * stride;
+    if (A.write_grads) gp[e] = g[k];
+    m[k] = A.b1 * m[k] + (1.f - A.b1) * g[k];
+    v[k] = A.b2 * v[k] + (1.f - A.b2) * g[k] * g[k];
+    p[k] -= A.lr * (m[k] * c1) / (sqrtf(v[k] * c2) + A.eps);
+    pm[e] = m[k];
+    pv[e] = v[k];
+    pp[e] = p[k];
+  }
+}
+
 // With Adam folded in, degree 3 would take 184 VGPRs (2 waves per SIMD);
 // 3 waves fit in 166 without spilling.
 template <int D, bool ADAM>
@@ -532,25 +566,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) b
   // sequence, so each gradient cache line is written once (a separate
   // zero-writing branch made every line of a mixed wave be written twice).
   const float c1 = ADAM ? A.coef[0] : 1.f, c2 = ADAM ? A.coef[1] : 1.f;
-  if (gm)
-    for (int k = 0; k < 3; ++k) put_grad<ADAM>(gm, S.means, k * n + i, gmean[k], A, c1, c2);
-  if (gl)
-    for (int k = 0; k < 3; ++k) put_grad<ADAM>(gl, S.log_scales, k * n + i, gs[k] * g.s[k], A, c1, c2);
+  if (gm) put_grads<ADAM, 3>(gm, S.means, i, n, gmean, A, c1, c2);
+  if (gl) {
+    const float v[3] = {gs[0] * g.s[0], gs[1] * g.s[1], gs[2] * g.s[2]};
+    put_grads<ADAM, 3>(gl, S.log_scales, i, n, v, A, c1, c2);
+  }
   if (gq) {
     float gw, gx, gy, gz;
     quat_rot_vjp(g.qw, g.qx, g.qy, g.qz, gM, gw, gx, gy, gz);
     // through q / |q|
     const float dot = gw * g.qw + gx * g.qx + gy * g.qy + gz * g.qz;
     const float inv = 1.f / g.qn;
-    put_grad<ADAM>(gq, S.quats, i, (gw - dot * g.qw) * inv, A, c1, c2);
-    put_grad<ADAM>(gq, S.quats, n + i, (gx - dot * g.qx) * inv, A, c1, c2);
-    put_grad<ADAM>(gq, S.quats, 2 * n + i, (gy - dot * g.qy) * inv, A, c1, c2);
-    put_grad<ADAM>(gq, S.quats, 3 * n + i, (gz - dot * g.qz) * inv, A, c1, c2);
+    const float v[4] = {(gw - dot * g.qw) * inv, (gx - dot * g.qx) * inv, (gy - dot * g.qy) * inv,
+                        (gz - dot * g.qz) * inv};
+    put_grads<ADAM, 4>(gq, S.quats, i, n, v, A, c1, c2);
   }
   if (go_) put_grad<ADAM>(go_, S.logits, i, go * g.o * (1.f - g.o), A, c1, c2);
   if (gsh_) {
+    constexpr int G = (3 * K) % 8 == 0 ? 8 : 3;
 #pragma unroll
-    for (int j = 0; j < 3 * K; ++j) put_grad<ADAM>(gsh_, S.sh, j * n + i, gsh[j], A, c1, c2);
+    for (int j = 0; j < 3 * K; j += G) put_grads<ADAM, G>(gsh_, S.sh, (uint64_t)j * n + i, n, gsh + j, A, c1, c2);
   }
 }
 
