@@ -128,18 +128,20 @@ __global__ void __launch_bounds__(256) loss_pixels_kernel(const void *__restrict
     if (u >= 0 && u < W && v >= 0 && v < H) {
       f = 4;
       const uint64_t p = (uint64_t)v * W + u;
-      if (rd.mask == nullptr || rd.mask[p]) {
-        f |= 2;
-        const float d = rd.o_depth[p];
-        if (d > 0.f) {
-          f |= 1;
-          px = d * (((float)u + 0.5f - cx) / fx);
-          py = d * (((float)v + 0.5f - cy) / fy);
-          pz = d;
-        }
-        const int iu = u - x0, iv = v - y0;
-        if (iu >= 0 && iu < kLB && iv >= 0 && iv < kLB) any = 1;
+      // depth is read together with the mask (not after it), and used only
+      // where the pixel is masked
+      const float d = rd.o_depth[p];
+      const bool m = rd.mask == nullptr || rd.mask[p];
+      const float dm = m ? d : 0.f;
+      if (m) f |= 2;
+      if (dm > 0.f) {
+        f |= 1;
+        px = dm * (((float)u + 0.5f - cx) / fx);
+        py = dm * (((float)v + 0.5f - cy) / fy);
+        pz = dm;
       }
+      const int iu = u - x0, iv = v - y0;
+      if (m && iu >= 0 && iu < kLB && iv >= 0 && iv < kLB) any = 1;
     }
     sF[k] = (uint8_t)f;
     sP[0][k] = px;
@@ -155,8 +157,31 @@ __global__ void __launch_bounds__(256) loss_pixels_kernel(const void *__restrict
   float e_sum = 0.f;
 
   // normal term on the 18 x 18 ring: values (inner cells), rendered-normal
-  // gradients (inner cells) and dL/d(dPx), dL/d(dPy) (every cell)
-  for (int k = threadIdx.x; k < kGX * kGX; k += 256) {
+  // gradients (inner cells) and dL/d(dPx), dL/d(dPy) (every cell).  A thread
+  // covers at most two cells: both cells' rendered normals are loaded before
+  // any gradient is stored, and the stores wait until after both.
+  static_assert(kGX * kGX <= 2 * 256, "two cells per thread");
+  float Nc[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int k = threadIdx.x + 256 * it;
+    if (k < kGX * kGX) {
+      const int gx = k % kGX, gy = k / kGX;
+      if (sF[(gy + 1) * kSX + (gx + 1)] & 1) {
+        const uint64_t p = (uint64_t)(y0 - 1 + gy) * W + (x0 - 1 + gx);
+        Nc[it][0] = rd.o_normal[p];
+        Nc[it][1] = rd.o_normal[plane + p];
+        Nc[it][2] = rd.o_normal[2 * plane + p];
+      }
+    }
+  }
+  float gNs[2][3];
+  uint64_t pst[2];
+  bool st[2] = {false, false};
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int k = threadIdx.x + 256 * it;
+    if (k >= kGX * kGX) break;
     const int gx = k % kGX, gy = k / kGX;
     const int s = (gy + 1) * kSX + (gx + 1);
     const int u = x0 - 1 + gx, v = y0 - 1 + gy;
@@ -179,8 +204,7 @@ __global__ void __launch_bounds__(256) loss_pixels_kernel(const void *__restrict
         const float c1 = ay[2] * ax[0] - ay[0] * ax[2];
         const float c2 = ay[0] * ax[1] - ay[1] * ax[0];
         const float cl2 = c0 * c0 + c1 * c1 + c2 * c2;
-        const uint64_t p = (uint64_t)v * W + u;
-        const float N0 = rd.o_normal[p], N1 = rd.o_normal[plane + p], N2 = rd.o_normal[2 * plane + p];
+        const float N0 = Nc[it][0], N1 = Nc[it][1], N2 = Nc[it][2];
         const float nl = sqrtf(N0 * N0 + N1 * N1 + N2 * N2);
         if (cl2 > 0.f && nl > lp.eps) {
           const float il = 1.f / sqrtf(cl2), inl = 1.f / nl;
@@ -224,13 +248,20 @@ __global__ void __launch_bounds__(256) loss_pixels_kernel(const void *__restrict
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) sG[c][k] = G[c];
-    if (inner && (f & 2)) {
-      const uint64_t p = (uint64_t)v * W + u;
-      float *gn = const_cast<float *>(rd.g_normal);
-      gn[p] = gN[0];
-      gn[plane + p] = gN[1];
-      gn[2 * plane + p] = gN[2];
-    }
+    st[it] = inner && (f & 2);
+    pst[it] = (uint64_t)v * W + u;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gNs[it][c] = gN[c];
+  }
+  {
+    float *gn = const_cast<float *>(rd.g_normal);
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+      if (st[it]) {
+        gn[pst[it]] = gNs[it][0];
+        gn[plane + pst[it]] = gNs[it][1];
+        gn[2 * plane + pst[it]] = gNs[it][2];
+      }
   }
   __syncthreads();
 
@@ -244,9 +275,15 @@ __global__ void __launch_bounds__(256) loss_pixels_kernel(const void *__restrict
     if (f & 2) {
       const uint64_t p = (uint64_t)v * W + u;
       float *grgb = const_cast<float *>(rd.g_rgb);
+      float orgb[3], trgb[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float df = rd.o_rgb[c * plane + p] - gt[c * plane + p];
+        orgb[c] = rd.o_rgb[c * plane + p];
+        trgb[c] = gt[c * plane + p];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float df = orgb[c] - trgb[c];
         r_sum += fabsf(df);
         grgb[c * plane + p] = sgnf(df) * kr;
       }
