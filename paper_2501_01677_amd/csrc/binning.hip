@@ -775,12 +775,26 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict
       const uint32_t wpr = (txn + 31) / 32;
       const uint32_t wd = x1 - x0;
       const uint32_t sh = x0 & 31;
-      for (uint32_t r = 0; r < y1 - y0; ++r) {
-        const uint32_t *row = am_all + amoff + (y0 + r) * wpr + x0 / 32;
-        uint64_t two = row[0];
-        if (sh + wd > 32) two |= (uint64_t)row[1] << 32;
-        seg[r] = (uint32_t)(two >> sh) & (wd == 32 ? ~0u : ((1u << wd) - 1u));
+      const uint32_t nr = y1 - y0;
+      // every row's words are loaded before the first is used, so the rows
+      // cost one round trip rather than one each
+      uint32_t lo[kSegRows], hi[kSegRows];
+#pragma unroll
+      for (uint32_t r = 0; r < kSegRows; ++r) {
+        lo[r] = 0u;
+        hi[r] = 0u;
+        if (r < nr) {
+          const uint32_t *row = am_all + amoff + (y0 + r) * wpr + x0 / 32;
+          lo[r] = row[0];
+          if (sh + wd > 32) hi[r] = row[1];
+        }
       }
+#pragma unroll
+      for (uint32_t r = 0; r < kSegRows; ++r)
+        if (r < nr) {
+          const uint64_t two = (uint64_t)lo[r] | ((uint64_t)hi[r] << 32);
+          seg[r] = (uint32_t)(two >> sh) & (wd == 32 ? ~0u : ((1u << wd) - 1u));
+        }
     }
     const uint64_t staged_mask = __ballot(staged);
     __builtin_amdgcn_wave_barrier();
