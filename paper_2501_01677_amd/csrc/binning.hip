@@ -319,13 +319,17 @@ __global__ void __launch_bounds__(kCompactBlock) compact_kernel(const void *__re
   const uint32_t vid = virtual_block(st + S_CTR_COMPACT);
   if (vid >= nb) return;
   const uint32_t *nact = ws_ptr<uint32_t>(ws, h.ws.nact);
+  const uint32_t *dkey = ws_ptr<uint32_t>(ws, h.ws.depth_key);
   const uint64_t base = (uint64_t)vid * kScanChunk + (uint64_t)threadIdx.x * kCompactItems;
-  uint32_t f[kCompactItems];
+  uint32_t f[kCompactItems], dk[kCompactItems];
   uint32_t ts = 0;
+  // the depth keys are loaded with the counts, ahead of the scan and the
+  // look-back (below, the stores would keep the compiler from hoisting them)
 #pragma unroll
   for (int k = 0; k < kCompactItems; ++k) {
     const uint64_t i = base + k;
     f[k] = (i < n && nact[i] > 0) ? 1u : 0u;
+    dk[k] = i < n ? dkey[i] : 0u;
     ts += f[k];
   }
   uint32_t tot;
@@ -338,7 +342,6 @@ __global__ void __launch_bounds__(kCompactBlock) compact_kernel(const void *__re
   __syncthreads();
   const uint64_t prefix = s_prefix;
   if (vid == nb - 1 && threadIdx.x == 0) st[S_NVIS] = (uint32_t)(prefix + tot);
-  const uint32_t *dkey = ws_ptr<uint32_t>(ws, h.ws.depth_key);
   uint32_t *ko = ws_ptr<uint32_t>(ws, h.ws.vis_key[0]);
   uint32_t *vo = ws_ptr<uint32_t>(ws, h.ws.vis_val[0]);
   // digit histograms of the depth keys for the radix passes
@@ -351,7 +354,7 @@ __global__ void __launch_bounds__(kCompactBlock) compact_kernel(const void *__re
 #pragma unroll
   for (int k = 0; k < kCompactItems; ++k) {
     const uint64_t i = base + k;
-    const uint32_t key = f[k] ? dkey[i] : 0u;
+    const uint32_t key = f[k] ? dk[k] : 0u;
     if (f[k]) {
       ko[pos] = key;
       vo[pos] = (uint32_t)i;
