@@ -544,17 +544,28 @@ __global__ void __launch_bounds__(64 * NW) chunk_scatter_kernel(uint32_t *keys0,
   uint32_t *vout = pp.parity ? vals0 : vals1;
   const int shift = dbits * pass;
   const uint32_t dmask = (1u << dbits) - 1u;
+  // The keys, the values and this chunk's output offset of each digit are
+  // all loaded here, so they arrive in one round trip (after the barriers
+  // below the compiler could not move the later loads up).
+  const uint32_t gb = (tid < kRadixBins && (uint32_t)tid <= dmask) ? table[(uint64_t)tid * nb_bound + c] : 0u;
+  const uint64_t qbase = (uint64_t)c * CH + (uint64_t)wave * (CH / NW);
+  uint32_t kin_r[RI], vv[RI];
+#pragma unroll
+  for (int r = 0; r < RI; ++r) {
+    const uint64_t i = qbase + (uint64_t)r * 64 + lane;
+    kin_r[r] = i < n ? kin[i] : 0u;
+    vv[r] = i < n ? vin[i] : 0u;
+  }
   if (tid < kRadixBins)
     for (int w = 0; w < NW; ++w) wrun[w][tid] = 0;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint64_t qbase = (uint64_t)c * CH + (uint64_t)wave * (CH / NW);
   uint32_t kk[RI], rk[RI];
 #pragma unroll
   for (int r = 0; r < RI; ++r) {
     const uint64_t i = qbase + (uint64_t)r * 64 + lane;
     const bool valid = i < n;
-    const uint32_t key = valid ? kin[i] : 0u;
+    const uint32_t key = kin_r[r];
     const uint32_t d = (key >> shift) & dmask;
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -589,7 +600,7 @@ __global__ void __launch_bounds__(64 * NW) chunk_scatter_kernel(uint32_t *keys0,
     const uint32_t cb = block_exclusive_scan<NW>(tot_d, &tot);
     if (tid < kRadixBins) {
       cbase[tid] = cb;
-      gbase[tid] = (uint32_t)tid <= dmask ? table[(uint64_t)tid * nb_bound + c] : 0u;
+      gbase[tid] = gb;
       uint32_t o = cb;
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
@@ -605,7 +616,7 @@ __global__ void __launch_bounds__(64 * NW) chunk_scatter_kernel(uint32_t *keys0,
       const uint32_t d = (kk[r] >> shift) & dmask;
       const uint32_t lp = woff[wave][d] + rk[r];
       skey[lp] = kk[r];
-      sval[lp] = vin[qbase + (uint64_t)r * 64 + lane];
+      sval[lp] = vv[r];
     }
   }
   __syncthreads();
