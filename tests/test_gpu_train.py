@@ -27,8 +27,8 @@ pytestmark = pytest.mark.gpu
 PARAMS = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
 
-def _prepared_scene(seed):
-    sc = scenes.small_scene(seed, n=160, width=52, height=44, sh_degree=2, n_views=2)
+def _prepared_scene(seed, sh_degree=2):
+    sc = scenes.small_scene(seed, n=160, width=52, height=44, sh_degree=sh_degree, n_views=2)
     rng = np.random.default_rng(seed + 1)
     renders, gts, refs = [], [], []
     for rd in sc.renders:
@@ -141,10 +141,12 @@ def test_device_step_adam_matches_host_step():
         np.testing.assert_allclose(y.cpu().numpy(), x.cpu().numpy(), rtol=1e-6, atol=1e-9)
 
 
+@pytest.mark.parametrize("sh_degree", [2, 3])
 @pytest.mark.parametrize("keep_grads", [False, True])
-def test_adam_folded_into_backward_matches_separate_update(keep_grads):
-    print(f"[case] fused backward+Adam keep_grads={keep_grads}", flush=True)
-    sc, gts, _ = _prepared_scene(403)
+def test_adam_folded_into_backward_matches_separate_update(keep_grads, sh_degree):
+    # degree 2 updates the SH coefficients in groups of 3, degree 3 in groups of 8
+    print(f"[case] fused backward+Adam keep_grads={keep_grads} sh_degree={sh_degree}", flush=True)
+    sc, gts, _ = _prepared_scene(403, sh_degree)
     lc = LossConfig(lambda_load=0.41)
     a = _trainer(sc, gts, lc, fused=False)
     b = _trainer(sc, gts, lc, fused=True, keep_grads=keep_grads)
