@@ -568,3 +568,124 @@ def test_tilted_plane_depth_with_rotated_camera():
     np.testing.assert_allclose(r["depth"][cov], ref, rtol=2e-5)
     # rendered normal faces the camera: n . ray < 0
     assert np.all((r["normal"][cov] * ray_c).sum(1) < 0)
+
+
+# ------------------------------------------- Jacobian clamp (reading R5)
+
+def _rodrigues(qq):
+    """Rotation of a unit quaternion (w, x, y, z) from its axis and angle."""
+    qq = np.asarray(qq, np.float64) / np.linalg.norm(qq)
+    w, x, y, z = qq
+    s = math.sqrt(x * x + y * y + z * z)
+    ang = 2 * math.atan2(s, w)
+    ax = np.array([x, y, z]) / max(s, 1e-300)
+    K = np.array([[0, -ax[2], ax[1]], [ax[2], 0, -ax[0]], [-ax[1], ax[0], 0]])
+    return np.eye(3) + math.sin(ang) * K + (1 - math.cos(ang)) * K @ K
+
+
+def _numerical_pinhole_jacobian(cam, p):
+    """2x3 Jacobian of the pinhole map (x, y, z) -> (fx x/z + cx, fy y/z + cy)
+    at camera point p, by FP64 central differences."""
+    def proj(tt):
+        return np.array([cam.fx * tt[0] / tt[2] + cam.cx, cam.fy * tt[1] / tt[2] + cam.cy])
+    h = 1e-6
+    return np.stack([(proj(p + h * e) - proj(p - h * e)) / (2 * h) for e in np.eye(3)], 1)
+
+
+def test_jacobian_clamp_beyond_the_lateral_limit():
+    """A Gaussian far off to the side is projected with the Jacobian of the
+    pinhole map taken at its mean pulled back to the lateral limit
+    1.3 x tan(half field of view) (the half image over the focal length) per
+    axis, at the same depth; its 2D mean is not clamped.  Three Gaussians:
+    clamped in x, clamped in y, clamped in both, under a rotated camera."""
+    W, H, f = 24, 20, 20.0
+    R, t = scenes.look_at([0.3, -0.2, -4.0], [0.1, 0.2, 0.0], up=(0.0, -1.0, 0.0))
+    cam = scenes.pinhole(W, H, f, f, 11.0, 10.5, R, t)
+    Rc, tc = cam.R.astype(np.float64), cam.t.astype(np.float64)
+    limx, limy = 1.3 * (W / 2) / cam.fx, 1.3 * (H / 2) / cam.fy
+    # camera-frame targets: x/z 1.4 limx; y/z -1.3 limy; both
+    cam_pts = np.array([[1.4 * limx * 3.0, 0.1, 3.0],
+                        [0.2, -1.3 * limy * 2.5, 2.5],
+                        [-1.25 * limx * 4.0, 1.2 * limy * 4.0, 4.0]])
+    means = (cam_pts - tc) @ Rc                       # world = R^T (x_c - t)
+    rng = np.random.default_rng(8)
+    ls = rng.uniform(-1.5, -0.5, (3, 3))
+    q = rng.normal(size=(3, 4))
+    gs = make_set(means, ls, q, np.zeros(3), colours=np.full((3, 3), 0.5))
+    prep = oc.prepare(gs, cam, None, CFG)
+    assert len(prep.dec.order) == 3
+    cov = prep.proj["cov2d"].numpy()
+    m2d = prep.proj["mean2d"].numpy()
+    k_of = {int(i): k for k, i in enumerate(prep.dec.order)}
+    teeth = []
+    for i in range(3):
+        k = k_of[i]
+        p = Rc @ gs.means[:, i].astype(np.float64) + tc
+        xr, yr = p[0] / p[2], p[1] / p[2]
+        clamped = np.array([np.clip(xr, -limx, limx) * p[2], np.clip(yr, -limy, limy) * p[2], p[2]])
+        J = _numerical_pinhole_jacobian(cam, clamped)
+        Rr = _rodrigues(gs.quats[:, i])
+        Sig = Rc @ Rr @ np.diag(np.exp(2 * gs.log_scales[:, i].astype(np.float64))) @ Rr.T @ Rc.T
+        ref = J @ Sig @ J.T + 0.3 * np.eye(2)
+        np.testing.assert_allclose(cov[k], [ref[0, 0], ref[0, 1], ref[1, 1]], rtol=1e-6, atol=1e-9)
+        # the 2D mean is the unclamped projection
+        np.testing.assert_allclose(m2d[k], [cam.fx * xr + cam.cx, cam.fy * yr + cam.cy], rtol=1e-12)
+        # the same covariance without the clamp, and with a limit of the whole
+        # image over the focal length, are far from it: the pin has teeth
+        for alt in (p, np.array([np.clip(xr, -2 * limx, 2 * limx) * p[2],
+                                 np.clip(yr, -2 * limy, 2 * limy) * p[2], p[2]])):
+            Ja = _numerical_pinhole_jacobian(cam, alt)
+            ra = Ja @ Sig @ Ja.T + 0.3 * np.eye(2)
+            teeth.append(np.abs(ra - ref).max() / np.abs(ref).max())
+    assert min(teeth) > 1e-3, teeth
+
+
+# ----------------------------------------------- Eq. 4 depth guard (R16)
+
+def test_depth_guard_on_an_edge_on_plane():
+    """Eq. 4 divides the blended distance by N . K^-1 p~; the reading sets the
+    depth (and its gradient) to 0 unless that denominator is below -1e-6.
+    One flat Gaussian whose plane is parallel to the ray of pixel (20, 16)
+    (tilted by eps): the denominator there is alpha (n . r), computed here
+    from an axis-angle rotation of the FP32 quaternion, and spans both sides
+    of -1e-6 and of 0."""
+    cam = scenes.pinhole(32, 32, 32.0, 32.0)
+    u, v = 20, 16
+    r = np.array([(u + 0.5 - cam.cx) / cam.fx, (v + 0.5 - cam.cy) / cam.fy, 1.0])
+    mean = at_pixel(cam, 16, 16, 3.0)
+    ls = [math.log(2.0), math.log(1.0), math.log(1e-3)]   # axis 2 is the normal
+
+    def one(eps):
+        n = np.array([1.0, 0.0, -r[0] + eps])
+        n /= np.linalg.norm(n)
+        e1 = np.array([0.0, 1.0, 0.0])
+        e0 = np.cross(e1, n)
+        Rm = np.stack([e0, e1, n], 1)
+        assert np.linalg.det(Rm) > 0
+        q = scenes._rot_to_quat(Rm[None])[:, 0]
+        return make_set([mean], [ls], [q], [logit(0.8)], colours=[[0.4, 0.5, 0.6]])
+
+    res0 = oc.render(one(0.0), cam, None, CFG, mode="brute", pixels=[[v, u]])
+    a0 = float(res0["alpha"][0])
+    assert a0 > 0.1
+    for target in (5e-7, -5e-7, -3e-6, 3e-6):
+        nrm = math.sqrt(1 + r[0] ** 2)
+        gs = one(target * nrm / a0)
+        res = oc.render(gs, cam, None, CFG, mode="brute", pixels=[[v, u]])
+        alpha, den = float(res["alpha"][0]), float(res["den"][0])
+        n_ind = _rodrigues(gs.quats[:, 0])[:, 2]
+        t_c = gs.means[:, 0].astype(np.float64)
+        assert n_ind @ t_c < 0                              # faces the camera: no flip
+        np.testing.assert_allclose(den, alpha * (n_ind @ r), rtol=1e-6, atol=1e-12)
+        assert abs(den - target) < 0.3 * abs(target)        # the intended band
+        depth = float(res["depth"][0])
+        gout = {"depth": np.zeros((cam.height, cam.width), np.float32)}
+        gout["depth"][v, u] = 1.0
+        g = oc.render_grad(gs, cam, None, CFG, gout, mode="brute", pixels=[[v, u]])
+        gmax = max(np.abs(x).max() for x in g.values())
+        if den < -1e-6:
+            # D / den, D = alpha (n . t) from the same independent normal
+            np.testing.assert_allclose(depth, alpha * (n_ind @ t_c) / den, rtol=1e-5)
+            assert gmax > 0
+        else:
+            assert depth == 0.0 and gmax == 0.0, (target, den, depth, gmax)
