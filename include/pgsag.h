@@ -68,7 +68,7 @@
 extern "C" {
 #endif
 
-#define PGSAG_ABI_VERSION 1
+#define PGSAG_ABI_VERSION 2
 #define PGSAG_NUM_STAGES 8
 
 typedef enum pgsag_status_code {
@@ -159,6 +159,18 @@ typedef struct pgsag_config {
         (less work per tile, twice the resident workgroups; best for short
         tile lists).  Any other value is an error. */
   int32_t bwd_reduce;
+  /* 0: the backward compositing pass adds each wave's per-record sums to
+        the record's 2D-gradient slot with float atomics, so the gradients
+        can differ in the last bits from run to run (addition order);
+     1: deterministic -- every (tile pair, wave) writes its sums to a slot of
+        its own, and a segmented reduction then adds each record's slots in
+        a fixed order (its tiles in row-major order, waves in index order).
+        Gradients are then bit-identical from run to run, between a batch
+        and the same renders launched one by one, and between the plain and
+        the persistent launch.  Costs workspace (4 + 64 x (tile/8)^2 bytes
+        per pair of capacity) and about twice the backward time.
+     Any other value is an error. */
+  int32_t deterministic;
 } pgsag_config;
 
 typedef struct pgsag_plan_info {
@@ -195,6 +207,10 @@ typedef struct pgsag_status {
   uint64_t pairs_needed; /* pairs the last forward/binning emitted or needed */
   uint32_t overflow;     /* 1 if pairs_needed > capacity (outputs invalid) */
   uint32_t n_visible;    /* records with at least one active tile */
+  uint32_t error;        /* non-zero if a single-pass scan of the binning gave
+                            up waiting for a predecessor's prefix (a bounded
+                            wait): that pass's outputs are invalid */
+  uint32_t reserved;
 } pgsag_status;
 
 /* PGSAG_ABI_VERSION of the loaded library. */
@@ -208,10 +224,12 @@ void pgsag_default_config(pgsag_config *cfg);
 
 /* Sizes the workspace and descriptor of a batch (host only, no device
  * work).  sets[n_sets] and renders[n_renders] are read for their sizes;
- * pair_capacity is the maximum number of (tile, Gaussian) pairs (1..2^32-1).
+ * pair_capacity is the maximum number of (tile, Gaussian) pairs (1..2^30-1).
  * Returns INVALID_ARGUMENT for n_sets < 1, n_renders < 1, a render whose set
- * index is out of range, width/height < 1 or > 65535*tile, sh_degree
- * outside 0..3, tile not in {8,16,32}, n < 0, or totals beyond 2^32-1. */
+ * index is out of range, width/height < 1 or > 65535 pixels, sh_degree
+ * outside 0..3, tile not in {8,16,32}, bwd_reduce or deterministic not 0/1,
+ * n < 0; UNSUPPORTED for more than 4096 renders, more than 64 renders of
+ * one set, 2^30 or more records or 2^32-1 or more tiles in the batch. */
 int pgsag_plan(const pgsag_config *cfg, const pgsag_gaussians *sets, int32_t n_sets,
                const pgsag_render *renders, int32_t n_renders, uint64_t pair_capacity,
                pgsag_plan_info *out);
@@ -258,7 +276,9 @@ int pgsag_backward(const void *host_desc, const void *dev_desc, void *workspace,
 int pgsag_binning(const void *host_desc, const void *dev_desc, void *workspace,
                   size_t workspace_bytes, void *stream);
 
-/* Copies the status word to *out and synchronises the stream. */
+/* Copies the status word of the last forward (or binning) to *out and
+ * synchronises the stream.  The outputs of that pass are valid only when
+ * both out->overflow and out->error are 0. */
 int pgsag_read_status(const void *host_desc, const void *workspace, pgsag_status *out,
                       void *stream);
 

@@ -9,7 +9,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpgsag.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 NUM_STAGES = 8
 STAGES = ("tile_mask", "preprocess", "depth_sort", "emit", "tile_sort", "composite",
           "backward_composite", "backward_preprocess")
@@ -53,7 +53,8 @@ class Config(C.Structure):
                 ("workgroups_per_cu", C.c_int32), ("alpha_min", C.c_float), ("t_min", C.c_float),
                 ("alpha_max", C.c_float), ("dilation", C.c_float), ("z_near", C.c_float),
                 ("fov_clamp", C.c_float), ("logit_min", C.c_float), ("depth_guard", C.c_float),
-                ("bg", C.c_float * 3), ("bwd_reduce", C.c_int32)]
+                ("bg", C.c_float * 3), ("bwd_reduce", C.c_int32),
+                ("deterministic", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -81,7 +82,8 @@ class AdamConfig(C.Structure):
 
 
 class Status(C.Structure):
-    _fields_ = [("pairs_needed", C.c_uint64), ("overflow", C.c_uint32), ("n_visible", C.c_uint32)]
+    _fields_ = [("pairs_needed", C.c_uint64), ("overflow", C.c_uint32), ("n_visible", C.c_uint32),
+                ("error", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 SYMBOLS = ("pgsag_version", "pgsag_last_error", "pgsag_default_config", "pgsag_plan", "pgsag_pack",

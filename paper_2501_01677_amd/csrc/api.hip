@@ -52,6 +52,8 @@ int validate(const pgsag_config *cfg, const pgsag_gaussians *sets, int32_t n_set
   if (n_renders > 4096) return fail(PGSAG_UNSUPPORTED, "at most 4096 renders per batch");
   if (cfg->bwd_reduce != 0 && cfg->bwd_reduce != 1)
     return fail(PGSAG_INVALID_ARGUMENT, "bwd_reduce must be 0 or 1 (got %d)", cfg->bwd_reduce);
+  if (cfg->deterministic != 0 && cfg->deterministic != 1)
+    return fail(PGSAG_INVALID_ARGUMENT, "deterministic must be 0 or 1 (got %d)", cfg->deterministic);
   if (cfg->persistent && (cfg->queue_chunk < 1 || cfg->queue_chunk > 64))
     return fail(PGSAG_INVALID_ARGUMENT, "queue_chunk must be in 1..64");
   if (cfg->persistent && (cfg->workgroups_per_cu < 1 || cfg->workgroups_per_cu > 16))
@@ -95,7 +97,7 @@ int validate(const pgsag_config *cfg, const pgsag_gaussians *sets, int32_t n_set
   return PGSAG_OK;
 }
 
-Layout make_layout(const Sizes &z, uint64_t cap, int n_renders) {
+Layout make_layout(const pgsag_config &cfg, const Sizes &z, uint64_t cap, int n_renders) {
   Layout L{};
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
@@ -123,6 +125,11 @@ Layout make_layout(const Sizes &z, uint64_t cap, int n_renders) {
   L.pix_T = take(z.n_pixels * 4);
   L.pix_last = take(z.n_pixels * 4);
   L.g2 = take(z.n_records * kG2 * 4);
+  if (cfg.deterministic) {
+    L.pair_rec = take(cap * 4);
+    L.part = take(cap * (uint64_t)waves_per_tile(cfg.tile) * kG2 * 4);
+    L.pair_inv = L.pair_val[(passes & 1) ^ 1];
+  }
   // contiguous zero-initialised region (status words first)
   L.zero_begin = off;
   const uint64_t status_at = take(S_WORDS * 4);
@@ -240,7 +247,7 @@ int pgsag_plan(const pgsag_config *cfg, const pgsag_gaussians *sets, int32_t n_s
   Sizes z;
   int rc = validate(cfg, sets, n_sets, renders, n_renders, pair_capacity, z);
   if (rc) return rc;
-  const Layout L = make_layout(z, pair_capacity, n_renders);
+  const Layout L = make_layout(*cfg, z, pair_capacity, n_renders);
   const DescLayout d = desc_layout(n_sets, n_renders);
   std::memset(out, 0, sizeof *out);
   out->workspace_bytes = L.end;
@@ -292,7 +299,7 @@ int pgsag_pack(const pgsag_config *cfg, const pgsag_gaussians *sets, const pgsag
   h->row_starts_off = d.row_starts_off;
   h->rec_starts_off = d.rec_starts_off;
   h->desc_bytes = d.bytes;
-  h->ws = make_layout(z, pair_capacity, n_renders);
+  h->ws = make_layout(*cfg, z, pair_capacity, n_renders);
   h->ws_bytes = h->ws.end;
   h->any_grads = set_grads != nullptr;
   for (int k = 0; k < 4; ++k) {
@@ -464,8 +471,10 @@ int run_backward(const Header *h, const void *dev_desc, void *workspace, const A
   StageTimer tm{events, s};
   launch_fill_u32(ws_ptr<uint32_t>(workspace, h->ws.g2), 0u, h->n_records * kG2, s);
   if (h->cfg.persistent) launch_fill_u32(ws_ptr<uint32_t>(workspace, h->ws.status) + S_QUEUE_BWD, 0u, 1, s);
+  if (h->cfg.deterministic) launch_det_clear(dev_desc, *h, workspace, s);
   tm.begin(PGSAG_STAGE_BACKWARD_COMPOSITE);
   launch_backward_composite(dev_desc, *h, workspace, s);
+  if (h->cfg.deterministic) launch_det_reduce(dev_desc, *h, workspace, s);
   tm.end(PGSAG_STAGE_BACKWARD_COMPOSITE);
   int rc;
   if ((rc = check_hip("backward composite"))) return rc;
@@ -531,7 +540,7 @@ int pgsag_read_status(const void *host_desc, const void *workspace, pgsag_status
   const Header *h = check_desc(host_desc);
   if (!h) return PGSAG_INVALID_ARGUMENT;
   if (!workspace || !out) return fail(PGSAG_INVALID_ARGUMENT, "null workspace or output");
-  uint32_t w[8];
+  uint32_t w[S_ERROR + 1];
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipMemcpyAsync(w, ws_ptr<uint32_t>(workspace, h->ws.status), sizeof w, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -539,6 +548,8 @@ int pgsag_read_status(const void *host_desc, const void *workspace, pgsag_status
   out->pairs_needed = (uint64_t)w[S_PAIRS_LO] | ((uint64_t)w[S_PAIRS_HI] << 32);
   out->overflow = w[S_OVERFLOW];
   out->n_visible = w[S_NVIS];
+  out->error = w[S_ERROR];
+  out->reserved = 0;
   return PGSAG_OK;
 }
 

@@ -779,6 +779,8 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict
     const uint32_t *am_all = ws_ptr<uint32_t>(ws, h.ws.amask);
     uint32_t *key_out = ws_ptr<uint32_t>(ws, h.ws.pair_key[0]);
     uint32_t *val_out = ws_ptr<uint32_t>(ws, h.ws.pair_val[0]);
+    const bool det = h.cfg.deterministic != 0;
+    uint32_t *prec = ws_ptr<uint32_t>(ws, h.ws.pair_rec);
     // Every lane, as owner of its record, stages the active-tile bits of its
     // rectangle's rows (bit 0 = column x0) in LDS once, for rectangles of at
     // most kSegRows rows and 32 columns; the pair lanes below then walk rows
@@ -874,8 +876,16 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict
             }
           }
         }
-        key_out[off0 + t] = gt;
-        val_out[off0 + t] = orec;
+        const uint64_t e = off0 + t;
+        key_out[e] = gt;
+        if (det) {
+          // the tile sort carries the emission index; the record follows
+          // it through pair_rec (det_fixup_kernel)
+          val_out[e] = (uint32_t)e;
+          prec[e] = orec;
+        } else {
+          val_out[e] = orec;
+        }
         for (int q = 0; q < passes; ++q) atomicAdd(&hs[q][(gt >> (tdb * q)) & tmask], 1u);
       }
     }
@@ -885,6 +895,22 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict
   if (threadIdx.x < kRadixBins)
     for (int q = 0; q < passes; ++q)
       if (hs[q][threadIdx.x]) atomicAdd(&th[q * kRadixBins + threadIdx.x], hs[q][threadIdx.x]);
+}
+
+// Deterministic mode: the tile sort has carried every pair's emission index
+// (record-major order: a record's pairs are consecutive, its tiles in
+// row-major order).  Put the record ids in place for the compositing passes
+// and keep the inverse permutation (emission index -> tile-sorted index),
+// which the backward's segmented reduction walks record by record.
+__global__ void __launch_bounds__(256) det_fixup_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+  const Header &h = *header(desc);
+  const uint32_t np = status_of(ws, h)[S_NPAIRS];
+  const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= np) return;
+  uint32_t *sv = ws_ptr<uint32_t>(ws, h.ws.sorted_val);
+  const uint32_t e = sv[j];
+  sv[j] = ws_ptr<const uint32_t>(ws, h.ws.pair_rec)[e];
+  ws_ptr<uint32_t>(ws, h.ws.pair_inv)[e] = (uint32_t)j;
 }
 
 // ------------------------------------------------------------ ranges
@@ -977,6 +1003,8 @@ void launch_tile_sort(const void *d_desc, const Header &h, void *ws, hipStream_t
   uint32_t *vals[2] = {ws_ptr<uint32_t>(ws, h.ws.pair_val[0]), ws_ptr<uint32_t>(ws, h.ws.pair_val[1])};
   radix_sort(keys, vals, h.pair_capacity, st + S_NPAIRS, (int)h.tile_bits, 0, 1, ws_ptr<uint32_t>(ws, h.ws.thist),
              ws_ptr<uint32_t>(ws, h.ws.rtable), st, -1, s);
+  if (h.cfg.deterministic)
+    hipLaunchKernelGGL(det_fixup_kernel, dim3(blocks_for(h.pair_capacity)), dim3(256), 0, s, d_desc, ws);
   const uint32_t *sorted_tiles = ws_ptr<uint32_t>(ws, h.ws.sorted_key);
   hipLaunchKernelGGL(ranges_kernel, dim3(blocks_for((h.pair_capacity + kRangeItems - 1) / kRangeItems)), dim3(256), 0, s,
                      d_desc, ws, sorted_tiles);

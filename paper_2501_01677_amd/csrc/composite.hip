@@ -332,6 +332,15 @@ __device__ __forceinline__ float wave_reduce16(const float v[16]) {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// A wave's per-record sum goes to the record's 2D-gradient slot with a float
+// atomic, or (deterministic mode) is stored to the slot of its own (tile
+// pair, wave), which nothing else writes.
+template <bool DET>
+__device__ __forceinline__ void add_or_store(float *p, float v) {
+  if constexpr (DET) *p = v;
+  else unsafeAtomicAdd(p, v);
+}
+
 // Per-wave LDS of the backward pass's per-record reduction.  For up to 8
 // contributing records the wave buffers every pixel's colour weight
 // w = alpha T (rows 0..7) and dL/dq (rows 8..15); columns are the wave's 64
@@ -366,10 +375,12 @@ __device__ __forceinline__ float feature_slot(int n, float g, float x, float y) 
 //   sum u dx = R_x - cx R_1,  sum u dx dy = R_xy - cx R_y - cy R_x + cx cy R_1,
 //   sum u dx^2 = R_xx - 2 cx R_x + cx^2 R_1  (lane group 3 takes R_1 from
 // group 2), and sum(alpha gate) = -2 R_1.  Every valid nonzero value of the
-// first nb records is then added to its slot.
+// first nb records is then added to its slot (dst + id * STRIDE), or with
+// DET stored there (the slot belongs to this wave and record alone).
+template <int STRIDE, bool DET>
 __device__ __forceinline__ void flush_records(WaveAcc &acc, int nb, const float (&bf)[16], uint32_t fields,
                                               uint32_t isid, float icx, float icy, float bcx, float bcy,
-                                              float *__restrict__ g2) {
+                                              float *__restrict__ dst) {
   const int lane = threadIdx.x & 63, j = lane & 15, kk = lane >> 4;
   floatx4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -407,8 +418,8 @@ __device__ __forceinline__ void flush_records(WaveAcc &acc, int nb, const float 
   const float v0 = stage[rb * 16 + f], v1 = stage[(4 + rb) * 16 + f];
   const uint32_t id0 = __shfl(isid, rb, 64), id1 = __shfl(isid, 4 + rb, 64);
   if (f < 13) {
-    if (rb < nb && v0 != 0.f) unsafeAtomicAdd(g2 + (uint64_t)id0 * kG2 + f, v0);
-    if (4 + rb < nb && v1 != 0.f) unsafeAtomicAdd(g2 + (uint64_t)id1 * kG2 + f, v1);
+    if (rb < nb && v0 != 0.f) add_or_store<DET>(dst + (uint64_t)id0 * STRIDE + f, v0);
+    if (4 + rb < nb && v1 != 0.f) add_or_store<DET>(dst + (uint64_t)id1 * STRIDE + f, v1);
   }
 }
 
@@ -427,11 +438,17 @@ __device__ __forceinline__ uint32_t slot_fields(int kk) {
 // instruction.  Same sums, different speed: the matrix-core form spends
 // fewer instructions per record, the lane-exchange form less per tile and
 // fewer registers and LDS (twice the resident workgroups).
-template <int T, bool MM>
+//
+// DET (deterministic mode): instead of float atomics into the record's slot,
+// each wave stores its sums for a record into the slot of (tile-sorted pair
+// index, wave); det_reduce_kernel adds them per record in a fixed order.
+template <int T, bool MM, bool DET>
 __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, const Header &h, void *__restrict__ ws, uint32_t tile,
                               float4 (*srec)[4], float4 *sabc, uint32_t *sid, Entry (*lists)[bwd_batch_of<T, MM>()],
                               WaveAcc *accs, int *smax, const uint32_t *__restrict__ vals) {
   constexpr int NT = bwd_batch_of<T, MM>();
+  constexpr int WPT = (T / 8) * (T / 8);
+  constexpr int STRIDE = DET ? WPT * kG2 : kG2;
   // nothing to do for a tile without masked pixels (uniform over the workgroup)
   if (ws_ptr<const uint32_t>(ws, h.ws.tile_count)[tile] == 0) return;
   TileGeom g;
@@ -443,7 +460,9 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
   const bool masked = g.inside && (rd.mask == nullptr || rd.mask[pix] != 0);
   const uint2 rg = ws_ptr<uint2>(ws, h.ws.ranges)[tile];
   const float4 *rec4 = ws_ptr<float4>(ws, h.ws.rec);
-  float *g2 = ws_ptr<float>(ws, h.ws.g2);
+  // where the per-record sums go: slot id * STRIDE of dst (id = record, or
+  // with DET the tile-sorted pair index; the wave picks its slot of the pair)
+  float *dst = DET ? ws_ptr<float>(ws, h.ws.part) + (threadIdx.x >> 6) * kG2 : ws_ptr<float>(ws, h.ws.g2);
   const float amax = h.cfg.alpha_max;
   const float l2min = __log2f(h.cfg.alpha_min);
   const float fx = g.px + 0.5f, fy = g.py + 0.5f;
@@ -586,7 +605,7 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
           const float tot = wave_reduce16(v);
           const int which = (lane >> 2) & 15;
           if ((lane & 3) == 0 && which < 13 && tot != 0.f)
-            unsafeAtomicAdd(g2 + (uint64_t)sid[cur.k] * kG2 + which, tot);
+            add_or_store<DET>(dst + (uint64_t)(DET ? bstart + cur.k : sid[cur.k]) * STRIDE + which, tot);
         }
       } else {
         // back to front; the next entry and its coefficients are loaded while
@@ -627,12 +646,12 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
             acc.a[nb][col] = w;
             acc.a[8 + nb][col] = -0.5f * a * gate;
             const bool mine = lane == nb;
-            isid = mine ? rid : isid;
+            isid = mine ? (DET ? bstart + e.k : rid) : isid;
             icx = mine ? r0.x : icx;
             icy = mine ? r0.y : icy;
             if (++nb == 8) {
               __builtin_amdgcn_wave_barrier();
-              flush_records(acc, 8, bf, fields, isid, icx, icy, bcx, bcy, g2);
+              flush_records<STRIDE, DET>(acc, 8, bf, fields, isid, icx, icy, bcx, bcy, dst);
               __builtin_amdgcn_wave_barrier();
               nb = 0;
             }
@@ -645,7 +664,7 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
   }
   if (MM && nb > 0) {
     __builtin_amdgcn_wave_barrier();
-    flush_records(acc, nb, bf, fields, isid, icx, icy, bcx, bcy, g2);
+    flush_records<STRIDE, DET>(acc, nb, bf, fields, isid, icx, icy, bcx, bcy, dst);
   }
 }
 
@@ -694,7 +713,7 @@ __global__ void __launch_bounds__(T *T) forward_kernel(const void *__restrict__ 
 // per CU at T = 16 (96-record batches, 30.6 KB; 96 VGPRs, the per-tile
 // constants spill to scratch outside the record loop), 4 waves per SIMD
 // otherwise.
-template <int T, bool MM>
+template <int T, bool MM, bool DET>
 __global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(MM ? (T == 16 ? 5 : 4) : 8))) backward_kernel(const void *__restrict__ desc, void *__restrict__ ws,
                                                          const uint32_t *__restrict__ vals) {
   constexpr int NT = bwd_batch_of<T, MM>();
@@ -708,7 +727,7 @@ __global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(MM ? 
   __shared__ uint32_t s_item;
   const Header &h = *header(desc);
   if (!h.cfg.persistent) {
-    backward_tile<T, MM>(desc, h, ws, blockIdx.x, srec, sabc, sid, lists, accs, &smax, vals);
+    backward_tile<T, MM, DET>(desc, h, ws, blockIdx.x, srec, sabc, sid, lists, accs, &smax, vals);
     return;
   }
   uint32_t *ctr = ws_ptr<uint32_t>(ws, h.ws.status) + S_QUEUE_BWD;
@@ -724,7 +743,7 @@ __global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(MM ? 
     const uint32_t stop = min(ntiles, base + chunk);
     for (uint32_t it = base; it < stop; ++it) {
       __syncthreads();
-      backward_tile<T, MM>(desc, h, ws, queue[it], srec, sabc, sid, lists, accs, &smax, vals);
+      backward_tile<T, MM, DET>(desc, h, ws, queue[it], srec, sabc, sid, lists, accs, &smax, vals);
     }
   }
 }
@@ -741,14 +760,69 @@ void launch_fwd_t(const void *d, const Header &h, void *ws, hipStream_t s) {
   hipLaunchKernelGGL(HIP_KERNEL_NAME(forward_kernel<T>), dim3(grid), dim3(T * T), 0, s, d, ws, vals);
 }
 
-template <int T>
-void launch_bwd_t(const void *d, const Header &h, void *ws, hipStream_t s) {
+template <int T, bool DET>
+void launch_bwd_td(const void *d, const Header &h, void *ws, hipStream_t s) {
   const uint32_t *vals = ws_ptr<uint32_t>(ws, h.ws.sorted_val);
   const unsigned grid = h.cfg.persistent ? persistent_grid(h) : (unsigned)h.n_tiles;
   if (h.cfg.bwd_reduce == 0)
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(backward_kernel<T, true>), dim3(grid), dim3(T * T), 0, s, d, ws, vals);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(backward_kernel<T, true, DET>), dim3(grid), dim3(T * T), 0, s, d, ws, vals);
   else
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(backward_kernel<T, false>), dim3(grid), dim3(T * T), 0, s, d, ws, vals);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(backward_kernel<T, false, DET>), dim3(grid), dim3(T * T), 0, s, d, ws, vals);
+}
+
+template <int T>
+void launch_bwd_t(const void *d, const Header &h, void *ws, hipStream_t s) {
+  if (h.cfg.deterministic) launch_bwd_td<T, true>(d, h, ws, s);
+  else launch_bwd_td<T, false>(d, h, ws, s);
+}
+
+// Deterministic mode: zero the (pair, wave) slots of the pairs of this
+// forward (a pair/wave slot that no wave writes must read as zero).
+__global__ void __launch_bounds__(256) det_clear_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+  const Header &h = *header(desc);
+  const uint64_t np = ws_ptr<const uint32_t>(ws, h.ws.status)[S_NPAIRS];
+  const uint64_t n4 = np * (uint64_t)waves_per_tile(h.cfg.tile) * (kG2 / 4);
+  float4 *p = ws_ptr<float4>(ws, h.ws.part);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
+    p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Deterministic mode: the segmented reduction.  One thread per visible
+// record (depth order): its pairs are emission indices [pair_off, pair_off
+// + active tiles) -- its active tiles in row-major order -- and each maps to
+// its tile-sorted slot through the inverse permutation.  The record's 13
+// sums are added over its pairs in that order and over the waves of each
+// tile in index order, then written (not added) to its 2D-gradient slot.
+template <int WPT>
+__global__ void __launch_bounds__(256) det_reduce_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+  const Header &h = *header(desc);
+  const uint32_t *st = ws_ptr<const uint32_t>(ws, h.ws.status);
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= st[S_NVIS]) return;
+  const uint32_t rid = ws_ptr<const uint32_t>(ws, h.ws.vis_val[st[S_DEPTH_CUR] ? 1 : 0])[i];
+  const uint64_t e0 = ws_ptr<const uint32_t>(ws, h.ws.pair_off)[i];
+  const uint64_t e1 = min(e0 + ws_ptr<const uint32_t>(ws, h.ws.nact)[rid], (uint64_t)st[S_NPAIRS]);
+  const uint32_t *inv = ws_ptr<const uint32_t>(ws, h.ws.pair_inv);
+  const float4 *part = ws_ptr<const float4>(ws, h.ws.part);
+  float s[13];
+#pragma unroll
+  for (int f = 0; f < 13; ++f) s[f] = 0.f;
+  for (uint64_t e = e0; e < e1; ++e) {
+    const uint64_t j = inv[e];
+#pragma unroll
+    for (int w = 0; w < WPT; ++w) {
+      const float4 *q = part + (j * WPT + w) * (kG2 / 4);
+      const float4 a = q[0], b = q[1], c = q[2], d = q[3];
+      s[0] += a.x; s[1] += a.y; s[2] += a.z; s[3] += a.w;
+      s[4] += b.x; s[5] += b.y; s[6] += b.z; s[7] += b.w;
+      s[8] += c.x; s[9] += c.y; s[10] += c.z; s[11] += c.w;
+      s[12] += d.x;
+    }
+  }
+  float *g = ws_ptr<float>(ws, h.ws.g2) + (uint64_t)rid * kG2;
+#pragma unroll
+  for (int f = 0; f < 13; ++f) g[f] = s[f];
 }
 
 }  // namespace
@@ -759,6 +833,23 @@ void launch_composite(const void *d_desc, const Header &h, void *ws, hipStream_t
     case 8: launch_fwd_t<8>(d_desc, h, ws, s); break;
     case 16: launch_fwd_t<16>(d_desc, h, ws, s); break;
     default: launch_fwd_t<32>(d_desc, h, ws, s); break;
+  }
+}
+
+void launch_det_clear(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
+  if (h.pair_capacity == 0) return;
+  uint64_t blocks = (h.pair_capacity * waves_per_tile(h.cfg.tile) * (kG2 / 4) + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(det_clear_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_desc, ws);
+}
+
+void launch_det_reduce(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
+  if (h.n_records == 0) return;
+  const dim3 grid((unsigned)((h.n_records + 255) / 256));
+  switch (h.cfg.tile) {
+    case 8: hipLaunchKernelGGL(det_reduce_kernel<1>, grid, dim3(256), 0, s, d_desc, ws); break;
+    case 16: hipLaunchKernelGGL(det_reduce_kernel<4>, grid, dim3(256), 0, s, d_desc, ws); break;
+    default: hipLaunchKernelGGL(det_reduce_kernel<16>, grid, dim3(256), 0, s, d_desc, ws); break;
   }
 }
 

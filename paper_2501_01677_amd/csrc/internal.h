@@ -86,6 +86,12 @@ struct Layout {
   uint64_t pair_key[2], pair_val[2];
   uint64_t sorted_key, sorted_val;  // the pair buffers holding the tile-sorted result
   uint64_t pix_T, pix_last, g2;
+  // Deterministic backward only (0 otherwise): the record of every emitted
+  // pair (uint32 [capacity], emission order), and one 16-float slot per
+  // (tile-sorted pair, wave of the tile) for the backward compositing sums.
+  // After the tile sort the spare pair-value buffer holds the inverse
+  // permutation (emission index -> tile-sorted index).
+  uint64_t pair_rec, part, pair_inv;
   // Region [zero_begin, zero_end) is cleared at the start of every forward:
   // status words, single-pass scan look-back words, digit histograms,
   // radix look-back words and the queue buckets.
@@ -190,6 +196,12 @@ void launch_emit(const void *d_desc, const Header &h, void *ws, hipStream_t s);
 void launch_tile_sort(const void *d_desc, const Header &h, void *ws, hipStream_t s);
 void launch_composite(const void *d_desc, const Header &h, void *ws, hipStream_t s);
 void launch_backward_composite(const void *d_desc, const Header &h, void *ws, hipStream_t s);
+// Deterministic backward: clears the per-(pair, wave) slots before the
+// compositing pass and adds every record's slots in a fixed order after it.
+void launch_det_clear(const void *d_desc, const Header &h, void *ws, hipStream_t s);
+void launch_det_reduce(const void *d_desc, const Header &h, void *ws, hipStream_t s);
+// Waves (8 x 8 pixel blocks) per tile.
+__host__ __device__ inline int waves_per_tile(int tile) { return (tile / 8) * (tile / 8); }
 // Adam folded into the backward projection (a disabled instance writes the
 // plain gradients).  coef: the step's bias corrections (two floats).
 struct AdamArgs {

@@ -39,6 +39,7 @@ class RenderConfig:
     depth_guard: float = 1e-6
     bg: tuple = (0.0, 0.0, 0.0)
     bwd_reduce: int = 0  # 0: matrix-core per-record sums, 1: wave lane exchanges
+    deterministic: bool = False  # bit-reproducible gradients (segmented reduction, no float atomics)
 
     def to_c(self) -> A.Config:
         c = A.Config()
@@ -49,6 +50,7 @@ class RenderConfig:
             setattr(c, k, getattr(self, k))
         c.bg = (C.c_float * 3)(*self.bg)
         c.bwd_reduce = int(self.bwd_reduce)
+        c.deterministic = int(bool(self.deterministic))
         return c
 
 
@@ -71,6 +73,22 @@ class LossConfig:
 
 class CapacityError(RuntimeError):
     pass
+
+
+class DeviceError(RuntimeError):
+    """The device reported that the outputs of the last forward are invalid
+    (a bounded wait of a single-pass scan gave up)."""
+
+
+# largest pair capacity the library plans for (pgsag_plan: 1..2^30-1)
+MAX_PAIR_CAPACITY = (1 << 30) - 1
+
+
+def _capacity(want):
+    want = int(want)
+    if want > MAX_PAIR_CAPACITY:
+        raise CapacityError(f"{want} (tile, Gaussian) pairs needed; the library plans at most {MAX_PAIR_CAPACITY}")
+    return max(1, want)
 
 
 def _p(t):
@@ -143,8 +161,9 @@ class Batch:
                     self.grads.append({k: torch.zeros_like(s[k]) for k in PARAMS})
         n_rec = sum(int(sets[rd["set"]]["means"].shape[1]) for rd in renders)
         if pair_capacity is None:
-            pair_capacity = max(1 << 16, 8 * n_rec)
-        self._pack(int(min(pair_capacity, (1 << 31) - 1)))
+            pair_capacity = min(max(1 << 16, 8 * n_rec), MAX_PAIR_CAPACITY)
+        self.generation = 0  # forwards run so far (the autograd function checks it)
+        self._pack(_capacity(pair_capacity))
 
     # ------------------------------------------------------------ packing
     def _c_arrays(self):
@@ -212,18 +231,29 @@ class Batch:
             A.check(self.lib.pgsag_forward(self.host_desc, _p(self.dev_desc), _p(self.workspace),
                                            int(self.info.workspace_bytes), _stream(stream),
                                            self._events(events)), "pgsag_forward")
+            self.generation += 1
             if not check_overflow:
                 return self.out
-            st = self.status(stream)
+            st = self.check_status(stream)
             if not st.overflow:
                 return self.out
-            self._pack(int(min((1 << 31) - 1, max(st.pairs_needed * 5 // 4, 1024))))
+            self._pack(_capacity(max(st.pairs_needed * 5 // 4, 1024)))
         raise CapacityError("pair capacity overflow persists after replanning")
+
+    def check_status(self, stream=None):
+        """Reads the status word of the last forward (a stream
+        synchronisation) and raises DeviceError if the device reported its
+        results invalid; returns the status (overflow is left to the caller)."""
+        st = self.status(stream)
+        if st.error:
+            raise DeviceError(f"device reported invalid binning results (error word {st.error}); "
+                              "the outputs of the last forward are invalid")
+        return st
 
     def fit_capacity(self, slack=1.25, stream=None):
         """Replans the pair capacity to slack x what the last forward needed."""
-        st = self.status(stream)
-        want = int(min((1 << 31) - 1, max(1024, st.pairs_needed * slack)))
+        st = self.check_status(stream)
+        want = _capacity(max(1024, st.pairs_needed * slack))
         if want != self.capacity:
             self._pack(want)
         return st
@@ -326,10 +356,18 @@ def adam_step(params, grads, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8, stream=
 
 
 class _RasterizeFn(torch.autograd.Function):
+    """The backward reads the per-pixel state the batch's workspace holds
+    and the parameter tensors as they are then, so it is only valid for the
+    batch's latest forward with unchanged parameters: the forward generation
+    and the parameters' version counters are saved and checked."""
+
     @staticmethod
     def forward(ctx, batch, *flat):
         batch.forward()
         ctx.batch = batch
+        ctx.generation = batch.generation
+        ctx.versions = [t._version for t in flat]
+        ctx.flat = flat
         outs = []
         for o in batch.out:
             for name in GRAD_OUTPUTS:
@@ -341,6 +379,12 @@ class _RasterizeFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, *grads):
         batch = ctx.batch
+        if batch.generation != ctx.generation:
+            raise RuntimeError("the batch ran another forward since this output was rendered; "
+                               "its backward would differentiate the newer forward")
+        if [t._version for t in ctx.flat] != ctx.versions:
+            raise RuntimeError("a Gaussian parameter tensor was modified in place between "
+                               "the forward and the backward")
         per = len(GRAD_OUTPUTS) + 1
         gouts = []
         for i in range(len(batch.renders)):
@@ -483,4 +527,7 @@ class Trainer:
         return self.loss_out
 
     def overflowed(self):
-        return bool(self.batch.status().overflow)
+        """Whether the last step's forward ran out of pair capacity (then
+        that step is invalid: fit() again).  Raises DeviceError if the device
+        reported the step's binning invalid."""
+        return bool(self.batch.check_status().overflow)

@@ -40,12 +40,13 @@ STRUCTS = {
     "pgsag_outputs": (A.Outputs, ["rgb", "alpha", "n_contrib"]),
     "pgsag_grad_outputs": (A.GradOutputs, ["rgb", "alpha"]),
     "pgsag_render": (A.Render, ["set", "cam", "mask", "out", "gout"]),
-    "pgsag_config": (A.Config, ["tile", "alpha_min", "logit_min", "depth_guard", "bg", "bwd_reduce"]),
+    "pgsag_config": (A.Config, ["tile", "alpha_min", "logit_min", "depth_guard", "bg", "bwd_reduce",
+                                         "deterministic"]),
     "pgsag_adam_config": (A.AdamConfig, ["lr", "step_state", "m_offset", "v_offset", "write_grads"]),
     "pgsag_loss_config": (A.LossConfig, ["lambda_rgb", "lambda_load", "normal_norm", "normal_eps", "reserved"]),
     "pgsag_plan_info": (A.PlanInfo, ["workspace_bytes", "pair_capacity", "tile_bits"]),
     "pgsag_layout": (A.Layout, ["status", "records", "grad2d", "end"]),
-    "pgsag_status": (A.Status, ["pairs_needed", "overflow", "n_visible"]),
+    "pgsag_status": (A.Status, ["pairs_needed", "overflow", "n_visible", "error", "reserved"]),
 }
 
 

@@ -325,3 +325,26 @@ def test_capacity_overflow_is_flagged_and_replanned():
     o1, o2 = outputs_numpy(ref_b, 0), outputs_numpy(b, 0)
     for k in o1:
         assert np.array_equal(o1[k], o2[k]), k
+
+
+def test_device_error_word_is_reported_and_raises():
+    """A single-pass scan that gives up its bounded wait sets the status
+    error word: read_status reports it, the binding raises instead of
+    returning invalid outputs, and the next forward starts clean.  (The word
+    is planted from the host after a normal forward.)"""
+    from paper_2501_01677_amd.raster import DeviceError
+    sc = scenes.small_scene(91, n=100, width=40, height=32, sh_degree=1)
+    b = device_scene(sc, RenderConfig(tile=16))
+    b.forward()
+    st = b.status()
+    assert st.error == 0 and st.overflow == 0
+    words = b.view("status", torch.int32, 16)
+    words[9] = 1
+    assert b.status().error == 1
+    with pytest.raises(DeviceError):
+        b.check_status()
+    with pytest.raises(DeviceError):
+        b.fit_capacity()
+    b.forward()
+    assert b.status().error == 0
+
