@@ -382,6 +382,37 @@ int pgsag_loss(const pgsag_loss_config *lc, const void *host_desc, const void *d
 int pgsag_luminance_weights(const void *host_desc, const void *dev_desc, void *workspace, uint64_t workspace_bytes,
                             int32_t render, const float *gt_rgb, float *weight, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Building-point voting (Sec. 4.1, "Reliability-scored Multi-view Voting
+ * Filter", Eq. 6-7).  SfM sparse points are re-projected into every coarsely
+ * masked view.  Point p is in Image_j when its camera-frame depth exceeds
+ * z_near and its projection lies inside the image, and in M_j when it is in
+ * Image_j and the mask pixel under the projection is non-zero:
+ *   votes(p) = sum_j I(p in M_j)                  (Eq. 6: potential building
+ *                                                  point iff votes > 0)
+ *   US(p)    = sum_j I(p in Image_j \ M_j)        (Eq. 7: unreliability score)
+ *   flags(p) = bit 0: votes > 0; bit 1: votes > 0 and US < tau (reliable).
+ * The projection is taken in FP32 with every operation rounded on its own,
+ * in this order: xc = ((R00 x + R01 y) + R02 z) + t0 (likewise yc, zc);
+ * in front iff zc > z_near; u = fx (xc / zc) + cx, v = fy (yc / zc) + cy
+ * (correctly rounded division); inside iff 0 <= u < W and 0 <= v < H; the
+ * pixel is (floor u, floor v).  No occlusion test. */
+typedef struct pgsag_vote_view {
+  pgsag_camera cam;
+  const uint8_t *mask; /* device [H][W], non-zero = building pixel; NULL = every pixel */
+} pgsag_vote_view;
+
+/* host_views and dev_views hold the same n_views views (the host copy is
+ * read for validation, the device copy by the kernel; the caller uploads
+ * it).  points: device float [3][n_points] (planar x, y, z).  votes, us:
+ * device uint16 [n_points] or NULL (not wanted); flags: device uint8
+ * [n_points], required.  1 <= n_views <= 65535 (the counts are 16-bit),
+ * n_points >= 0, tau >= 0, z_near > 0, image sizes 1..65535.  Every output
+ * element is written.  No allocation, no synchronisation; capturable. */
+int pgsag_vote(const pgsag_vote_view *host_views, const pgsag_vote_view *dev_views, int32_t n_views,
+               const float *points, int64_t n_points, float z_near, int32_t tau, uint16_t *votes,
+               uint16_t *us, uint8_t *flags, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,6 +81,10 @@ class AdamConfig(C.Structure):
                 ("write_grads", C.c_int32), ("reserved", C.c_int32)]
 
 
+class VoteView(C.Structure):
+    _fields_ = [("cam", Camera), ("mask", C.c_void_p)]
+
+
 class Status(C.Structure):
     _fields_ = [("pairs_needed", C.c_uint64), ("overflow", C.c_uint32), ("n_visible", C.c_uint32),
                 ("error", C.c_uint32), ("reserved", C.c_uint32)]
@@ -89,7 +93,8 @@ class Status(C.Structure):
 SYMBOLS = ("pgsag_version", "pgsag_last_error", "pgsag_default_config", "pgsag_plan", "pgsag_pack",
            "pgsag_layout_of", "pgsag_forward", "pgsag_backward", "pgsag_binning",
            "pgsag_read_status", "pgsag_adam_step", "pgsag_load_stats", "pgsag_default_loss_config",
-           "pgsag_loss", "pgsag_luminance_weights", "pgsag_adam_step_device", "pgsag_backward_adam")
+           "pgsag_loss", "pgsag_luminance_weights", "pgsag_adam_step_device", "pgsag_backward_adam",
+           "pgsag_vote")
 
 _lib = None
 
@@ -125,6 +130,7 @@ def lib():
     L.pgsag_default_loss_config.restype = None
     L.pgsag_loss.argtypes = [C.POINTER(LossConfig), vp, vp, vp, u64, C.POINTER(vp), vp, vp]
     L.pgsag_luminance_weights.argtypes = [vp, vp, vp, u64, i32, vp, vp, vp]
+    L.pgsag_vote.argtypes = [C.POINTER(VoteView), vp, i32, vp, i64, f32, i32, vp, vp, vp, vp]
     for name in SYMBOLS:
         if name not in ("pgsag_last_error", "pgsag_default_config", "pgsag_default_loss_config"):
             getattr(L, name).restype = C.c_int

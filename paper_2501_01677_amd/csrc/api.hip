@@ -34,6 +34,26 @@ int check_hip(const char *where) {
   return PGSAG_OK;
 }
 
+}  // namespace
+
+namespace pgsag {
+
+int set_error(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+int hip_status(const char *where) { return check_hip(where); }
+
+}  // namespace pgsag
+
+namespace {
+
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 struct Sizes {

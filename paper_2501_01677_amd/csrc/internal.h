@@ -185,6 +185,12 @@ __device__ inline int upper_index(const T *a, int n, T x) {
   return lo;
 }
 
+// Error reporting of the C ABI (thread-local message read by
+// pgsag_last_error): set_error stores the formatted message and returns
+// `code`; hip_status turns a pending HIP launch error into PGSAG_HIP_ERROR.
+int set_error(int code, const char *fmt, ...);
+int hip_status(const char *where);
+
 // ---------------------------------------------------------------- launches
 // Host-side launch helpers, defined in the kernel translation units.
 void launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t s);

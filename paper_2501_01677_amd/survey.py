@@ -1,0 +1,57 @@
+"""Python boundary of the survey-side steps around the rasterizer: the
+multi-view building-point voting filter (Sec. 4.1, Eq. 6-7).
+
+Argument marshalling only: the views are packed into the C structs of
+include/pgsag.h, uploaded into a caller-owned device tensor, and every step
+runs in the library's HIP kernels.  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _abi as A
+from .raster import _p, _stream, make_camera
+
+
+def pack_views(cameras, masks):
+    """Host array of pgsag_vote_view and its device copy (uint8 tensor).
+    masks: device uint8 [H][W] tensors (or None = every pixel); they must
+    outlive every call that uses the returned views."""
+    n = len(cameras)
+    if len(masks) != n:
+        raise ValueError("one mask (or None) per camera")
+    host = (A.VoteView * n)()
+    for j, (cam, m) in enumerate(zip(cameras, masks)):
+        host[j].cam = make_camera(cam)
+        if m is not None:
+            if m.dtype != torch.uint8 or not m.is_cuda or not m.is_contiguous():
+                raise ValueError("masks must be contiguous uint8 device tensors")
+            if tuple(m.shape) != (cam.height, cam.width):
+                raise ValueError(f"mask {j} has shape {tuple(m.shape)}, camera is {cam.height}x{cam.width}")
+        host[j].mask = None if m is None else m.data_ptr()
+    raw = np.frombuffer(bytes(host), dtype=np.uint8)
+    dev = torch.from_numpy(raw.copy()).cuda()
+    return host, dev
+
+
+def vote(points, cameras, masks, tau, z_near=0.2, views=None, out=None, stream=None):
+    """Eq. 6-7 for every point of points (device float32 [3][M]) over the
+    views: returns (votes uint16 [M], us uint16 [M], flags uint8 [M]);
+    flags bit 0 = potential building point, bit 1 = reliable.
+    `views` may pass a (host, device) pair from pack_views to skip packing."""
+    if points.dtype != torch.float32 or not points.is_cuda or points.dim() != 2 or points.shape[0] != 3:
+        raise ValueError("points must be a float32 device tensor [3][M]")
+    points = points.contiguous()
+    m = points.shape[1]
+    host, dev = views if views is not None else pack_views(cameras, masks)
+    if out is None:
+        out = (torch.empty(m, dtype=torch.uint16, device=points.device),
+               torch.empty(m, dtype=torch.uint16, device=points.device),
+               torch.empty(m, dtype=torch.uint8, device=points.device))
+    votes, us, flags = out
+    A.check(A.lib().pgsag_vote(host, _p(dev), len(host), _p(points), m, float(z_near), int(tau),
+                               _p(votes), _p(us), _p(flags), _stream(stream)), "pgsag_vote")
+    return votes, us, flags

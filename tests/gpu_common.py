@@ -48,18 +48,22 @@ def compare_images(gpu, ref, render, report=None):
     v, u = pix[:, 0], pix[:, 1]
     allow = ref["allow"]
     bad = {}
+    used = np.zeros(len(pix), bool)  # pixels whose error exceeds the tolerance without the allowance
 
-    def chk(name, got, want, tol):
+    def chk(name, got, want, tol, base=None):
         err = np.abs(got - want)
         fail = err > tol
+        if base is not None:
+            used[(err > base).reshape(len(pix), -1).any(1)] = True
         if np.any(fail):
             i = np.flatnonzero(fail.reshape(len(pix), -1).any(1))[:5]
             bad[name] = (int(fail.sum()), float(err.max()), [tuple(pix[j]) for j in i])
 
-    chk("rgb", gpu["rgb"][:, v, u].T, ref["rgb"], 1e-4 + allow[:, 0:3])
-    chk("normal", gpu["normal"][:, v, u].T, ref["normal"], 1e-4 + allow[:, 3:6])
-    chk("dist", gpu["dist"][v, u], ref["dist"], 1e-4 * np.maximum(1, np.abs(ref["dist"])) + allow[:, 6])
-    chk("alpha", gpu["alpha"][v, u], ref["alpha"], 1e-4 + allow[:, 7])
+    chk("rgb", gpu["rgb"][:, v, u].T, ref["rgb"], 1e-4 + allow[:, 0:3], 1e-4)
+    chk("normal", gpu["normal"][:, v, u].T, ref["normal"], 1e-4 + allow[:, 3:6], 1e-4)
+    dbase = 1e-4 * np.maximum(1, np.abs(ref["dist"]))
+    chk("dist", gpu["dist"][v, u], ref["dist"], dbase + allow[:, 6], dbase)
+    chk("alpha", gpu["alpha"][v, u], ref["alpha"], 1e-4 + allow[:, 7], 1e-4)
     ok = ~ref["depth_unreliable"]
     rel = np.where(np.abs(ref["den"]) >= 0.1 * ref["alpha"], 1e-4, 1e-3)
     dtol = rel * np.maximum(1.0, np.abs(ref["depth"]))
@@ -72,6 +76,7 @@ def compare_images(gpu, ref, render, report=None):
         report["allow_pixels"] = int((allow.sum(1) > 0).sum())
         report["pixels"] = len(pix)
         report["depth_excluded"] = int((~ok).sum())
+        report["used_allowance"] = int(used.sum())
     return bad
 
 

@@ -47,6 +47,7 @@ STRUCTS = {
     "pgsag_plan_info": (A.PlanInfo, ["workspace_bytes", "pair_capacity", "tile_bits"]),
     "pgsag_layout": (A.Layout, ["status", "records", "grad2d", "end"]),
     "pgsag_status": (A.Status, ["pairs_needed", "overflow", "n_visible", "error", "reserved"]),
+    "pgsag_vote_view": (A.VoteView, ["cam", "mask"]),
 }
 
 
@@ -146,6 +147,32 @@ def test_adam_rejects_bad_arguments_without_touching_memory():
     assert L.pgsag_adam_step(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 1, None) == A.INVALID_ARGUMENT
     p = C.c_void_p(0x1000)
     assert L.pgsag_adam_step(p, p, p, p, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == A.INVALID_ARGUMENT
+
+
+def test_vote_validates_on_the_host_without_touching_memory():
+    L = A.lib()
+    views = (A.VoteView * 2)()
+    for j in range(2):
+        views[j].cam = make_camera(scenes.pinhole(64, 48, 50.0, 50.0))
+    p = C.c_void_p(0x1000)
+    ok_args = (views, p, 2, p, 10, 0.2, 2, p, p, p, None)
+    bad = [
+        (None, p, 2, p, 10, 0.2, 2, p, p, p, None),        # no host views
+        (views, p, 0, p, 10, 0.2, 2, p, p, p, None),       # no view
+        (views, p, 2, p, -1, 0.2, 2, p, p, p, None),       # n < 0
+        (views, p, 2, None, 10, 0.2, 2, p, p, p, None),    # no points
+        (views, p, 2, p, 10, 0.2, 2, p, p, None, None),    # no flags
+        (views, p, 2, p, 10, 0.0, 2, p, p, p, None),       # z_near <= 0
+        (views, p, 2, p, 10, 0.2, -1, p, p, p, None),      # tau < 0
+    ]
+    for args in bad:
+        assert L.pgsag_vote(*args) == A.INVALID_ARGUMENT, args
+    views[1].cam.width = 0
+    assert L.pgsag_vote(*ok_args) == A.INVALID_ARGUMENT
+    assert b"view 1" in L.pgsag_last_error()
+    # nothing to do: returns before any launch
+    views[1].cam.width = 64
+    assert L.pgsag_vote(views, p, 2, None, 0, 0.2, 2, None, None, None, None) == A.OK
 
 
 def test_autotune_shape_key_buckets():

@@ -52,13 +52,21 @@ def test_headline_forward_sampled_pixels(headline):
     rep = {}
     bad = compare_images(gpu, ref, rd, rep)
     assert not bad, bad
-    # ~260 fragments are evaluated per pixel here, so a few pixels hold a
-    # decision within the allowance margins (those are still checked, within
-    # tolerance + allowance, above)
+    # About 260 fragments are evaluated per pixel here, so a few percent of
+    # the pixels hold some decision within the oracle's margins (alpha within
+    # 1e-3 relative of the cut-off, T' within 1e-3 of the stop, a near edge-on
+    # normal flip).  That share is a property of the workload and the oracle
+    # alone (42 of these 1024 seeded pixels, 4.10%); those pixels are still
+    # checked within tolerance + allowance above.  What the GPU's FP32
+    # decisions actually change is the share of pixels whose error exceeds
+    # the plain tolerance, i.e. that need their allowance at all.
     frac = rep["allow_pixels"] / rep["pixels"]
+    used = rep["used_allowance"] / rep["pixels"]
     print(f"[info] 1080p sample: {rep['allow_pixels']} of {rep['pixels']} pixels carry an allowance "
-          f"({100 * frac:.2f}%), {rep['depth_excluded']} excluded from the depth check", flush=True)
-    assert frac < 0.02
+          f"({100 * frac:.2f}%), {rep['used_allowance']} need it ({100 * used:.2f}%), "
+          f"{rep['depth_excluded']} excluded from the depth check", flush=True)
+    assert frac <= 0.045
+    assert used <= 0.005
     assert check_unmasked_zero(gpu, rd.mask)
     assert int(b.status().overflow) == 0
 
@@ -208,7 +216,9 @@ def test_training_scale_forward_sampled_pixels(training_scale):
         assert not bad, (r, bad)
         assert check_unmasked_zero(gpu, rd.mask)
         assert ref["n_contrib"].mean() > 5
-        print(f"[info] view {r}: {rep['allow_pixels']} of {rep['pixels']} pixels carry an allowance", flush=True)
+        print(f"[info] view {r}: {rep['allow_pixels']} of {rep['pixels']} pixels carry an allowance, "
+              f"{rep['used_allowance']} need it", flush=True)
+        assert rep["used_allowance"] <= 0.01 * rep["pixels"]
     assert int(b.status().overflow) == 0
     del b
     torch.cuda.empty_cache()
