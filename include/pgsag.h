@@ -413,6 +413,52 @@ int pgsag_vote(const pgsag_vote_view *host_views, const pgsag_vote_view *dev_vie
                const float *points, int64_t n_points, float z_near, int32_t tau, uint16_t *votes,
                uint16_t *us, uint8_t *flags, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Building grouping (Sec. 4.1, "Building Grouping"): DBSCAN (the clustering
+ * the paper names) over the ground-plane coordinates (x, y) of the points
+ * that take part -- e.g. the reliable building points of pgsag_vote -- and
+ * the views each group keeps.
+ *   N(p)    = points q taking part with d2 = dx*dx + dy*dy <= eps*eps, in
+ *             FP32 with every operation rounded on its own (dx = px - qx,
+ *             dy = py - qy); p itself included
+ *   core    = |N(p)| >= min_pts
+ *   cluster = connected component of core points joined within eps, named
+ *             by its smallest core point index
+ *   border  = non-core point with a core neighbour: it takes the smallest
+ *             name among its core neighbours' clusters (DBSCAN leaves the
+ *             choice to the visiting order; this rule makes it unique)
+ *   noise   = label -1; points that take no part also get -1 (and count 0) */
+
+/* Device workspace bytes for pgsag_dbscan over n_points points
+ * (0 <= n_points <= 2^23). */
+int pgsag_dbscan_workspace(int64_t n_points, uint64_t *bytes);
+
+/* points: device float [3][n_points] (x, y used; planar).  A point takes
+ * part when flags is NULL or (flags[i] & flag_mask) != 0 (flags: device
+ * uint8 [n_points], e.g. pgsag_vote's flags with flag_mask 2 = reliable).
+ * eps > 0 (finite), min_pts >= 1.  Outputs (device, every element written):
+ * count int32 [n] = |N(p)| (0 for points taking no part; NULL = not
+ * wanted), label int32 [n] = cluster name or -1, cluster int32 [n] =
+ * compact id 0..k-1 in ascending order of the names or -1 (NULL = not
+ * wanted), n_clusters uint32 [1] = k.  workspace: device buffer of
+ * pgsag_dbscan_workspace bytes, owned by the caller, scratch only (no state
+ * kept between calls).  No allocation, no synchronisation; capturable. */
+int pgsag_dbscan(const float *points, int64_t n_points, const uint8_t *flags, uint32_t flag_mask, float eps,
+                 int32_t min_pts, int32_t *count, int32_t *label, int32_t *cluster, uint32_t *n_clusters,
+                 void *workspace, uint64_t workspace_bytes, void *stream);
+
+/* Views of each group ("subgroups that each contain the ... original
+ * images", Sec. 4.1): hits[c][j] = points with cluster id c that land inside
+ * view j's building mask, with the projection of pgsag_vote; assigned[c][j]
+ * = hits >= min_hits.  cluster: device int32 [n_points] compact ids (< 0 =
+ * none; ids >= max_clusters are ignored, so size max_clusters from
+ * pgsag_dbscan's n_clusters).  hits: device uint32 [max_clusters][n_views];
+ * assigned: device uint8 [max_clusters][n_views] or NULL.  Views as for
+ * pgsag_vote.  No allocation, no synchronisation; capturable. */
+int pgsag_group_views(const pgsag_vote_view *host_views, const pgsag_vote_view *dev_views, int32_t n_views,
+                      const float *points, int64_t n_points, const int32_t *cluster, int32_t max_clusters,
+                      float z_near, uint32_t min_hits, uint32_t *hits, uint8_t *assigned, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,7 +31,7 @@ the view's building mask, with the FP32 projection of the voting filter
 (``oracle.voting.project``).
 """
 import numpy as np
-from scipy.sparse import coo_matrix
+from scipy.sparse import csr_matrix
 from scipy.sparse.csgraph import connected_components
 
 from . import voting as ov
@@ -39,29 +39,30 @@ from . import voting as ov
 F32 = np.float32
 
 
-def neighbour_pairs(xy, eps, block=4096):
-    """All ordered pairs (i, j), i != j, with the FP32 squared distance <= eps^2.
-    Candidate pairs come from a uniform grid of cell side > eps (every
-    neighbour sits in the 3x3 cells around a point); the decision itself is
-    the FP32 rule of the module docstring."""
+def neighbour_pairs(xy, eps):
+    """The neighbour relation, in the order of a uniform grid of cell side
+    1.001 eps (every neighbour of a point lies in the 3x3 cells around it,
+    so the grid only picks the candidates; the decision is the FP32 rule of
+    the module docstring).  Returns (order, rows, cols): order = the point
+    of each grid position; rows, cols = int32 grid positions of every
+    ordered pair within eps (self pairs included), rows nondecreasing."""
     x = np.asarray(xy[0], F32)
     y = np.asarray(xy[1], F32)
     n = len(x)
     e2 = F32(eps) * F32(eps)
     if n == 0:
-        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+        return np.zeros(0, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32)
     side = 1.001 * float(eps)
     cx = np.floor((x.astype(np.float64) - x.min()) / side).astype(np.int64)
     cy = np.floor((y.astype(np.float64) - y.min()) / side).astype(np.int64)
     gx = int(cx.max()) + 1
     cell = cy * gx + cx
     order = np.argsort(cell, kind="stable")
-    cs = cell[order]
-    uniq, start, count = np.unique(cs, return_index=True, return_counts=True)
+    xs, ys = x[order], y[order]
+    uniq, start, count = np.unique(cell[order], return_index=True, return_counts=True)
     where = {int(c): (int(s), int(k)) for c, s, k in zip(uniq, start, count)}
-    I, J = [], []
-    for c, (s, k) in where.items():
-        a = order[s:s + k]
+    rows, cols = [], []
+    for c, (s0, k) in where.items():
         ccx, ccy = c % gx, c // gx
         cand = []
         for dy in (-1, 0, 1):
@@ -69,47 +70,59 @@ def neighbour_pairs(xy, eps, block=4096):
                 key = (ccy + dy) * gx + ccx + dx
                 if 0 <= ccx + dx < gx and key in where:
                     s2, k2 = where[key]
-                    cand.append(order[s2:s2 + k2])
+                    cand.append(np.arange(s2, s2 + k2))
         b = np.concatenate(cand)
-        for o in range(0, len(a), block):
-            aa = a[o:o + block]
-            ddx = x[aa][:, None] - x[b][None, :]
-            ddy = y[aa][:, None] - y[b][None, :]
-            d2 = ddx * ddx + ddy * ddy
-            assert d2.dtype == F32
-            ii, jj = np.nonzero(d2 <= e2)
-            keep = aa[ii] != b[jj]
-            I.append(aa[ii][keep])
-            J.append(b[jj][keep])
-    return np.concatenate(I), np.concatenate(J)
+        ddx = xs[s0:s0 + k, None] - xs[b][None, :]
+        ddy = ys[s0:s0 + k, None] - ys[b][None, :]
+        d2 = ddx * ddx + ddy * ddy
+        assert d2.dtype == F32
+        ii, jj = np.nonzero(d2 <= e2)
+        rows.append((ii + s0).astype(np.int32))
+        cols.append(b[jj].astype(np.int32))
+    return order, np.concatenate(rows), np.concatenate(cols)
 
 
 def dbscan(xy, eps, min_pts):
     """Returns dict(count = |N(p)| int64, core bool, label int64 (cluster
     name or -1), cluster int64 (compact id or -1), n_clusters)."""
     n = np.asarray(xy).shape[1]
-    I, J = neighbour_pairs(xy, eps)
-    count = 1 + np.bincount(I, minlength=n)
-    core = count >= min_pts
-    cc = core[I] & core[J]
-    g = coo_matrix((np.ones(int(cc.sum()), np.int8), (I[cc], J[cc])), shape=(n, n))
+    out = dict(count=np.zeros(n, np.int64), core=np.zeros(n, bool), label=np.full(n, -1, np.int64),
+               cluster=np.full(n, -1, np.int64), n_clusters=0)
+    if n == 0:
+        return out
+    order, R, Cc = neighbour_pairs(xy, eps)
+    # everything below is in grid positions; `order` maps back to points
+    cnt = np.bincount(R, minlength=n)
+    core = cnt >= min_pts
+    # clusters: connected components over core-core pairs (each pair once)
+    keep = core[R] & core[Cc] & (R < Cc)
+    R2, C2 = R[keep], Cc[keep]
+    indptr = np.zeros(n + 1, np.int64)
+    indptr[1:] = np.cumsum(np.bincount(R2, minlength=n))
+    g = csr_matrix((np.ones(len(R2), np.int8), C2, indptr), shape=(n, n))
     _, comp = connected_components(g, directed=False)
-    # name of a component: smallest index among its (core) points
-    name_of_comp = np.full(comp.max() + 1 if n else 0, np.iinfo(np.int64).max, np.int64)
-    idx = np.flatnonzero(core)
-    np.minimum.at(name_of_comp, comp[idx], idx)
+    # a cluster's name: the smallest point index among its core points
+    big = np.iinfo(np.int64).max
+    name = np.full(comp.max() + 1, big, np.int64)
+    cpos = np.flatnonzero(core)
+    np.minimum.at(name, comp[cpos], order[cpos])
     label = np.full(n, -1, np.int64)
-    label[idx] = name_of_comp[comp[idx]]
-    # border points: smallest name among their core neighbours
-    b = ~core[I] & core[J]
-    best = np.full(n, np.iinfo(np.int64).max, np.int64)
-    np.minimum.at(best, I[b], label[J[b]])
-    border = ~core & (best != np.iinfo(np.int64).max)
+    label[cpos] = name[comp[cpos]]
+    # border points: the smallest name among their core neighbours
+    b = ~core[R] & core[Cc]
+    best = np.full(n, big, np.int64)
+    np.minimum.at(best, R[b], label[Cc[b]])
+    border = ~core & (best != big)
     label[border] = best[border]
+    # back to point order
+    out["count"][order] = cnt
+    out["core"][order] = core
+    out["label"][order] = label
     names = np.unique(label[label >= 0])
-    cluster = np.full(n, -1, np.int64)
-    cluster[label >= 0] = np.searchsorted(names, label[label >= 0])
-    return dict(count=count, core=core, label=label, cluster=cluster, n_clusters=len(names))
+    lab = out["label"]
+    out["cluster"][lab >= 0] = np.searchsorted(names, lab[lab >= 0])
+    out["n_clusters"] = len(names)
+    return out
 
 
 def dbscan_points(points, eps, min_pts, part=None):

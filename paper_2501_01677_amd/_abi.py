@@ -94,7 +94,7 @@ SYMBOLS = ("pgsag_version", "pgsag_last_error", "pgsag_default_config", "pgsag_p
            "pgsag_layout_of", "pgsag_forward", "pgsag_backward", "pgsag_binning",
            "pgsag_read_status", "pgsag_adam_step", "pgsag_load_stats", "pgsag_default_loss_config",
            "pgsag_loss", "pgsag_luminance_weights", "pgsag_adam_step_device", "pgsag_backward_adam",
-           "pgsag_vote")
+           "pgsag_vote", "pgsag_dbscan_workspace", "pgsag_dbscan", "pgsag_group_views")
 
 _lib = None
 
@@ -131,6 +131,9 @@ def lib():
     L.pgsag_loss.argtypes = [C.POINTER(LossConfig), vp, vp, vp, u64, C.POINTER(vp), vp, vp]
     L.pgsag_luminance_weights.argtypes = [vp, vp, vp, u64, i32, vp, vp, vp]
     L.pgsag_vote.argtypes = [C.POINTER(VoteView), vp, i32, vp, i64, f32, i32, vp, vp, vp, vp]
+    L.pgsag_dbscan_workspace.argtypes = [i64, C.POINTER(C.c_uint64)]
+    L.pgsag_dbscan.argtypes = [vp, i64, vp, C.c_uint32, f32, i32, vp, vp, vp, vp, vp, u64, vp]
+    L.pgsag_group_views.argtypes = [C.POINTER(VoteView), vp, i32, vp, i64, vp, i32, f32, C.c_uint32, vp, vp, vp]
     for name in SYMBOLS:
         if name not in ("pgsag_last_error", "pgsag_default_config", "pgsag_default_loss_config"):
             getattr(L, name).restype = C.c_int

@@ -1,5 +1,6 @@
 """Python boundary of the survey-side steps around the rasterizer: the
-multi-view building-point voting filter (Sec. 4.1, Eq. 6-7).
+multi-view building-point voting filter (Sec. 4.1, Eq. 6-7) and the
+building grouping (Sec. 4.1: DBSCAN and the views of each group).
 
 Argument marshalling only: the views are packed into the C structs of
 include/pgsag.h, uploaded into a caller-owned device tensor, and every step
@@ -55,3 +56,43 @@ def vote(points, cameras, masks, tau, z_near=0.2, views=None, out=None, stream=N
     A.check(A.lib().pgsag_vote(host, _p(dev), len(host), _p(points), m, float(z_near), int(tau),
                                _p(votes), _p(us), _p(flags), _stream(stream)), "pgsag_vote")
     return votes, us, flags
+
+
+def dbscan(points, eps, min_pts, flags=None, flag_mask=2, workspace=None, stream=None):
+    """DBSCAN over the (x, y) of points (device float32 [3][M]) that take part
+    (flags & flag_mask, or all).  Returns dict(count, label, cluster int32
+    [M], n_clusters uint32 [1] device tensors)."""
+    if points.dtype != torch.float32 or not points.is_cuda or points.dim() != 2 or points.shape[0] != 3:
+        raise ValueError("points must be a float32 device tensor [3][M]")
+    points = points.contiguous()
+    m = points.shape[1]
+    L = A.lib()
+    need = C.c_uint64()
+    A.check(L.pgsag_dbscan_workspace(m, C.byref(need)), "pgsag_dbscan_workspace")
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(max(1, need.value), dtype=torch.uint8, device=points.device)
+    if flags is not None and (flags.dtype != torch.uint8 or flags.numel() != m or not flags.is_cuda):
+        raise ValueError("flags must be a uint8 device tensor [M]")
+    dev = points.device
+    out = dict(count=torch.empty(m, dtype=torch.int32, device=dev), label=torch.empty(m, dtype=torch.int32, device=dev),
+               cluster=torch.empty(m, dtype=torch.int32, device=dev),
+               n_clusters=torch.empty(1, dtype=torch.int32, device=dev))
+    A.check(L.pgsag_dbscan(_p(points), m, _p(flags), int(flag_mask), float(eps), int(min_pts), _p(out["count"]),
+                           _p(out["label"]), _p(out["cluster"]), _p(out["n_clusters"]), _p(workspace),
+                           workspace.numel(), _stream(stream)), "pgsag_dbscan")
+    out["workspace"] = workspace
+    return out
+
+
+def group_views(points, cluster, max_clusters, cameras, masks, min_hits, z_near=0.2, views=None, stream=None):
+    """hits [max_clusters][V] uint32 (as int32 storage) and assigned uint8."""
+    points = points.contiguous()
+    m = points.shape[1]
+    host, dev = views if views is not None else pack_views(cameras, masks)
+    nv = len(host)
+    hits = torch.empty((max(1, max_clusters), nv), dtype=torch.int32, device=points.device)
+    assigned = torch.empty((max(1, max_clusters), nv), dtype=torch.uint8, device=points.device)
+    A.check(A.lib().pgsag_group_views(host, _p(dev), nv, _p(points), m, _p(cluster), int(max_clusters),
+                                      float(z_near), int(min_hits), _p(hits), _p(assigned), _stream(stream)),
+            "pgsag_group_views")
+    return hits[:max_clusters], assigned[:max_clusters]

@@ -9,6 +9,7 @@ import pytest
 import torch
 
 import scenes
+from oracle import grouping as og
 from oracle import voting as ov
 from paper_2501_01677_amd import survey as gs
 from scenes import survey as sv
@@ -97,3 +98,92 @@ def test_vote_full_size_bit_exact():
     rel = (ref["flags"] & 2) != 0
     print(f"[info] full vote: {int(rel.sum())} reliable of {s.points.shape[1]} points, "
           f"{int((ref['votes'] + ref['us']).sum())} sightings", flush=True)
+
+
+# ------------------------------------------------------------ grouping
+
+def _dbscan_gpu(points, eps, min_pts, flags=None):
+    r = gs.dbscan(torch.from_numpy(np.ascontiguousarray(points)).cuda(), eps, min_pts,
+                  flags=None if flags is None else torch.from_numpy(flags).cuda())
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if k != "workspace" else v) for k, v in r.items()}
+
+
+def _check_dbscan(points, eps, min_pts, flags=None):
+    part = None if flags is None else (flags & 2) != 0
+    ref = og.dbscan_points(points, eps, min_pts, part)
+    got = _dbscan_gpu(points, eps, min_pts, flags)
+    assert np.array_equal(got["count"], ref["count"]), int((got["count"] != ref["count"]).sum())
+    assert np.array_equal(got["label"], ref["label"]), int((got["label"] != ref["label"]).sum())
+    assert np.array_equal(got["cluster"], ref["cluster"])
+    assert int(got["n_clusters"][0]) == ref["n_clusters"]
+    return ref, got
+
+
+@pytest.mark.parametrize("seed,eps,min_pts", [(61, 5.0, 20), (62, 3.0, 10), (63, 8.0, 40)])
+def test_dbscan_reliable_points_bit_exact(seed, eps, min_pts):
+    print(f"[case] dbscan small seed={seed} eps={eps} min_pts={min_pts}", flush=True)
+    s = sv.vote_small(seed=seed)
+    v = ov.vote(s.points, s.cameras, s.masks, tau=2)
+    ref, _ = _check_dbscan(s.points, eps, min_pts, v["flags"])
+    assert ref["n_clusters"] > 3
+
+
+def test_dbscan_lattice_ties_hand_cases_and_degenerate_inputs():
+    print("[case] dbscan lattice / hand cases / degenerate", flush=True)
+    rng = np.random.default_rng(5)
+    g = np.stack(np.meshgrid(np.arange(0, 40, 0.5), np.arange(0, 30, 0.5)), 0).reshape(2, -1)
+    g = g[:, rng.uniform(size=g.shape[1]) < 0.5]
+    pts = np.vstack([g, np.zeros((1, g.shape[1]))]).astype(np.float32)
+    _check_dbscan(pts, 1.0, 4)
+    x = np.array([0, 1, 2, 3, 4.5, 6, 7, 8, 20], np.float32)
+    _check_dbscan(np.stack([x, np.zeros_like(x), np.zeros_like(x)]), 1.5, 3)
+    a = np.array([[4, 4, 4, 5, 0, 0, 0, -1, 2], [-1, 0, 1, 0, -1, 0, 1, 0, 0], [0] * 9], np.float32)
+    _check_dbscan(a, 2.0, 4)
+    # everything noise; everything one cluster; a single point; no point taking part
+    pts = sv.vote_small(seed=66, n_points=3000).points
+    ref, _ = _check_dbscan(pts, 0.5, 1000)
+    assert ref["n_clusters"] == 0
+    ref, _ = _check_dbscan(pts, 5000.0, 1)
+    assert ref["n_clusters"] == 1
+    _check_dbscan(pts[:, :1].copy(), 1.0, 1)
+    _check_dbscan(pts, 3.0, 5, np.zeros(pts.shape[1], np.uint8))
+
+
+def test_group_views_bit_exact():
+    print("[case] group views small", flush=True)
+    s = sv.vote_small(seed=61)
+    v = ov.vote(s.points, s.cameras, s.masks, tau=2)
+    ref = og.dbscan_points(s.points, 5.0, 20, (v["flags"] & 2) != 0)
+    hits_ref, asg_ref = og.assign_views(s.points, ref["cluster"], ref["n_clusters"], s.cameras, s.masks, 30)
+    pts = torch.from_numpy(s.points).cuda()
+    dm = [torch.from_numpy(m).cuda() for m in s.masks]
+    cl = torch.from_numpy(ref["cluster"].astype(np.int32)).cuda()
+    hits, asg = gs.group_views(pts, cl, ref["n_clusters"], s.cameras, dm, 30)
+    torch.cuda.synchronize()
+    assert np.array_equal(hits.cpu().numpy().astype(np.int64), hits_ref)
+    assert np.array_equal(asg.cpu().numpy().astype(bool), asg_ref)
+    # ids beyond max_clusters are ignored
+    hits2, _ = gs.group_views(pts, cl, 3, s.cameras, dm, 30)
+    torch.cuda.synchronize()
+    assert np.array_equal(hits2.cpu().numpy().astype(np.int64), hits_ref[:3])
+
+
+@pytest.mark.timeout(900)
+def test_grouping_full_size_bit_exact():
+    """The benchmarked grouping: the reliable points of the 2M-point,
+    64-view survey (about 1.36M points), eps 3 m, 10 points; then the views
+    of every group."""
+    print("[case] grouping full size", flush=True)
+    s = sv.vote_full()
+    v = ov.vote(s.points, s.cameras, s.masks, tau=3)
+    ref, got = _check_dbscan(s.points, 3.0, 10, v["flags"])
+    print(f"[info] full grouping: {ref['n_clusters']} groups over {int((ref['label'] >= 0).sum())} points",
+          flush=True)
+    hits_ref, asg_ref = og.assign_views(s.points, ref["cluster"], ref["n_clusters"], s.cameras, s.masks, 200)
+    pts = torch.from_numpy(s.points).cuda()
+    dm = [torch.from_numpy(m).cuda() for m in s.masks]
+    hits, asg = gs.group_views(pts, torch.from_numpy(got["cluster"]).cuda(), ref["n_clusters"], s.cameras, dm, 200)
+    torch.cuda.synchronize()
+    assert np.array_equal(hits.cpu().numpy().astype(np.int64), hits_ref)
+    assert np.array_equal(asg.cpu().numpy().astype(bool), asg_ref)
