@@ -187,3 +187,107 @@ def vote_full(seed=62, n_points=2_000_000, n_views=64):
     """Full voting workload: 2M sparse points of a 1 km^2 scene of 200
     buildings, 64 oblique views at 5472x3648 (the paper's image size)."""
     return survey(seed, n_points, n_views)
+
+
+@dataclass
+class DepthStack:
+    cameras: List[Camera]
+    depths: List[List[np.ndarray]]  # [view][group] float32 [H][W], 0 = no depth
+    boxes: np.ndarray
+    volume: dict                    # origin (3), voxel, dims (nx, ny, nz), trunc
+    info: dict = field(default_factory=dict)
+
+
+def _ray_box_depth(cam: Camera, boxes, ground=False, which=False):
+    """Camera-frame depth of the nearest hit of each pixel-centre ray with a
+    set of axis-aligned boxes (and the ground plane z = 0 if `ground`);
+    0 where nothing is hit.  With `which`, also the index of the box hit
+    (-1 for the ground or nothing).  The generator of the stand-in depth
+    maps."""
+    W, H = cam.width, cam.height
+    R = cam.R.astype(np.float64)
+    t = cam.t.astype(np.float64)
+    C = -R.T @ t
+    u = (np.arange(W) + 0.5 - cam.cx) / cam.fx
+    v = (np.arange(H) + 0.5 - cam.cy) / cam.fy
+    # world direction with camera-frame z = 1, so the ray parameter is the depth
+    dw = [R[0, a] * u[None, :] + R[1, a] * v[:, None] + R[2, a] for a in range(3)]
+    inv = [np.divide(1.0, d, out=np.full_like(d, np.inf), where=d != 0) for d in dw]
+    best = np.full((H, W), np.inf)
+    idx = np.full((H, W), -1)
+    for b, (cx, cy, w, d, h) in enumerate(boxes):
+        lo = (cx - w / 2, cy - d / 2, 0.0)
+        hi = (cx + w / 2, cy + d / 2, h)
+        tn = np.full((H, W), -np.inf)
+        tf = np.full((H, W), np.inf)
+        for a in range(3):
+            t0 = (lo[a] - C[a]) * inv[a]
+            t1 = (hi[a] - C[a]) * inv[a]
+            tn = np.maximum(tn, np.minimum(t0, t1))
+            tf = np.minimum(tf, np.maximum(t0, t1))
+        hit = (tn <= tf) & (tn > 0) & (tn < best)
+        best[hit] = tn[hit]
+        idx[hit] = b
+    if ground:
+        tg = -C[2] * inv[2]
+        g = (tg > 0) & (tg < best)
+        best[g] = tg[g]
+        idx[g] = -1
+    depth = np.where(np.isfinite(best), best, 0.0)
+    return (depth, idx) if which else depth
+
+
+def depth_stack(seed, n_views=8, width=1600, height=1200, f=1400.0, n_groups=3, n_boxes=8,
+                half_extent=100.0, distance=140.0, noise=0.05, holes=0.02, voxel=0.5, trunc=1.5):
+    """Depth maps of one sub-region seen by `n_views` oblique views (pitch 45
+    degrees, yaw every 360/n_views degrees, as the batched groups of the
+    rasterizer).  The boxes are split into `n_groups` building groups (by x)
+    plus one background block (the ground); each group's map holds the
+    depth of the visible surfaces of its own boxes (its building mask) and
+    the background's map the visible ground, each with its own N(0, noise %)
+    relative noise and `holes` of missing pixels.  Neighbouring groups share
+    their boundary boxes, so their maps overlap there.  The volume covers the sub-region
+    at `voxel` metres."""
+    rng = np.random.default_rng(seed)
+    boxes = _boxes(rng, n_boxes, half_extent)
+    order = np.argsort(boxes[:, 0])
+    split = np.array_split(order, n_groups)
+    # neighbouring groups share the boxes on their boundary (the last of one
+    # split and the first of the next)
+    members = [np.union1d(np.union1d(split[g], split[g + 1][:1] if g + 1 < n_groups else []),
+                          split[g - 1][-1:] if g > 0 else []).astype(np.int64) for g in range(n_groups)]
+    cams, depths = [], []
+    for vi in range(n_views):
+        yaw = 2 * math.pi * vi / n_views
+        eye = (distance * math.sin(yaw), -distance * math.cos(yaw), distance)
+        R, t = look_at(eye, (0.0, 0.0, 0.0))
+        cam = pinhole(width, height, f, f, width / 2, height / 2, R, t)
+        d_all, which = _ray_box_depth(cam, boxes, ground=True, which=True)
+        maps = []
+        for g in range(n_groups + 1):
+            own = np.isin(which, members[g]) if g < n_groups else (which < 0)
+            d = np.where(own, d_all, 0.0)
+            d = d * (1.0 + noise * 0.01 * rng.normal(size=d.shape))
+            d[rng.uniform(size=d.shape) < holes] = 0.0
+            maps.append(_f32(d))
+        cams.append(cam)
+        depths.append(maps)
+    ext = half_extent + 10.0
+    top = float(boxes[:, 4].max()) + 5.0
+    dims = (int(math.ceil(2 * ext / voxel)), int(math.ceil(2 * ext / voxel)), int(math.ceil(top / voxel)))
+    vol = dict(origin=_f32([-ext, -ext, -2.0]), voxel=float(np.float32(voxel)), dims=dims,
+               trunc=float(np.float32(trunc)))
+    return DepthStack(cams, depths, boxes, vol, info=dict(seed=seed, members=members))
+
+
+def depth_small(seed=81):
+    """Small fusion/TSDF workload: 4 views at 256x192, 2 groups, 2 m voxels."""
+    return depth_stack(seed, n_views=4, width=256, height=192, f=1400.0 * 256 / 1600, n_groups=2, voxel=2.0,
+                       trunc=5.0)
+
+
+def depth_full(seed=82):
+    """Full fusion/TSDF workload: one sub-region, 8 views at 1600x1200 with 3
+    building groups and the background block each, volume at 0.5 m voxels
+    (440 x 440 x ~250)."""
+    return depth_stack(seed)
