@@ -459,6 +459,53 @@ int pgsag_group_views(const pgsag_vote_view *host_views, const pgsag_vote_view *
                       const float *points, int64_t n_points, const int32_t *cluster, int32_t max_clusters,
                       float z_near, uint32_t min_hits, uint32_t *hits, uint8_t *assigned, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Depth fusion and TSDF integration (Sec. 4.4, "Mesh Extraction and
+ * Merge"): the depth maps several groups render from one view (the depth
+ * output of pgsag_forward) are merged by their mean where they overlap, and
+ * the fused maps of many views are integrated into a truncated signed
+ * distance volume (the TSDF method the paper cites).  Meshing itself is not
+ * part of this library. */
+
+/* Mean fusion of n_maps (1..64) depth maps of one view: for every pixel,
+ * over the maps with depth > 0 in their given order, s = s + depth (FP32,
+ * each addition rounded), fused = s / (their number) (one rounded
+ * division), 0 where none has a depth.  depths: host array of n_maps device
+ * pointers to float [height][width]; fused: device float [height][width];
+ * count: device uint8 [height][width] (maps with a depth) or NULL.  Every
+ * element written.  No allocation, no synchronisation; capturable. */
+int pgsag_fuse_depth(const float *const *depths, int32_t n_maps, int32_t width, int32_t height, float *fused,
+                     uint8_t *count, void *stream);
+
+typedef struct pgsag_volume {
+  float origin[3]; /* world position of the volume's corner */
+  float voxel;     /* voxel side (> 0) */
+  int32_t nx, ny, nz; /* voxels per side (0..2^23); storage [nz][ny][nx] */
+  float trunc;     /* truncation distance (> 0) */
+} pgsag_volume;
+
+typedef struct pgsag_depth_view {
+  pgsag_camera cam;
+  const float *depth; /* device float [H][W] (e.g. a fused map), 0 = no depth */
+} pgsag_depth_view;
+
+/* Projective TSDF with unit weights over n_views (0..65535) views.  Voxel
+ * (i, j, k) has the centre c = ((i + 0.5) voxel + origin_x, ...) (FP32, each
+ * operation rounded).  A view sees c when, with the projection of
+ * pgsag_vote, c is in front (zc > z_near) and inside the image, the depth D
+ * at its pixel is > 0 and sdf = D - zc >= -trunc; it then adds
+ * min(1, sdf / trunc) with weight 1.  accumulate = 0: tsdf = (sum of the
+ * added values) / W and weight = W (the number of views that saw the
+ * voxel), tsdf = 1 and weight = 0 where none did.  accumulate = 1: a running
+ * average continuing from the values already in tsdf and weight, tsdf =
+ * (W0 tsdf0 + sum) / (W0 + W), weight = W0 + W (voxels no view saw keep
+ * theirs).  tsdf, weight: device float [nz][ny][nx].  host_views and
+ * dev_views hold the same views (host copy validated, device copy read).
+ * No allocation, no synchronisation; capturable. */
+int pgsag_tsdf_integrate(const pgsag_volume *vol, const pgsag_depth_view *host_views,
+                         const pgsag_depth_view *dev_views, int32_t n_views, float z_near, float *tsdf,
+                         float *weight, int32_t accumulate, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,6 +1,7 @@
 """Python boundary of the survey-side steps around the rasterizer: the
 multi-view building-point voting filter (Sec. 4.1, Eq. 6-7) and the
-building grouping (Sec. 4.1: DBSCAN and the views of each group).
+building grouping (Sec. 4.1: DBSCAN and the views of each group), and the
+depth fusion and TSDF integration ahead of meshing (Sec. 4.4).
 
 Argument marshalling only: the views are packed into the C structs of
 include/pgsag.h, uploaded into a caller-owned device tensor, and every step
@@ -96,3 +97,62 @@ def group_views(points, cluster, max_clusters, cameras, masks, min_hits, z_near=
                                       float(z_near), int(min_hits), _p(hits), _p(assigned), _stream(stream)),
             "pgsag_group_views")
     return hits[:max_clusters], assigned[:max_clusters]
+
+
+def fuse_depth(maps, out=None, count=True, stream=None):
+    """Mean fusion (Sec. 4.4) of device float32 [H][W] depth maps of one view:
+    returns (fused float32 [H][W], count uint8 [H][W] or None)."""
+    if not maps:
+        raise ValueError("need at least one depth map")
+    H, W = maps[0].shape
+    for m in maps:
+        if m.dtype != torch.float32 or not m.is_cuda or not m.is_contiguous() or tuple(m.shape) != (H, W):
+            raise ValueError("depth maps must be contiguous float32 device tensors of one size")
+    fused = out if out is not None else torch.empty((H, W), dtype=torch.float32, device=maps[0].device)
+    cnt = torch.empty((H, W), dtype=torch.uint8, device=maps[0].device) if count else None
+    ptrs = (C.c_void_p * len(maps))(*[m.data_ptr() for m in maps])
+    A.check(A.lib().pgsag_fuse_depth(ptrs, len(maps), W, H, _p(fused), _p(cnt), _stream(stream)),
+            "pgsag_fuse_depth")
+    return fused, cnt
+
+
+def make_volume(origin, voxel, dims, trunc) -> A.Volume:
+    v = A.Volume()
+    v.origin = (C.c_float * 3)(*[float(x) for x in np.asarray(origin, np.float32)])
+    v.voxel = float(voxel)
+    v.nx, v.ny, v.nz = (int(d) for d in dims)
+    v.trunc = float(trunc)
+    return v
+
+
+def pack_depth_views(cameras, depths):
+    n = len(cameras)
+    host = (A.DepthView * n)()
+    for j, (cam, d) in enumerate(zip(cameras, depths)):
+        if d.dtype != torch.float32 or not d.is_cuda or not d.is_contiguous():
+            raise ValueError("depth maps must be contiguous float32 device tensors")
+        if tuple(d.shape) != (cam.height, cam.width):
+            raise ValueError(f"depth map {j} has shape {tuple(d.shape)}, camera is {cam.height}x{cam.width}")
+        host[j].cam = make_camera(cam)
+        host[j].depth = d.data_ptr()
+    raw = np.frombuffer(bytes(host), dtype=np.uint8) if n else np.zeros(1, np.uint8)
+    return host, torch.from_numpy(raw.copy()).cuda()
+
+
+def tsdf_integrate(volume, cameras, depths, z_near=0.2, tsdf=None, weight=None, accumulate=False, views=None,
+                   stream=None):
+    """Projective TSDF (Sec. 4.4) of the depth maps (device float32 [H][W],
+    one per camera) into the volume dict(origin, voxel, dims, trunc).
+    Returns (tsdf, weight), device float32 [nz][ny][nx]."""
+    nx, ny, nz = volume["dims"]
+    vol = make_volume(volume["origin"], volume["voxel"], volume["dims"], volume["trunc"])
+    dev = torch.device("cuda")
+    if tsdf is None:
+        tsdf = torch.empty((nz, ny, nx), dtype=torch.float32, device=dev)
+    if weight is None:
+        weight = torch.empty((nz, ny, nx), dtype=torch.float32, device=dev)
+    host, dv = views if views is not None else pack_depth_views(cameras, depths)
+    A.check(A.lib().pgsag_tsdf_integrate(C.byref(vol), host, _p(dv), len(host), float(z_near), _p(tsdf),
+                                         _p(weight), int(bool(accumulate)), _stream(stream)),
+            "pgsag_tsdf_integrate")
+    return tsdf, weight

@@ -48,6 +48,8 @@ STRUCTS = {
     "pgsag_layout": (A.Layout, ["status", "records", "grad2d", "end"]),
     "pgsag_status": (A.Status, ["pairs_needed", "overflow", "n_visible", "error", "reserved"]),
     "pgsag_vote_view": (A.VoteView, ["cam", "mask"]),
+    "pgsag_volume": (A.Volume, ["origin", "voxel", "nx", "nz", "trunc"]),
+    "pgsag_depth_view": (A.DepthView, ["cam", "depth"]),
 }
 
 
