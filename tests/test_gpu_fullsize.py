@@ -13,7 +13,9 @@
     256 sampled pixels per view, and the whole step -- forward, the loss of
     Sec. 4.2-4.3 (squared-L2 normal term, balance-load share 0.41), backward
     with the Adam update folded in at lr = 0 -- with the building mask cut to
-    one 32x32 crop per view, against the oracle's chain.
+    one 32x32 crop per view, each stage against the oracle on the same
+    inputs (planes, loss gradients at the GPU's planes, parameter gradients
+    of those loss gradients).
 """
 import numpy as np
 import pytest
@@ -232,15 +234,23 @@ def _subset(gs, ids):
 
 
 @pytest.mark.timeout(900)
-def test_training_scale_step_gradient_matches_oracle_chain(training_scale):
+def test_training_scale_step_stages_match_oracle(training_scale):
     """The captured-size training step on the 10M-Gaussian two-view batch
     with each view's building mask cut to one 32x32 crop (less its
-    near-threshold pixels): the loss (squared-L2 normal term, balance-load
-    share 0.41), the backward with Adam folded in at lr = 0 storing the
-    gradients, against the oracle's chain (its render, its loss gradients at
-    the FP32-rounded planes, its vector-Jacobian product).  The oracle works
-    on the Gaussians whose exact support meets a crop; every other Gaussian
-    must get exactly zero gradient."""
+    near-threshold pixels): forward, the loss (squared-L2 normal term,
+    balance-load share 0.41) and the backward with Adam folded in at lr = 0
+    storing the gradients.  Each stage is compared with the oracle on the
+    same inputs: the loss values and the loss gradients at the GPU's FP32
+    planes, and the parameter gradients as the oracle's vector-Jacobian
+    product of those loss gradients.  The oracle works on the Gaussians
+    whose exact support meets a crop; every other Gaussian must get exactly
+    zero gradient.
+
+    The stages are not chained through the oracle's own planes: at these
+    distances (about 770 m, 0.16 m per pixel) the depth-derived normal of
+    Sec. 4.2 differentiates the depth over a two-pixel baseline, which
+    multiplies the relative rounding of an FP32 depth (about 2e-6) some
+    2400-fold.  The chained comparison is printed for reference."""
     print("[case] 10M facade training step, crop masks", flush=True)
     sc, preps = training_scale
     gs = sc.sets[0]
@@ -254,8 +264,7 @@ def test_training_scale_step_gradient_matches_oracle_chain(training_scale):
     sub = _subset(gs, ids)
     olc = ol.LossConfig(lambda_normal=0.2, normal_norm=2, lambda_load=0.41)
     rng = np.random.default_rng(41)
-    masks, gts, losses = [], [], []
-    ref = {k: np.zeros(getattr(sub, k).shape) for k in PARAMS}
+    masks, gts, chain = [], [], []
     ex = np.zeros(sub.n, bool)
     for (v0, u0, s), rd in zip(crops, sc.renders):
         H, W = rd.camera.height, rd.camera.width
@@ -267,17 +276,11 @@ def test_training_scale_step_gradient_matches_oracle_chain(training_scale):
         bad = fw["unsafe"] | fw["depth_unreliable"]
         sel[cp[bad, 0], cp[bad, 1]] = False
         m1 = sel.astype(np.uint8)
-        r1 = oc.render(sub, rd.camera, m1, CFG)
-        im = r1["images"]
+        im = oc.render(sub, rd.camera, m1, CFG)["images"]
         off = rng.choice([-1.0, 1.0], (3, H, W)) * rng.uniform(0.02, 0.1, (3, H, W))
         gt = (im["rgb"] + off).astype(np.float32)
-        planes = {k: im[k].astype(np.float32) for k in ("rgb", "normal", "depth")}
-        lg = ol.loss_and_grads(planes["rgb"], planes["normal"], planes["depth"], gt, m1, rd.camera, olc)
-        losses.append(lg["total"])
-        g = oc.render_grad(sub, rd.camera, m1, CFG, {"rgb": lg["g_rgb"], "normal": lg["g_normal"],
-                                                     "depth": lg["g_depth"]})
-        for k in PARAMS:
-            ref[k] += g[k]
+        chain.append(ol.loss_and_grads(*(im[k].astype(np.float32) for k in ("rgb", "normal", "depth")), gt, m1,
+                                       rd.camera, olc))
         dec = op.decide(sub, rd.camera, CFG)
         ex |= (dec.colour_min < 1e-5) | (dec.clamp_margin < 1e-5) | (dec.flip_margin < 1e-5)
         masks.append(m1)
@@ -292,11 +295,35 @@ def test_training_scale_step_gradient_matches_oracle_chain(training_scale):
     out = t.step().cpu().numpy()
     torch.cuda.synchronize()
     assert not t.overflowed()
-    geo_gpu = (1 - 0.41) * (out[:, 1].astype(np.float64) + 0.2 * out[:, 2])
-    np.testing.assert_allclose(geo_gpu, losses, rtol=1e-4)
+    ref = {k: np.zeros(getattr(sub, k).shape) for k in PARAMS}
+    ref_chain = {k: np.zeros(getattr(sub, k).shape) for k in PARAMS}
+    for r, rd in enumerate(sc.renders):
+        m = masks[r].astype(bool)
+        planes = {k: t.batch.out[r][k].cpu().numpy() for k in ("rgb", "normal", "depth")}
+        gout = {k: t.batch.gout[r][k].cpu().numpy() for k in ("rgb", "normal", "depth")}
+        # the rendered planes at the crop pixels, under the image tolerances
+        ref_px = oc.render(sub, rd.camera, masks[r], CFG, pixels=np.argwhere(m))
+        rep = {}
+        assert not compare_images({k: t.batch.out[r][k].cpu().numpy() for k in t.batch.out[r]}, ref_px, rd, rep)
+        # loss values and gradients at the GPU's planes
+        lg = ol.loss_and_grads(planes["rgb"], planes["normal"], planes["depth"], gts[r], masks[r], rd.camera, olc)
+        np.testing.assert_allclose((1 - 0.41) * (out[r, 1].astype(np.float64) + 0.2 * out[r, 2]), lg["total"],
+                                   rtol=1e-4)
+        np.testing.assert_allclose(gout["rgb"][:, m], lg["g_rgb"][:, m], rtol=1e-6, atol=0)
+        for ch in ("normal", "depth"):
+            ok, ratio, rel = grad_tolerance_check(gout[ch][..., m], lg["g_" + ch][..., m])
+            assert ok, ("loss gradient", ch, r, ratio, rel)
+        g = oc.render_grad(sub, rd.camera, masks[r], CFG, gout)
+        gc = oc.render_grad(sub, rd.camera, masks[r], CFG, {k: chain[r]["g_" + k] for k in ("rgb", "normal", "depth")})
+        for k in PARAMS:
+            ref[k] += g[k]
+            ref_chain[k] += gc[k]
     for k in PARAMS:
         got = t.batch.grads[0][k].cpu().numpy()
         ok, ratio, rel = grad_tolerance_check(got[..., ids], ref[k], exclude=ex)
+        _, cratio, crel = grad_tolerance_check(got[..., ids], ref_chain[k], exclude=ex)
+        print(f"[info] {k}: worst ratio {ratio:.3f}, relative L2 {rel:.2e} "
+              f"(chained through the oracle's planes: {cratio:.3f}, {crel:.2e})", flush=True)
         assert ok, (k, ratio, rel)
         # outside the crops' supports: exactly zero
         rest = np.ones(gs.n, bool)
@@ -305,4 +332,3 @@ def test_training_scale_step_gradient_matches_oracle_chain(training_scale):
     # lr = 0: the parameters are unchanged, the step counter advanced
     np.testing.assert_array_equal(t.params[0]["means"].cpu().numpy(), gs.means)
     assert int(t.state[0]) == 1
-
