@@ -10,6 +10,9 @@ depth order (FP32 depth key, ties by index):
     C = sum c_i alpha_i T_i + T_final bg,  N = sum n_i alpha_i T_i  (Eq. 2)
     D = sum d_i alpha_i T_i (Eq. 3),       depth = D / (N . K^-1 p~)  (Eq. 4)
     alpha_out = 1 - T_final,   n_contrib = number of blended fragments
+    count = sum of alpha_i over the blended fragments (a soft n_contrib:
+            the differentiable stand-in for the contributor count g_i of
+            Eq. 9, whose own gradient is zero almost everywhere)
 
 Here the products over j are taken with a cumulative product along the
 depth order (a library step), the stop is the set of fragments whose
@@ -63,12 +66,12 @@ def _geo(proj, dec, pos=None):
 def composite_block(px, py, g: Geo, cfg, want_allow=True):
     """Composite pixel centres (px, py) [P] against candidates ``g`` (already
     in depth order).  Returns (F [P,7], T_final [P], n [P], allow [P,8],
-    grad_unsafe [P])."""
+    grad_unsafe [P], count [P])."""
     P, G = px.shape[0], g.mx.shape[0]
     if G == 0:
         F = torch.zeros((P, 7), dtype=F64)
         return F, torch.ones(P, dtype=F64), torch.zeros(P, dtype=torch.int64), \
-            torch.zeros((P, 8), dtype=F64), torch.zeros(P, dtype=torch.bool)
+            torch.zeros((P, 8), dtype=F64), torch.zeros(P, dtype=torch.bool), torch.zeros(P, dtype=F64)
     dx = px[:, None] - g.mx[None, :]
     dy = py[:, None] - g.my[None, :]
     q = g.a[None] * dx * dx + 2.0 * g.b[None] * dx * dy + g.c[None] * dy * dy
@@ -88,6 +91,7 @@ def composite_block(px, py, g: Geo, cfg, want_allow=True):
     F = w @ g.feat
     T = tin[:, -1]
     n = contrib.sum(dim=1)
+    count = a_c.sum(dim=1)
     allow = torch.zeros((P, 8), dtype=F64)
     unsafe = torch.zeros(P, dtype=torch.bool)
     if want_allow:
@@ -108,7 +112,7 @@ def composite_block(px, py, g: Geo, cfg, want_allow=True):
             allow[:, 6] += wf @ fa[:, 6]
             near_amax = live & keep & ((raw.detach() / cfg.alpha_max - 1.0).abs() < AMAX_MARGIN)
             unsafe = (allow.sum(1) > 0) | near_amax.any(1)
-    return F, T, n, allow, unsafe
+    return F, T, n, allow, unsafe, count
 
 
 def _candidates_by_cell(proj, cam, cfg, cell):
@@ -219,14 +223,14 @@ def render(gs, cam, mask, cfg, mode="culled", pixels=None, cell=16, prep=None):
     res = dict(pix=pix, rgb=np.zeros((Pn, 3)), normal=np.zeros((Pn, 3)), dist=np.zeros(Pn),
                depth=np.zeros(Pn), alpha=np.zeros(Pn), n_contrib=np.zeros(Pn, np.int64),
                allow=np.zeros((Pn, 8)), unsafe=np.zeros(Pn, bool),
-               depth_unreliable=np.zeros(Pn, bool), T=np.ones(Pn), den=np.zeros(Pn))
+               depth_unreliable=np.zeros(Pn, bool), T=np.ones(Pn), den=np.zeros(Pn), count=np.zeros(Pn))
     with torch.no_grad():
         g_all = _geo(proj, dec)
         for rows, cand in _groups(pix, proj, cam, cfg, mode, cell):
             g = Geo(*(getattr(g_all, f)[torch.as_tensor(cand)] for f in
                       ("mx", "my", "a", "b", "c", "o", "feat", "flip_near")))
             pixf = torch.tensor(pix[rows][:, ::-1] + 0.5, dtype=F64)  # (x, y)
-            F, T, n, allow, unsafe = composite_block(pixf[:, 0], pixf[:, 1], g, cfg)
+            F, T, n, allow, unsafe, count = composite_block(pixf[:, 0], pixf[:, 1], g, cfg)
             rgb, nrm, dist, depth, alpha, den, r = _pixel_outputs(F, T, pixf, cam, cfg)
             res["rgb"][rows] = rgb.numpy()
             res["normal"][rows] = nrm.numpy()
@@ -235,6 +239,7 @@ def render(gs, cam, mask, cfg, mode="culled", pixels=None, cell=16, prep=None):
             res["alpha"][rows] = alpha.numpy()
             res["T"][rows] = T.numpy()
             res["n_contrib"][rows] = n.numpy()
+            res["count"][rows] = count.numpy()
             res["den"][rows] = den.numpy()
             res["allow"][rows] = allow.numpy()
             nr = torch.linalg.norm(nrm, dim=1) * torch.linalg.norm(r, dim=1)
@@ -249,7 +254,7 @@ def render(gs, cam, mask, cfg, mode="culled", pixels=None, cell=16, prep=None):
             a = np.zeros((c, H, W))
             a[:, v, u] = res[name].T
             img[name] = a
-        for name in ("dist", "depth", "alpha"):
+        for name in ("dist", "depth", "alpha", "count"):
             a = np.zeros((H, W))
             a[v, u] = res[name]
             img[name] = a
@@ -265,7 +270,8 @@ def render_grad(gs, cam, mask, cfg, gout, pixels=None, mode="culled", cell=16):
     """Gradient of L = sum_p sum_ch gout_ch(p) out_ch(p) over the masked
     pixels (or the given (v, u) pixels) with respect to the raw parameters.
 
-    ``gout`` maps output name -> array [c][H][W] / [H][W] (missing = 0).
+    ``gout`` maps output name (rgb, normal, dist, depth, alpha, count) ->
+    array [c][H][W] / [H][W] (missing = 0).
     Returns dict of float64 arrays shaped like the inputs.
     """
     dec = decide(gs, cam, cfg)
@@ -286,7 +292,7 @@ def render_grad(gs, cam, mask, cfg, gout, pixels=None, mode="culled", cell=16):
         return g
 
     gplanes = {n: plane(n, c) for n, c in (("rgb", 3), ("normal", 3), ("dist", 1),
-                                            ("depth", 1), ("alpha", 1))}
+                                            ("depth", 1), ("alpha", 1), ("count", 1))}
     with torch.no_grad():
         proj_nd = {k: v.detach() for k, v in proj.items()}
     for rows, cand in _groups(pix, proj_nd, cam, cfg, mode, cell):
@@ -298,11 +304,11 @@ def render_grad(gs, cam, mask, cfg, gout, pixels=None, mode="culled", cell=16):
                 flip_near)
         pr = pix[rows]
         pixf = torch.tensor(pr[:, ::-1] + 0.5, dtype=F64)
-        F, T, n, _, _ = composite_block(pixf[:, 0], pixf[:, 1], g, cfg, want_allow=False)
+        F, T, n, _, _, count = composite_block(pixf[:, 0], pixf[:, 1], g, cfg, want_allow=False)
         rgb, nrm, dist, depth, alpha, _, _ = _pixel_outputs(F, T, pixf, cam, cfg)
         loss = torch.zeros((), dtype=F64)
         for name, val in (("rgb", rgb), ("normal", nrm), ("dist", dist), ("depth", depth),
-                          ("alpha", alpha)):
+                          ("alpha", alpha), ("count", count)):
             gp = gplanes[name]
             if gp is None:
                 continue
@@ -330,7 +336,7 @@ def loss_value(gs, cam, mask, cfg, gout, pixels=None, mode="culled"):
     pix = r["pix"]
     H, W = cam.height, cam.width
     tot = 0.0
-    for name, c in (("rgb", 3), ("normal", 3), ("dist", 1), ("depth", 1), ("alpha", 1)):
+    for name, c in (("rgb", 3), ("normal", 3), ("dist", 1), ("depth", 1), ("alpha", 1), ("count", 1)):
         g = gout.get(name)
         if g is None:
             continue

@@ -12,9 +12,15 @@ Per render, with M the number of masked pixels:
   L_geo  = lambda_rgb L_rgb + lambda_normal L_ban    (the PG-geo terms this
            path renders; the multi-view terms of Eq. 10 need other views'
            images and are not part of it)
-  L      = (1 - lambda_load) L_geo + lambda_load Var_t(pairs per active tile)
-           (Eq. 11; the balance term is a value only: a count has zero
-           gradient almost everywhere)
+  L      = (1 - lambda_load) L_geo + lambda_load L_load       (Eq. 11)
+  L_load = load_term 0: Var_t(pairs per active tile), a value only (a
+           count has zero gradient almost everywhere);
+           load_term 1: the GC-load of Eq. 9, std over masked pixels of
+           x_i = g_i / w_i with g_i = n_contrib, taken with a gradient
+           through the soft count s_i = sum of alpha over the fragments
+           blended at pixel i: the value uses the integer g_i, and
+           dL/ds_i = dL/dg_i = lambda_load (x_i - mean x) / (M std x w_i)
+           (straight through; 0 when std x = 0)
 
 Readings (where the paper is silent):
   - MB: masked pixels with at least one unmasked 4-neighbour inside the
@@ -52,6 +58,7 @@ class LossConfig:
     lambda_load: float = 0.0
     normal_norm: int = 1          # 1 = L1, 2 = squared L2
     normal_eps: float = 1e-6
+    load_term: int = 0            # 0 = tile-count variance (value), 1 = Eq. 9 GC-load
 
 
 def as_mask(mask, shape):
@@ -145,20 +152,28 @@ def tile_load_variance(tile_pairs, tile_active):
     return float(c.var()) if c.size else 0.0
 
 
-def loss_and_grads(rgb32, normal32, depth32, gt32, mask, cam, lc: LossConfig, load_var=0.0):
-    """Total loss and dL/d(rgb, normal, depth) at FP32 inputs (upcast)."""
+def loss_and_grads(rgb32, normal32, depth32, gt32, mask, cam, lc: LossConfig, load_var=0.0, n_contrib=None,
+                   weight=None):
+    """Total loss and dL/d(rgb, normal, depth) at FP32 inputs (upcast), and
+    dL/d(soft count) (zero unless lc.load_term is 1; then n_contrib [H][W]
+    and the Eq. 9 weights (None = 1) are needed, and load_var is not used)."""
     rgb = torch.tensor(np.asarray(rgb32, np.float64), requires_grad=True)
     nrm = torch.tensor(np.asarray(normal32, np.float64), requires_grad=True)
     dep = torch.tensor(np.asarray(depth32, np.float64), requires_grad=True)
     l_rgb, l_ban = geo_terms(rgb, nrm, dep, np.asarray(gt32, np.float64), mask, cam, lc,
                              normal32=np.asarray(normal32, np.float32))
     geo = lc.lambda_rgb * l_rgb + lc.lambda_normal * l_ban
-    total = (1.0 - lc.lambda_load) * geo + lc.lambda_load * load_var
+    g_count = np.zeros(np.shape(depth32))
+    load = float(load_var)
+    if lc.load_term == 1:
+        w = np.ones(np.shape(depth32)) if weight is None else weight
+        load, dg = gc_load_and_grad(n_contrib, w, mask)
+        g_count = lc.lambda_load * dg
+    total = (1.0 - lc.lambda_load) * geo + lc.lambda_load * load
     g = torch.autograd.grad(total, [rgb, nrm, dep], allow_unused=True)
     grads = [np.zeros(t.shape) if gi is None else gi.numpy() for gi, t in zip(g, (rgb, nrm, dep))]
     return dict(total=float(total.detach()), rgb=float(l_rgb.detach()), normal=float(l_ban.detach()),
-                load=float(load_var),
-                g_rgb=grads[0], g_normal=grads[1], g_depth=grads[2])
+                load=load, g_rgb=grads[0], g_normal=grads[1], g_depth=grads[2], g_count=g_count)
 
 
 def sign_margins(rgb32, normal32, depth32, gt32, mask, cam, lc: LossConfig):
@@ -194,3 +209,25 @@ def gc_load(n_contrib, weight, mask):
     m = as_mask(mask, np.shape(n_contrib))
     x = np.asarray(n_contrib, np.float64)[m] / np.asarray(weight, np.float64)[m]
     return float(x.std()) if x.size else 0.0
+
+
+def gc_load_and_grad(n_contrib, weight, mask):
+    """Eq. 9 GC-load and its gradient with respect to the per-pixel counts:
+    sigma = population std over the M masked pixels of x_i = g_i / w_i, and
+    d sigma / d g_i = (x_i - mean x) / (M sigma w_i) at masked pixels (0
+    elsewhere, and everywhere when sigma = 0).  The gradient is the one the
+    soft count carries (straight through the integer count)."""
+    shape = np.shape(n_contrib)
+    m = as_mask(mask, shape)
+    g = np.asarray(n_contrib, np.float64)
+    w = np.asarray(weight, np.float64)
+    grad = np.zeros(shape)
+    M = int(m.sum())
+    if M == 0:
+        return 0.0, grad
+    x = g[m] / w[m]
+    mu = x.mean()
+    sigma = float(np.sqrt(((x - mu) ** 2).mean()))
+    if sigma > 0:
+        grad[m] = (x - mu) / (M * sigma * w[m])
+    return sigma, grad

@@ -205,3 +205,58 @@ def test_gc_load_and_tile_variance_closed_forms():
     assert abs(ol.gc_load(g, w, m) - 1.0) < 1e-15          # values 2 and 4, half each
     assert ol.gc_load(np.full((4, 5), 7), np.ones((4, 5)), m) == 0.0
     assert abs(ol.tile_load_variance([1, 3, 100, 5], [True, True, False, True]) - 8.0 / 3.0) < 1e-14
+
+
+def test_gc_load_gradient_against_library_std():
+    """Eq. 9's GC-load std(g / w) over masked pixels: its value is numpy's
+    population std, its gradient in each g_i agrees with central
+    differences of numpy.std, the weighted gradient sums to zero (a shift of
+    every x_i leaves the std unchanged), and a constant x has none."""
+    rng = np.random.default_rng(9)
+    H, W = 6, 7
+    m = rng.uniform(size=(H, W)) < 0.7
+    g = rng.integers(0, 40, (H, W)).astype(np.float64)
+    w = rng.uniform(0.1, 3.0, (H, W))
+    val, grad = ol.gc_load_and_grad(g, w, m)
+    assert abs(val - np.std(g[m] / w[m])) < 1e-14
+    assert abs(val - ol.gc_load(g, w, m)) < 1e-14
+    assert np.all(grad[~m] == 0)
+    for i in np.flatnonzero(m.ravel())[:12]:
+        h = 1e-5
+        gp, gm = g.copy(), g.copy()
+        gp.ravel()[i] += h
+        gm.ravel()[i] -= h
+        fd = (np.std(gp[m] / w[m]) - np.std(gm[m] / w[m])) / (2 * h)
+        assert abs(fd - grad.ravel()[i]) <= 1e-8 * max(1.0, abs(fd)), (i, fd, grad.ravel()[i])
+    assert abs((grad * w)[m].sum()) < 1e-12
+    w2 = np.where(rng.uniform(size=(H, W)) < 0.5, 0.5, 2.0)   # x = g / w exactly 3
+    v0, g0 = ol.gc_load_and_grad(3.0 * w2, w2, m)
+    assert v0 < 1e-12 and np.all(g0 == 0)
+
+
+def test_loss_with_the_gc_load_term():
+    """load_term 1: L = (1 - lambda) L_geo + lambda std(g / w), and the
+    soft-count gradient is lambda times that of the std; the geometric
+    gradients are scaled by (1 - lambda) only."""
+    cam = _cam(20, 16)
+    m = _blob_mask(4, 16, 20)
+    rng = np.random.default_rng(3)
+    rgb = rng.uniform(0, 1, (3, 16, 20)).astype(np.float32)
+    gt = rng.uniform(0, 1, (3, 16, 20)).astype(np.float32)
+    nrm = np.zeros((3, 16, 20), np.float32)
+    nrm[2] = -1
+    dep = np.full((16, 20), 3.0, np.float32)
+    nc = rng.integers(1, 30, (16, 20))
+    w = rng.uniform(0.2, 2.0, (16, 20))
+    lam = 0.41
+    base = ol.loss_and_grads(rgb, nrm, dep, gt, m, cam, ol.LossConfig())
+    lc = ol.LossConfig(lambda_load=lam, load_term=1)
+    r = ol.loss_and_grads(rgb, nrm, dep, gt, m, cam, lc, n_contrib=nc, weight=w)
+    val, grad = ol.gc_load_and_grad(nc, w, m)
+    assert abs(r["load"] - val) < 1e-15
+    assert abs(r["total"] - ((1 - lam) * base["total"] + lam * val)) < 1e-12
+    np.testing.assert_allclose(r["g_count"], lam * grad, rtol=0, atol=1e-18)
+    np.testing.assert_allclose(r["g_rgb"], (1 - lam) * base["g_rgb"], rtol=1e-12, atol=0)
+    # the tile-variance term (load_term 0) carries no count gradient
+    r0 = ol.loss_and_grads(rgb, nrm, dep, gt, m, cam, ol.LossConfig(lambda_load=lam), load_var=5.0)
+    assert np.all(r0["g_count"] == 0) and r0["load"] == 5.0

@@ -381,6 +381,76 @@ def test_gradient_matches_central_differences(seed):
             assert abs(fd - ad) <= 1e-6 * max(1.0, abs(ad)) + 1e-7, (name, i, fd, ad)
 
 
+def test_soft_count_closed_forms():
+    """The soft contributor count (sum of alpha over the blended fragments,
+    the differentiable stand-in for g_i of Eq. 9): one Gaussian at a pixel
+    centre gives its alpha; three stacked ones give the plain sum of their
+    alphas (not weighted by transmittance); behind opaque layers only the
+    blended ones count."""
+    cam = cam_id(32, 32, 32.0)
+    o = 0.45
+    gs = make_set([at_pixel(cam, 10, 12, 2.5)], [[-3.0, -3.5, -4.0]], [[1.0, 0, 0, 0]], [logit(o)],
+                  colours=[[0.2, 0.7, 0.9]])
+    r = oc.render(gs, cam, None, CFG, mode="brute")
+    o32 = 1 / (1 + math.exp(-float(np.float32(logit(o)))))
+    np.testing.assert_allclose(r["images"]["count"][12, 10], o32, rtol=1e-12)
+    os_ = [0.6, 0.5, 0.7]
+    pts = [at_pixel(cam, 15, 15, z) for z in (2.0, 3.0, 5.0)]
+    gs3 = make_set(pts, [[-2.5, -2.6, -5.0]] * 3, [[1.0, 0, 0, 0]] * 3, [logit(v) for v in os_],
+                   colours=[[0.5, 0.5, 0.5]] * 3)
+    r3 = oc.render(gs3, cam, None, CFG, mode="brute", pixels=[(15, 15)])
+    a = [1 / (1 + math.exp(-float(np.float32(logit(v))))) for v in os_]
+    np.testing.assert_allclose(r3["count"][0], sum(a), rtol=1e-12)
+    assert r3["n_contrib"][0] == 3
+    # 0.99 layers: the stop leaves two blended, each alpha 0.99
+    pts4 = [at_pixel(cam, 8, 8, z) for z in (2.0, 2.5, 3.0, 3.5)]
+    gs4 = make_set(pts4, [[-2.0, -2.0, -5.0]] * 4, [[1.0, 0, 0, 0]] * 4, [8.0] * 4, colours=[[1, 1, 1]] * 4)
+    r4 = oc.render(gs4, cam, None, CFG, mode="brute", pixels=[(8, 8)])
+    assert r4["n_contrib"][0] == 2
+    np.testing.assert_allclose(r4["count"][0], 2 * 0.99, rtol=1e-12)
+
+
+def _count64(gs, p64, cam, c):
+    """sum_p c_p count_p with perturbed FP64 parameters and the decisions of
+    the unperturbed FP32 inputs."""
+    dec = op.decide(gs, cam, CFG)
+    p = {k: torch.tensor(v) for k, v in p64.items()}
+    with torch.no_grad():
+        proj = op.project(p, cam, dec, CFG)
+        g = oc._geo(proj, dec)
+        pix = oc._pixel_list(cam, None, None)
+        pixf = torch.tensor(pix[:, ::-1] + 0.5, dtype=torch.float64)
+        *_, count = oc.composite_block(pixf[:, 0], pixf[:, 1], g, CFG, want_allow=False)
+    return float((torch.tensor(c[pix[:, 0], pix[:, 1]]) * count).sum())
+
+
+def test_soft_count_gradient_by_central_differences():
+    gs, rd = _fd_scene(23)
+    cam = rd.camera
+    fw = oc.render(gs, cam, None, CFG, mode="brute")
+    c = np.random.default_rng(5).normal(size=(cam.height, cam.width))
+    unsafe = np.zeros((cam.height, cam.width), bool)
+    unsafe[fw["pix"][:, 0], fw["pix"][:, 1]] = fw["unsafe"]
+    c = c * ~unsafe
+    assert fw["images"]["count"].max() > 0.5
+    g = oc.render_grad(gs, cam, None, CFG, {"count": c}, mode="brute")
+    assert np.all(g["sh"] == 0)   # the count does not see colour
+    rng = np.random.default_rng(23)
+    for name in ("means", "log_scales", "quats", "opacity_logits"):
+        flat = getattr(gs, name).reshape(-1)
+        for i in rng.choice(flat.size, size=min(10, flat.size), replace=False):
+            base = np.float64(flat[i])
+            h = 1e-6 * max(1.0, abs(base))
+            vals = []
+            for sgn in (+1, -1):
+                p64 = {k: np.asarray(v, np.float64).copy() for k, v in gs.arrays().items()}
+                p64[name].reshape(-1)[i] = base + sgn * h
+                vals.append(_count64(gs, p64, cam, c))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            ad = g[name].reshape(-1)[i]
+            assert abs(fd - ad) <= 1e-6 * max(1.0, abs(ad)) + 1e-7, (name, i, fd, ad)
+
+
 def _loss64(gs, p64, cam, gout):
     """FP64 forward with perturbed FP64 parameters, decisions from the
     unperturbed FP32 inputs (they are all far from their thresholds)."""
@@ -391,7 +461,7 @@ def _loss64(gs, p64, cam, gout):
         g = oc._geo(proj, dec)
         pix = oc._pixel_list(cam, None, None)
         pixf = torch.tensor(pix[:, ::-1] + 0.5, dtype=torch.float64)
-        F, T, n, _, _ = oc.composite_block(pixf[:, 0], pixf[:, 1], g, CFG, want_allow=False)
+        F, T, n, _, _, _ = oc.composite_block(pixf[:, 0], pixf[:, 1], g, CFG, want_allow=False)
         rgb, nrm, dist, depth, alpha, _, _ = oc._pixel_outputs(F, T, pixf, cam, CFG)
     tot = 0.0
     for name, val in (("rgb", rgb), ("normal", nrm), ("dist", dist), ("depth", depth), ("alpha", alpha)):
