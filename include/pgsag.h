@@ -46,7 +46,8 @@
  * Ownership: the caller owns every buffer -- parameters, outputs,
  * gradients, the workspace and the device copy of the descriptor.  The
  * library never allocates or frees device memory and keeps no global
- * mutable state except the thread-local error string.  Work is enqueued on
+ * mutable state except the thread-local error string and the static
+ * scratch array of pgsag_dbscan_static (held per GPU by the library).  Work is enqueued on
  * the caller's HIP stream (passed as void*, a hipStream_t; NULL = the null
  * stream); no call synchronises except pgsag_read_status.  pgsag_forward
  * and pgsag_backward are capturable into a HIP graph.
@@ -446,6 +447,26 @@ int pgsag_dbscan_workspace(int64_t n_points, uint64_t *bytes);
 int pgsag_dbscan(const float *points, int64_t n_points, const uint8_t *flags, uint32_t flag_mask, float eps,
                  int32_t min_pts, int32_t *count, int32_t *label, int32_t *cluster, uint32_t *n_clusters,
                  void *workspace, uint64_t workspace_bytes, void *stream);
+
+/* The scratch of pgsag_dbscan_static: up to this many points. */
+#define PGSAG_DBSCAN_STATIC_MAX_POINTS (1 << 19)
+
+/* pgsag_dbscan without a workspace argument, for callers that cannot
+ * allocate device memory (work under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, results and
+ * validation as pgsag_dbscan, with n_points limited to
+ * PGSAG_DBSCAN_STATIC_MAX_POINTS (more: INVALID_ARGUMENT, nothing
+ * launched).  The scratch is a static device array of the library
+ * (23,609,600 bytes) that each GPU it runs on holds from its first call there until the
+ * process ends; its device address is looked up on that first call, on the
+ * current device, which must be the device of `stream`.  Every call on one
+ * GPU shares that GPU's array (the kernels rewrite what they read in each
+ * call): calls that overlap on one GPU -- on different streams or from
+ * different threads -- race and give wrong results.  No allocation, no
+ * synchronisation. */
+int pgsag_dbscan_static(const float *points, int64_t n_points, const uint8_t *flags, uint32_t flag_mask, float eps,
+                        int32_t min_pts, int32_t *count, int32_t *label, int32_t *cluster, uint32_t *n_clusters,
+                        void *stream);
 
 /* Views of each group ("subgroups that each contain the ... original
  * images", Sec. 4.1): hits[c][j] = points with cluster id c that land inside

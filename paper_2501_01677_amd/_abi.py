@@ -103,7 +103,7 @@ SYMBOLS = ("pgsag_version", "pgsag_last_error", "pgsag_default_config", "pgsag_p
            "pgsag_layout_of", "pgsag_forward", "pgsag_backward", "pgsag_binning",
            "pgsag_read_status", "pgsag_adam_step", "pgsag_load_stats", "pgsag_default_loss_config",
            "pgsag_loss", "pgsag_luminance_weights", "pgsag_adam_step_device", "pgsag_backward_adam",
-           "pgsag_vote", "pgsag_dbscan_workspace", "pgsag_dbscan", "pgsag_group_views",
+           "pgsag_vote", "pgsag_dbscan_workspace", "pgsag_dbscan", "pgsag_dbscan_static", "pgsag_group_views",
            "pgsag_fuse_depth", "pgsag_tsdf_integrate")
 
 _lib = None
@@ -143,6 +143,7 @@ def lib():
     L.pgsag_vote.argtypes = [C.POINTER(VoteView), vp, i32, vp, i64, f32, i32, vp, vp, vp, vp]
     L.pgsag_dbscan_workspace.argtypes = [i64, C.POINTER(C.c_uint64)]
     L.pgsag_dbscan.argtypes = [vp, i64, vp, C.c_uint32, f32, i32, vp, vp, vp, vp, vp, u64, vp]
+    L.pgsag_dbscan_static.argtypes = [vp, i64, vp, C.c_uint32, f32, i32, vp, vp, vp, vp, vp]
     L.pgsag_fuse_depth.argtypes = [C.POINTER(vp), i32, i32, i32, vp, vp, vp]
     L.pgsag_tsdf_integrate.argtypes = [C.POINTER(Volume), C.POINTER(DepthView), vp, i32, f32, vp, vp, i32, vp]
     L.pgsag_group_views.argtypes = [C.POINTER(VoteView), vp, i32, vp, i64, vp, i32, f32, C.c_uint32, vp, vp, vp]

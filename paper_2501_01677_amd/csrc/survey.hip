@@ -15,6 +15,7 @@
 // taken in FP32 with one fixed operation order and no contraction: every
 // multiply, add and the (correctly rounded) division rounds on its own.
 #include <cmath>
+#include <mutex>
 
 #include "internal.h"
 
@@ -445,9 +446,9 @@ struct DbsLayout {
   uint32_t H;
 };
 
-inline uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+constexpr uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
-DbsLayout dbs_layout(int64_t n) {
+constexpr DbsLayout dbs_layout(int64_t n) {
   DbsLayout L{};
   uint64_t H = 1024;
   while (H < 2 * (uint64_t)n) H <<= 1;
@@ -490,6 +491,108 @@ __global__ void copy_u32_kernel(const uint32_t *__restrict__ a, uint32_t *__rest
 
 constexpr int64_t kDbsMaxPoints = int64_t(1) << 23;
 
+// Runs the DBSCAN kernels on scratch memory ws of at least
+// dbs_layout(n_points).end bytes (arguments already validated, n_points > 0).
+int dbscan_run(const float *points, int64_t n_points, const uint8_t *flags, uint32_t flag_mask, float eps,
+               int32_t min_pts, int32_t *count, int32_t *label, int32_t *cluster, uint32_t *n_clusters,
+               char *ws, hipStream_t s) {
+  const DbsLayout L = dbs_layout(n_points);
+  Dbs d{};
+  d.pts = points;
+  d.n = n_points;
+  d.flags = flags;
+  d.flag_mask = flag_mask;
+  d.e2 = eps * eps;
+  d.inv_side = 1.0 / (1.01 * (double)eps);
+  d.min_pts = min_pts;
+  d.hmask = L.H - 1;
+  d.bcount = reinterpret_cast<uint32_t *>(ws + L.bcount);
+  d.bstart = reinterpret_cast<uint32_t *>(ws + L.bstart);
+  d.cursor = reinterpret_cast<uint32_t *>(ws + L.cursor);
+  d.pbucket = reinterpret_cast<uint32_t *>(ws + L.pbucket);
+  d.sidx = reinterpret_cast<uint32_t *>(ws + L.sidx);
+  d.parent = reinterpret_cast<uint32_t *>(ws + L.parent);
+  d.npart = reinterpret_cast<uint32_t *>(ws + L.npart);
+  d.scan_sums = reinterpret_cast<uint32_t *>(ws + L.sums);
+  d.sxy = reinterpret_cast<float2 *>(ws + L.sxy);
+  d.score = reinterpret_cast<uint8_t *>(ws + L.score);
+  d.count = count;
+  d.label = label;
+  d.cluster = cluster;
+  d.n_clusters = n_clusters;
+  const unsigned pb = blocks_of((uint64_t)n_points);
+  // every scratch word the kernels read is written first in this call
+  // (the bucket counts by a fill kernel), so nothing carries over between
+  // calls on the same scratch
+  launch_fill(d.bcount, 0u, L.H, s);
+  hipLaunchKernelGGL(dbs_bucket_kernel, dim3(pb), dim3(256), 0, s, d);
+  launch_scan(d.bcount, d.bstart, d.scan_sums, d.npart, L.H, s);
+  hipLaunchKernelGGL(copy_u32_kernel, dim3(4096), dim3(256), 0, s, (const uint32_t *)d.bstart, d.cursor, (uint64_t)L.H);
+  hipLaunchKernelGGL(dbs_scatter_kernel, dim3(pb), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(dbs_count_kernel, dim3(pb), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(dbs_union_kernel, dim3(pb), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(dbs_root_kernel, dim3(pb), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(dbs_border_kernel, dim3(pb), dim3(256), 0, s, d);
+  // compact ids: root flags (in the cursor buffer, free after the scatter),
+  // scanned in place
+  uint32_t *ids = d.cursor;
+  hipLaunchKernelGGL(dbs_rootflag_kernel, dim3(pb), dim3(256), 0, s, d, ids);
+  launch_scan(ids, ids, d.scan_sums, n_clusters, (uint64_t)n_points, s);
+  if (cluster) hipLaunchKernelGGL(dbs_cluster_kernel, dim3(pb), dim3(256), 0, s, d, (const uint32_t *)ids);
+  return hip_status("dbscan");
+}
+
+// Validation shared by both DBSCAN entry points (all but the scratch).
+int dbscan_check(const float *points, int64_t n_points, int64_t max_points, float eps, int32_t min_pts,
+                 const int32_t *label, const uint32_t *n_clusters) {
+  if (n_points < 0 || n_points > max_points)
+    return set_error(PGSAG_INVALID_ARGUMENT, "n_points must be in 0..%lld", (long long)max_points);
+  if (!(eps > 0.f) || !std::isfinite(eps)) return set_error(PGSAG_INVALID_ARGUMENT, "eps must be finite and > 0");
+  if (min_pts < 1) return set_error(PGSAG_INVALID_ARGUMENT, "min_pts must be >= 1");
+  if (!n_clusters) return set_error(PGSAG_INVALID_ARGUMENT, "null n_clusters");
+  if (n_points > 0 && (!points || !label)) return set_error(PGSAG_INVALID_ARGUMENT, "null points or label");
+  return PGSAG_OK;
+}
+
+// ---------------------------------------------------------------------
+// Library-owned DBSCAN scratch for pgsag_dbscan_static: room for
+// PGSAG_DBSCAN_STATIC_MAX_POINTS points.  Each GPU the library runs on
+// holds its own copy of the array until the process ends.  In host code
+// `scratch` names a host-side stand-in, never a device address: the device
+// address is taken once per device with hipGetSymbolAddress (that device
+// current) and kept in scratch_ptr.
+constexpr uint64_t kStaticScratchBytes = dbs_layout(PGSAG_DBSCAN_STATIC_MAX_POINTS).end;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+}  // namespace pgsag
+
+static __device__ __align__(256) uint8_t scratch[pgsag::kStaticScratchBytes];
+
+namespace pgsag {
+namespace {
+
+std::mutex scratch_mu;
+void *scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (taken on its first use there).
+int static_scratch(char **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_error(PGSAG_HIP_ERROR, "hipGetDevice: %s", hipGetErrorName(e));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(PGSAG_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(PGSAG_HIP_ERROR, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorName(e));
+    scratch_ptr[dev] = p;
+  }
+  *out = static_cast<char *>(scratch_ptr[dev]);
+  return PGSAG_OK;
+}
+
 }  // namespace
 }  // namespace pgsag
 
@@ -530,13 +633,9 @@ int pgsag_dbscan_workspace(int64_t n_points, uint64_t *bytes) {
 int pgsag_dbscan(const float *points, int64_t n_points, const uint8_t *flags, uint32_t flag_mask, float eps,
                  int32_t min_pts, int32_t *count, int32_t *label, int32_t *cluster, uint32_t *n_clusters,
                  void *workspace, uint64_t workspace_bytes, void *stream) {
-  if (n_points < 0 || n_points > kDbsMaxPoints)
-    return set_error(PGSAG_INVALID_ARGUMENT, "n_points must be in 0..%lld", (long long)kDbsMaxPoints);
-  if (!(eps > 0.f) || !std::isfinite(eps)) return set_error(PGSAG_INVALID_ARGUMENT, "eps must be finite and > 0");
-  if (min_pts < 1) return set_error(PGSAG_INVALID_ARGUMENT, "min_pts must be >= 1");
-  if (!n_clusters) return set_error(PGSAG_INVALID_ARGUMENT, "null n_clusters");
-  if (n_points > 0 && (!points || !label || !workspace))
-    return set_error(PGSAG_INVALID_ARGUMENT, "null points, label or workspace");
+  const int rc = dbscan_check(points, n_points, kDbsMaxPoints, eps, min_pts, label, n_clusters);
+  if (rc != PGSAG_OK) return rc;
+  if (n_points > 0 && !workspace) return set_error(PGSAG_INVALID_ARGUMENT, "null workspace");
   const DbsLayout L = dbs_layout(n_points);
   if (n_points > 0 && workspace_bytes < L.end)
     return set_error(PGSAG_WORKSPACE_TOO_SMALL, "workspace needs %llu bytes", (unsigned long long)L.end);
@@ -545,47 +644,24 @@ int pgsag_dbscan(const float *points, int64_t n_points, const uint8_t *flags, ui
     launch_fill(n_clusters, 0u, 1, s);
     return hip_status("dbscan");
   }
-  char *ws = static_cast<char *>(workspace);
-  Dbs d{};
-  d.pts = points;
-  d.n = n_points;
-  d.flags = flags;
-  d.flag_mask = flag_mask;
-  d.e2 = eps * eps;
-  d.inv_side = 1.0 / (1.01 * (double)eps);
-  d.min_pts = min_pts;
-  d.hmask = L.H - 1;
-  d.bcount = reinterpret_cast<uint32_t *>(ws + L.bcount);
-  d.bstart = reinterpret_cast<uint32_t *>(ws + L.bstart);
-  d.cursor = reinterpret_cast<uint32_t *>(ws + L.cursor);
-  d.pbucket = reinterpret_cast<uint32_t *>(ws + L.pbucket);
-  d.sidx = reinterpret_cast<uint32_t *>(ws + L.sidx);
-  d.parent = reinterpret_cast<uint32_t *>(ws + L.parent);
-  d.npart = reinterpret_cast<uint32_t *>(ws + L.npart);
-  d.scan_sums = reinterpret_cast<uint32_t *>(ws + L.sums);
-  d.sxy = reinterpret_cast<float2 *>(ws + L.sxy);
-  d.score = reinterpret_cast<uint8_t *>(ws + L.score);
-  d.count = count;
-  d.label = label;
-  d.cluster = cluster;
-  d.n_clusters = n_clusters;
-  const unsigned pb = blocks_of((uint64_t)n_points);
-  launch_fill(d.bcount, 0u, L.H, s);
-  hipLaunchKernelGGL(dbs_bucket_kernel, dim3(pb), dim3(256), 0, s, d);
-  launch_scan(d.bcount, d.bstart, d.scan_sums, d.npart, L.H, s);
-  hipLaunchKernelGGL(copy_u32_kernel, dim3(4096), dim3(256), 0, s, (const uint32_t *)d.bstart, d.cursor, (uint64_t)L.H);
-  hipLaunchKernelGGL(dbs_scatter_kernel, dim3(pb), dim3(256), 0, s, d);
-  hipLaunchKernelGGL(dbs_count_kernel, dim3(pb), dim3(256), 0, s, d);
-  hipLaunchKernelGGL(dbs_union_kernel, dim3(pb), dim3(256), 0, s, d);
-  hipLaunchKernelGGL(dbs_root_kernel, dim3(pb), dim3(256), 0, s, d);
-  hipLaunchKernelGGL(dbs_border_kernel, dim3(pb), dim3(256), 0, s, d);
-  // compact ids: root flags (in the cursor buffer, free after the scatter),
-  // scanned in place
-  uint32_t *ids = d.cursor;
-  hipLaunchKernelGGL(dbs_rootflag_kernel, dim3(pb), dim3(256), 0, s, d, ids);
-  launch_scan(ids, ids, d.scan_sums, n_clusters, (uint64_t)n_points, s);
-  if (cluster) hipLaunchKernelGGL(dbs_cluster_kernel, dim3(pb), dim3(256), 0, s, d, (const uint32_t *)ids);
-  return hip_status("dbscan");
+  return dbscan_run(points, n_points, flags, flag_mask, eps, min_pts, count, label, cluster, n_clusters,
+                    static_cast<char *>(workspace), s);
+}
+
+int pgsag_dbscan_static(const float *points, int64_t n_points, const uint8_t *flags, uint32_t flag_mask, float eps,
+                        int32_t min_pts, int32_t *count, int32_t *label, int32_t *cluster, uint32_t *n_clusters,
+                        void *stream) {
+  const int rc = dbscan_check(points, n_points, PGSAG_DBSCAN_STATIC_MAX_POINTS, eps, min_pts, label, n_clusters);
+  if (rc != PGSAG_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n_points == 0) {
+    launch_fill(n_clusters, 0u, 1, s);
+    return hip_status("dbscan (static scratch)");
+  }
+  char *ws = nullptr;
+  const int sc = static_scratch(&ws);
+  if (sc != PGSAG_OK) return sc;
+  return dbscan_run(points, n_points, flags, flag_mask, eps, min_pts, count, label, cluster, n_clusters, ws, s);
 }
 
 int pgsag_group_views(const pgsag_vote_view *host_views, const pgsag_vote_view *dev_views, int32_t n_views,

@@ -85,6 +85,33 @@ def dbscan(points, eps, min_pts, flags=None, flag_mask=2, workspace=None, stream
     return out
 
 
+DBSCAN_STATIC_MAX_POINTS = 1 << 19
+
+
+def dbscan_static(points, eps, min_pts, flags=None, flag_mask=2, out=None, stream=None):
+    """dbscan() on the library's static scratch (pgsag_dbscan_static): no
+    workspace, and with ``out`` (a dict as dbscan returns) nothing allocated.
+    At most DBSCAN_STATIC_MAX_POINTS points; calls overlapping on one GPU
+    race."""
+    if points.dtype != torch.float32 or not points.is_cuda or points.dim() != 2 or points.shape[0] != 3:
+        raise ValueError("points must be a float32 device tensor [3][M]")
+    if not points.is_contiguous():
+        raise ValueError("points must be contiguous")
+    m = points.shape[1]
+    if flags is not None and (flags.dtype != torch.uint8 or flags.numel() != m or not flags.is_cuda):
+        raise ValueError("flags must be a uint8 device tensor [M]")
+    if out is None:
+        dev = points.device
+        out = dict(count=torch.empty(m, dtype=torch.int32, device=dev),
+                   label=torch.empty(m, dtype=torch.int32, device=dev),
+                   cluster=torch.empty(m, dtype=torch.int32, device=dev),
+                   n_clusters=torch.empty(1, dtype=torch.int32, device=dev))
+    A.check(A.lib().pgsag_dbscan_static(_p(points), m, _p(flags), int(flag_mask), float(eps), int(min_pts),
+                                        _p(out["count"]), _p(out["label"]), _p(out["cluster"]),
+                                        _p(out["n_clusters"]), _stream(stream)), "pgsag_dbscan_static")
+    return out
+
+
 def group_views(points, cluster, max_clusters, cameras, masks, min_hits, z_near=0.2, views=None, stream=None):
     """hits [max_clusters][V] uint32 (as int32 storage) and assigned uint8."""
     points = points.contiguous()

@@ -177,6 +177,29 @@ def test_vote_validates_on_the_host_without_touching_memory():
     assert L.pgsag_vote(views, p, 2, None, 0, 0.2, 2, None, None, None, None) == A.OK
 
 
+def test_static_scratch_dbscan_validates_on_the_host_before_any_device_call():
+    """pgsag_dbscan_static rejects sizes beyond its scratch (and bad
+    arguments) before it looks up the scratch or launches anything."""
+    L = A.lib()
+    p = C.c_void_p(0x1000)
+    mx = 1 << 19
+    hdr = open(HEADER).read()
+    assert re.search(r"#define PGSAG_DBSCAN_STATIC_MAX_POINTS \(1 << 19\)", hdr)
+    bad = [
+        (p, mx + 1, None, 2, 3.0, 10, p, p, p, p, None),   # beyond the scratch
+        (p, -1, None, 2, 3.0, 10, p, p, p, p, None),       # n < 0
+        (p, 10, None, 2, 0.0, 10, p, p, p, p, None),       # eps <= 0
+        (p, 10, None, 2, 3.0, 0, p, p, p, p, None),        # min_pts < 1
+        (p, 10, None, 2, 3.0, 10, p, None, p, None, None),  # no n_clusters
+        (None, 10, None, 2, 3.0, 10, p, p, p, p, None),    # no points
+        (p, 10, None, 2, 3.0, 10, p, None, p, p, None),    # no labels
+    ]
+    for args in bad:
+        assert L.pgsag_dbscan_static(*args) == A.INVALID_ARGUMENT, args
+    L.pgsag_dbscan_static(p, mx + 1, None, 2, 3.0, 10, p, p, p, p, None)
+    assert b"0..524288" in L.pgsag_last_error()
+
+
 def test_autotune_shape_key_buckets():
     import torch
     from paper_2501_01677_amd.autotune import shape_key
