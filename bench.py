@@ -194,6 +194,69 @@ def algorithmic_bytes(stage, batch, scene):
     return float("nan")
 
 
+def stage_bytes(batch, scene):
+    """Algorithmic HBM bytes per launch of each HBM-bound stage: what the
+    method itself must read and write (the sort at its floor of one read and
+    one write per key), not what the kernels move."""
+    st = batch.status()
+    n = sum(s.n for s in scene.sets)
+    nbytes_p = sum(s.n * 4 * (3 + 3 + 4 + 1 + 3 * (s.sh_degree + 1) ** 2) for s in scene.sets)
+    nrec = int(batch.info.n_records)
+    nvis = int(st.n_visible)
+    K = int(st.pairs_needed)
+    tiles = int(batch.info.n_tiles)
+    px = int(batch.info.n_pixels)
+    return {
+        # mask read; per-tile counts and active-tile row prefixes written
+        "tile_mask": px + 8 * tiles,
+        # raw parameters read; 52-byte record and 12 bytes of binning info
+        # (depth key, tile rect) written per (render, Gaussian)
+        "preprocess": nbytes_p + nrec * (52 + 12),
+        # counts and keys read; visible (key, record) pairs compacted, then
+        # sorted (one read and one write of 8 bytes each)
+        "depth_sort": nrec * 8 + nvis * (8 + 16),
+        # counts scanned (read, offsets written), rect/count/offset read per
+        # visible record; 8 bytes written per (tile, record) pair
+        "emit": nvis * (4 + 4 + 16) + K * 8,
+        # pairs sorted by tile (one read and one write of 8 bytes), ranges
+        # (tile ids read, [start, end) written)
+        "tile_sort": K * (16 + 4) + tiles * 8,
+        # raw parameters read, 52-byte 2D-gradient slot read, gradients written
+        "backward_preprocess": 2 * nbytes_p + nrec * 52,
+    }
+
+
+def hbm_kernels(stage, batch, scene):
+    """Per HBM-bound stage: algorithmic bytes, achieved GB/s over its event
+    time, fraction of the 8 TB/s peak."""
+    out = {}
+    for k, b in stage_bytes(batch, scene).items():
+        if k not in stage or stage[k] <= 0:
+            continue
+        gbs = b / (stage[k] * 1e-3) / 1e9
+        out[k] = {"bytes": int(b), "ms": round(stage[k], 4), "gb_s": round(gbs, 1),
+                  "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def step_roofline(stage, batch, scene, step_ms):
+    """Whole-step roofline fraction: sum over stages of max(bytes / HBM
+    peak, FP32 operations / FP32 peak), divided by the measured step time.
+    The compositing stages count the method's operations per blended pair;
+    the HBM-bound stages their algorithmic bytes."""
+    blends = float(sum(int(o["n_contrib"].sum().item()) for o in batch.out))
+    bound = {k: b / (HBM_PEAK_GBS * 1e9) for k, b in stage_bytes(batch, scene).items()}
+    flops = {"composite": FLOPS_PER_BLEND_FWD * blends, "backward_composite": FLOPS_PER_BLEND_BWD * blends}
+    t_pub = sum(bound.values()) + sum(f / (FP32_VECTOR_PEAK_TFLOPS * 1e12) for f in flops.values())
+    t_single = sum(bound.values()) + sum(f / (FP32_SINGLE_ISSUE_TFLOPS * 1e12) for f in flops.values())
+    t = step_ms * 1e-3
+    return {"frac": round(t_pub / t, 4), "frac_single_issue": round(t_single / t, 4),
+            "floor_ms": round(t_pub * 1e3, 4), "floor_ms_single_issue": round(t_single * 1e3, 4),
+            "hbm_floor_ms": round(sum(bound.values()) * 1e3, 4),
+            "note": "sum over stages of max(algorithmic bytes / 8 TB/s, method FP32 operations / peak) "
+                    "over the measured step; peaks 157.3 TFLOP/s published and 78.6 single-issue"}
+
+
 def tile_lists(batch, torch):
     """Per-tile list lengths over tiles holding masked pixels: the workload
     each compositing workgroup walks, whose spread is the thread-waiting
@@ -400,12 +463,23 @@ def batched_speedup(torch, steps=5, scale=1.0):
             b.backward()
     torch.cuda.synchronize()
     t_loop = (time.perf_counter() - t0) / steps
+
+    # the same loop captured once into a graph: batching measured apart
+    # from graph capture
+    def loop_step():
+        for b in loops:
+            b.forward(check_overflow=False)
+            b.backward()
+
+    t_loop_graph = _replay_time(loop_step, torch, steps)
+    if any(b.status().overflow for b in loops):
+        raise RuntimeError("overflow in the captured loop")
     for b in loops:
         del b.workspace
     del loops
     torch.cuda.empty_cache()
     out = dict(workload="16 sub-regions x 4 views, 1600x1200, %d Gaussians" % sum(s.n for s in sc.sets),
-               loop_ms=round(t_loop * 1e3, 3))
+               loop_ms=round(t_loop * 1e3, 3), loop_graph_ms=round(t_loop_graph * 1e3, 3))
     out["autotune_ms"] = {k: round(v * 1e3, 3) for k, v in times.items()}
     bb = build_batch(sc, cfg, torch)
     fill_gouts(bb, sc, 4000, torch)
@@ -416,11 +490,107 @@ def batched_speedup(torch, steps=5, scale=1.0):
     out["graph_config"] = {"tile": cfg.tile, "persistent": cfg.persistent, "queue_chunk": cfg.queue_chunk,
                            "workgroups_per_cu": cfg.workgroups_per_cu, "bwd_reduce": cfg.bwd_reduce}
     out["graph_stages_ms"] = {k: round(v, 3) for k, v in stage.items()}
+    out["tile_lists"] = tile_lists(bb, torch)
+    out["hbm_kernels"] = hbm_kernels(stage, bb, sc)
+    out["step_roofline"] = step_roofline(stage, bb, sc, best * 1e3)
     del bb.workspace
     del bb
     torch.cuda.empty_cache()
     out["speedup"] = round(t_loop / best, 3)
+    out["speedup_vs_loop_graph"] = round(t_loop_graph / best, 3)
     out["batched_mpix_s"] = round(masked / best / 1e6, 1)
+    return out
+
+
+def _event_ms(fn, torch, reps=3):
+    """Mean time (ms) of fn() on torch's current stream over reps runs after
+    one warm-up run (HIP events around the calls)."""
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def survey_bench(torch):
+    """The steps around the rasterizer on their full stand-in workloads: the
+    voting filter (2M sparse points x 64 views at 5472x3648), DBSCAN over
+    its reliable points and the views of every group, and the mean fusion
+    and TSDF integration of an 8-view 1600x1200 depth stack (3 building
+    groups and the background block per view) into a 0.5 m volume."""
+    from scenes import survey as sv
+    from paper_2501_01677_amd import survey as gs
+    out = {}
+    s = sv.vote_full()
+    pts = torch.from_numpy(s.points).cuda()
+    masks = [torch.from_numpy(np.ascontiguousarray(m)).cuda() for m in s.masks]
+    views = gs.pack_views(s.cameras, masks)
+    M, V = pts.shape[1], len(masks)
+    res = {}
+
+    def vote():
+        res["v"] = gs.vote(pts, s.cameras, masks, 3, views=views)
+
+    t = _event_ms(vote, torch)
+    votes, us, flags = res["v"]
+    sightings = int(votes.to(torch.int64).sum() + us.to(torch.int64).sum())
+    nbytes = 17 * M + sightings   # points read, votes/US/flags written, one mask byte per sighting
+    out["vote"] = {"workload": f"{M} points x {V} views at {s.cameras[0].width}x{s.cameras[0].height}",
+                   "ms": round(t, 4), "point_views_per_s": round(M * V / (t * 1e-3), 1),
+                   "sightings": sightings, "bytes": nbytes,
+                   "gb_s": round(nbytes / (t * 1e-3) / 1e9, 1),
+                   "frac": round(nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "note": "bound by the mask gathers (a 64-byte line per sighting), not by the algorithmic bytes"}
+    ws = {}
+
+    def dbscan():
+        ws["r"] = gs.dbscan(pts, 3.0, 10, flags=flags, workspace=ws.get("w"))
+        ws["w"] = ws["r"]["workspace"]
+
+    t = _event_ms(dbscan, torch)
+    k = int(ws["r"]["n_clusters"][0])
+    part = int(((flags & 2) != 0).sum())
+    out["dbscan"] = {"workload": f"{part} reliable points of {M}, eps 3 m, min 10", "ms": round(t, 4),
+                     "clusters": k, "points_per_s": round(part / (t * 1e-3), 1)}
+    cl = ws["r"]["cluster"]
+    t = _event_ms(lambda: gs.group_views(pts, cl, k, s.cameras, masks, 200, views=views), torch)
+    out["group_views"] = {"workload": f"{k} groups x {V} views", "ms": round(t, 4)}
+    del pts, masks, views, res, ws, cl, votes, us, flags
+    torch.cuda.empty_cache()
+
+    ds = sv.depth_full()
+    maps = [[torch.from_numpy(np.ascontiguousarray(d)).cuda() for d in per] for per in ds.depths]
+    fused = [torch.empty_like(m[0]) for m in maps]
+
+    def fuse():
+        for j, m in enumerate(maps):
+            gs.fuse_depth(m, out=fused[j], count=False)
+
+    t = _event_ms(fuse, torch)
+    H, W = maps[0][0].shape
+    K = len(maps[0])
+    nbytes = len(maps) * H * W * (4 * K + 4)
+    out["fuse"] = {"workload": f"{len(maps)} views x {K} maps at {W}x{H}", "ms": round(t, 4), "bytes": nbytes,
+                   "gb_s": round(nbytes / (t * 1e-3) / 1e9, 1),
+                   "frac": round(nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    vol = ds.volume
+    tv = {}
+    hv = gs.pack_depth_views(ds.cameras, fused)
+
+    def tsdf():
+        tv["r"] = gs.tsdf_integrate(vol, ds.cameras, fused, tsdf=tv.get("t"), weight=tv.get("w"), views=hv)
+        tv["t"], tv["w"] = tv["r"]
+
+    t = _event_ms(tsdf, torch)
+    nvox = int(np.prod(vol["dims"]))
+    out["tsdf"] = {"workload": f"{vol['dims'][0]}x{vol['dims'][1]}x{vol['dims'][2]} voxels x {len(fused)} views",
+                   "ms": round(t, 4), "voxel_views_per_s": round(nvox * len(fused) / (t * 1e-3), 1),
+                   "bytes": 8 * nvox, "gb_s": round(8 * nvox / (t * 1e-3) / 1e9, 1),
+                   "note": "bound by the per-(voxel, view) projection with correctly rounded divisions"}
     return out
 
 
@@ -434,6 +604,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-scale", type=float, default=1.0)
     ap.add_argument("--no-train", action="store_true", help="skip the 10M-Gaussian training step")
+    ap.add_argument("--no-survey", action="store_true", help="skip the voting / grouping / fusion steps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -460,6 +631,8 @@ def main():
     summary = stage.pop("_summary", None)
     lists = tile_lists(batch, torch)
     dom, roof = roofline(stage, batch, sc, torch, args.tile)
+    hbm = hbm_kernels(stage, batch, sc)
+    step_roof = step_roofline(stage, batch, sc, ms_wall)
     log("[bench] forward+loss+backward")
     ms_loss, _ = with_loss_time(batch, gt, torch, args.steps)
     if args.copy_calibration:
@@ -494,6 +667,8 @@ def main():
                       "note": "same step with the loss kernels in the graph (ground truth: the render of the "
                               "generating scene)"},
         "roofline": roof,
+        "hbm_kernels": hbm,
+        "step_roofline": step_roof,
     }
     del batch
     torch.cuda.empty_cache()
@@ -509,6 +684,12 @@ def main():
             line["train_step"] = train_step_bench(torch, max(3, args.steps // 4))
         except Exception as e:  # report, do not hide the headline
             line["train_step"] = {"error": repr(e)}
+    if not args.no_survey:
+        log("[bench] voting filter, grouping, depth fusion and TSDF")
+        try:
+            line["survey"] = survey_bench(torch)
+        except Exception as e:  # report, do not hide the headline
+            line["survey"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(sc)

@@ -69,7 +69,7 @@
 extern "C" {
 #endif
 
-#define PGSAG_ABI_VERSION 2
+#define PGSAG_ABI_VERSION 3
 #define PGSAG_NUM_STAGES 8
 
 typedef enum pgsag_status_code {
@@ -123,9 +123,13 @@ typedef struct pgsag_outputs {
 } pgsag_outputs;
 
 /* Device dL/d(output) planes, same layouts as pgsag_outputs; NULL = zero.
- * Values at unmasked pixels are ignored. */
+ * Values at unmasked pixels are ignored.  count: dL/ds [H][W] for the soft
+ * contributor count s = sum of alpha over the fragments blended at the
+ * pixel -- the differentiable stand-in for the integer count g_i of Eq. 9
+ * (Sec. 4.3), through which the balance-load term's gradient flows; s
+ * itself is not an output. */
 typedef struct pgsag_grad_outputs {
-  const float *rgb, *normal, *dist, *depth, *alpha;
+  const float *rgb, *normal, *dist, *depth, *alpha, *count;
 } pgsag_grad_outputs;
 
 typedef struct pgsag_render {
@@ -340,7 +344,13 @@ typedef struct pgsag_loss_config {
   float lambda_load;     /* lambda of Eq. 11 (balance-load share): 0 */
   int32_t normal_norm;   /* 1 = L1 (default), 2 = squared L2 (Eq. 8 as printed) */
   float normal_eps;      /* rendered normals with |N| <= eps take no part: 1e-6 */
-  int32_t reserved[2];
+  int32_t load_term;     /* the balance-load term L_load of Eq. 11:
+                            0 (default): variance of the pair counts over tiles
+                              holding masked pixels, a value only;
+                            1: the GC-load of Eq. 9, std over masked pixels of
+                              n_contrib / w, with its gradient taken through the
+                              soft count (see pgsag_grad_outputs.count) */
+  int32_t reserved;
 } pgsag_loss_config;
 
 void pgsag_default_loss_config(pgsag_loss_config *lc);
@@ -358,18 +368,28 @@ void pgsag_default_loss_config(pgsag_loss_config *lc);
  *           the pixel itself; it exists where the pixel has a neighbour
  *           along each axis; N is used where |N| > normal_eps
  *   L     = (1 - lambda_load)(lambda_rgb L_rgb + lambda_normal L_ban)
- *           + lambda_load * Var(pair counts over tiles holding masked
- *           pixels)   (that term is a value only: zero gradient)
- * Reads each render's rgb, normal and depth outputs (required) and
- * gt_rgb[r] (host array of n_renders device pointers to [3][H][W]).
- * Writes dL/d(rgb, normal, depth) into the render's grad-output planes
- * (required; the descriptor's const pointers are written here) and 0 into
- * its dist and alpha grad-output planes if present, at masked pixels only:
- * other pixels are left as they are (the backward ignores them).
- * loss: device float [n_renders][4] = {L, L_rgb, L_ban, Var}.  Needs the
- * workspace of the preceding pgsag_forward.  Capturable. */
+ *           + lambda_load * L_load
+ *   L_load = (load_term 0) Var(pair counts over tiles holding masked
+ *           pixels), a value only: zero gradient;
+ *           (load_term 1) the GC-load of Eq. 9: sigma = population std over
+ *           masked pixels of x = n_contrib / w, w = pixel_weight[r] (NULL
+ *           array or entry = 1; e.g. pgsag_luminance_weights).  Its gradient
+ *           is taken through the soft count s (straight through the integer
+ *           count): dL/ds = lambda_load (x - mean x) / (M sigma w), 0 when
+ *           sigma = 0.
+ * Reads each render's rgb, normal and depth outputs (required; n_contrib
+ * too with load_term 1) and gt_rgb[r] (host array of n_renders device
+ * pointers to [3][H][W]).  Writes dL/d(rgb, normal, depth) into the
+ * render's grad-output planes (required; the descriptor's const pointers
+ * are written here), 0 into its dist and alpha grad-output planes if
+ * present, and dL/ds into its count plane (required with load_term 1;
+ * written 0 with load_term 0 if present), at masked pixels only: other
+ * pixels are left as they are (the backward ignores them).  loss: device
+ * float [n_renders][4] = {L, L_rgb, L_ban, L_load}.  Needs the workspace of
+ * the preceding pgsag_forward.  Capturable. */
 int pgsag_loss(const pgsag_loss_config *lc, const void *host_desc, const void *dev_desc, void *workspace,
-               uint64_t workspace_bytes, const float *const *gt_rgb, float *loss, void *stream);
+               uint64_t workspace_bytes, const float *const *gt_rgb, const float *const *pixel_weight, float *loss,
+               void *stream);
 
 /* Per-pixel weights w_i of the gradient-constrained balance-load term
  * (Sec. 4.3 Eq. 9), a reading of its "gradient-dependent weight":
@@ -378,7 +398,7 @@ int pgsag_loss(const pgsag_loss_config *lc, const void *host_desc, const void *d
  * `render`), gradients by central differences inside the image and
  * one-sided differences on its border; w = 1 everywhere when that mean is
  * 0.  weight: device float [H][W], every pixel written.  Feed it to
- * pgsag_load_stats as pixel_weight.  Uses the workspace's loss
+ * pgsag_load_stats and pgsag_loss as pixel_weight.  Uses the workspace's loss
  * accumulators of that render. */
 int pgsag_luminance_weights(const void *host_desc, const void *dev_desc, void *workspace, uint64_t workspace_bytes,
                             int32_t render, const float *gt_rgb, float *weight, void *stream);

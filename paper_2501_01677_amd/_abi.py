@@ -9,7 +9,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpgsag.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 NUM_STAGES = 8
 STAGES = ("tile_mask", "preprocess", "depth_sort", "emit", "tile_sort", "composite",
           "backward_composite", "backward_preprocess")
@@ -40,7 +40,7 @@ class Outputs(C.Structure):
 
 class GradOutputs(C.Structure):
     _fields_ = [("rgb", C.c_void_p), ("normal", C.c_void_p), ("dist", C.c_void_p),
-                ("depth", C.c_void_p), ("alpha", C.c_void_p)]
+                ("depth", C.c_void_p), ("alpha", C.c_void_p), ("count", C.c_void_p)]
 
 
 class Render(C.Structure):
@@ -72,7 +72,7 @@ class Layout(C.Structure):
 class LossConfig(C.Structure):
     _fields_ = [("lambda_rgb", C.c_float), ("lambda_normal", C.c_float), ("boundary_weight", C.c_float),
                 ("lambda_load", C.c_float), ("normal_norm", C.c_int32), ("normal_eps", C.c_float),
-                ("reserved", C.c_int32 * 2)]
+                ("load_term", C.c_int32), ("reserved", C.c_int32)]
 
 
 class AdamConfig(C.Structure):
@@ -138,7 +138,7 @@ def lib():
     L.pgsag_load_stats.argtypes = [vp, vp, vp, C.POINTER(vp), vp, vp]
     L.pgsag_default_loss_config.argtypes = [C.POINTER(LossConfig)]
     L.pgsag_default_loss_config.restype = None
-    L.pgsag_loss.argtypes = [C.POINTER(LossConfig), vp, vp, vp, u64, C.POINTER(vp), vp, vp]
+    L.pgsag_loss.argtypes = [C.POINTER(LossConfig), vp, vp, vp, u64, C.POINTER(vp), C.POINTER(vp), vp, vp]
     L.pgsag_luminance_weights.argtypes = [vp, vp, vp, u64, i32, vp, vp, vp]
     L.pgsag_vote.argtypes = [C.POINTER(VoteView), vp, i32, vp, i64, f32, i32, vp, vp, vp, vp]
     L.pgsag_dbscan_workspace.argtypes = [i64, C.POINTER(C.c_uint64)]

@@ -169,7 +169,7 @@ Layout make_layout(const pgsag_config &cfg, const Sizes &z, uint64_t cap, int n_
   L.status = status_at;
   L.stats = take((uint64_t)n_renders * 8 * 8);
   L.loss = take((uint64_t)n_renders * 8 * 8);
-  L.loss_part = take((uint64_t)n_renders * 64 * 2 * 8);
+  L.loss_part = take((uint64_t)n_renders * 64 * 4 * 8);
   L.end = off;
   return L;
 }
@@ -403,6 +403,7 @@ int pgsag_pack(const pgsag_config *cfg, const pgsag_gaussians *sets, const pgsag
     o.g_dist = in.gout.dist;
     o.g_depth = in.gout.depth;
     o.g_alpha = in.gout.alpha;
+    o.g_count = in.gout.count;
     o.record_offset = recoff;
     o.pixel_offset = pixoff;
     o.tile_offset = (uint32_t)toff;
@@ -623,7 +624,8 @@ void pgsag_default_loss_config(pgsag_loss_config *lc) {
 }
 
 int pgsag_loss(const pgsag_loss_config *lc, const void *host_desc, const void *dev_desc, void *workspace,
-               uint64_t workspace_bytes, const float *const *gt_rgb, float *loss, void *stream) {
+               uint64_t workspace_bytes, const float *const *gt_rgb, const float *const *pixel_weight, float *loss,
+               void *stream) {
   const Header *h = check_desc(host_desc);
   if (!h) return PGSAG_INVALID_ARGUMENT;
   if (!lc || !dev_desc || !workspace || !gt_rgb || !loss)
@@ -632,6 +634,7 @@ int pgsag_loss(const pgsag_loss_config *lc, const void *host_desc, const void *d
   if (lc->normal_norm != 1 && lc->normal_norm != 2) return fail(PGSAG_INVALID_ARGUMENT, "normal_norm must be 1 or 2");
   if (!(lc->lambda_load >= 0.f && lc->lambda_load <= 1.f)) return fail(PGSAG_INVALID_ARGUMENT, "lambda_load must be in [0, 1]");
   if (!(lc->normal_eps >= 0.f)) return fail(PGSAG_INVALID_ARGUMENT, "normal_eps must be >= 0");
+  if (lc->load_term != 0 && lc->load_term != 1) return fail(PGSAG_INVALID_ARGUMENT, "load_term must be 0 or 1");
   const DevRender *rd = renders_of(host_desc);
   for (int r = 0; r < h->n_renders; ++r) {
     if (!rd[r].o_rgb || !rd[r].o_normal || !rd[r].o_depth)
@@ -639,8 +642,11 @@ int pgsag_loss(const pgsag_loss_config *lc, const void *host_desc, const void *d
     if (!rd[r].g_rgb || !rd[r].g_normal || !rd[r].g_depth)
       return fail(PGSAG_INVALID_ARGUMENT, "render %d: rgb, normal and depth grad-output planes are required", r);
     if (!gt_rgb[r]) return fail(PGSAG_INVALID_ARGUMENT, "render %d: null ground truth", r);
+    if (lc->load_term == 1 && (!rd[r].o_ncontrib || !rd[r].g_count))
+      return fail(PGSAG_INVALID_ARGUMENT, "render %d: the GC-load term needs the n_contrib output and the count "
+                  "grad-output plane", r);
   }
-  launch_loss(dev_desc, host_desc, workspace, *lc, gt_rgb, loss, static_cast<hipStream_t>(stream));
+  launch_loss(dev_desc, host_desc, workspace, *lc, gt_rgb, pixel_weight, loss, static_cast<hipStream_t>(stream));
   return check_hip("loss");
 }
 

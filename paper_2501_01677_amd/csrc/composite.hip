@@ -472,6 +472,9 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
   float Tr = 1.f, Tf = 1.f;
   float gch[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float ga = 0.f;
+  // dL/d(soft count): every blended fragment's alpha enters the pixel's
+  // soft count with weight 1 (the count output's gradient)
+  float gcount = 0.f;
   // GS = sum_c g_c S_c, S_c the blended features behind the current fragment
   // (plus the background term): dL/dalpha only needs this dot product, so it
   // is kept instead of the seven suffix sums.
@@ -492,6 +495,7 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
     }
     if (rd.g_dist) gch[6] = rd.g_dist[pix];
     if (rd.g_alpha) ga = rd.g_alpha[pix];
+    if (rd.g_count) gcount = rd.g_count[pix];
     if (rd.g_depth) {
       // depth = D / (N . r): fold its gradient into D and N
       const float gd = rd.g_depth[pix];
@@ -576,6 +580,7 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
           const float Tp = Tr * iom;
           const float w = contrib ? a * Tp : 0.f;
           // dL/dalpha = sum_c g_c (T f_c - S_c / (1 - alpha)) + g_alpha T_final / (1 - alpha)
+          //            + g_count
           float Gf = 0.f;
           float v[16];
 #pragma unroll
@@ -583,7 +588,7 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
             Gf = fmaf(gch[c], f[c], Gf);
             v[6 + c] = w * gch[c];
           }
-          const float dLda = Tp * Gf + (ga * Tf - GS) * iom;
+          const float dLda = Tp * Gf + (ga * Tf - GS) * iom + gcount;
           GS = contrib ? fmaf(w, Gf, GS) : GS;
           Tr = contrib ? Tp : Tr;
           // alpha = o G with G = exp(-q/2): dalpha/do = G = alpha / o,
@@ -630,10 +635,11 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
             const float Tp = Tr * iom;
             const float w = contrib ? a * Tp : 0.f;
             // dL/dalpha = sum_c g_c (T f_c - S_c / (1 - alpha)) + g_alpha T_final / (1 - alpha)
+            //            + g_count
             float Gf = 0.f;
 #pragma unroll
             for (int c = 0; c < 7; ++c) Gf = fmaf(gch[c], f[c], Gf);
-            const float dLda = Tp * Gf + (ga * Tf - GS) * iom;
+            const float dLda = Tp * Gf + (ga * Tf - GS) * iom + gcount;
             GS = contrib ? fmaf(w, Gf, GS) : GS;
             Tr = contrib ? Tp : Tr;
             // alpha = o G with G = exp(-q/2): dalpha/do = G = alpha / o,

@@ -70,7 +70,7 @@ struct DevRender {
   const uint8_t *mask;
   float *o_rgb, *o_normal, *o_dist, *o_depth, *o_alpha;
   int32_t *o_ncontrib;
-  const float *g_rgb, *g_normal, *g_dist, *g_depth, *g_alpha;
+  const float *g_rgb, *g_normal, *g_dist, *g_depth, *g_alpha, *g_count;
   uint64_t record_offset;  // first record of this render
   uint64_t pixel_offset;   // first per-pixel state slot
   uint32_t tile_offset;    // first global tile id
@@ -104,7 +104,7 @@ struct Layout {
   uint64_t qkey[2], qval0;       // queue sort buffers (the result lands in `queue`)
   uint64_t stats;
   uint64_t loss;       // double [n_renders][8] loss accumulators
-  uint64_t loss_part;  // double [n_renders][64][2] partial sums of the loss terms
+  uint64_t loss_part;  // double [n_renders][64][4] partial sums of the loss terms
   uint64_t end;
 };
 
@@ -221,7 +221,7 @@ void launch_adam_coef(int32_t *state, float b1, float b2, hipStream_t s);
 void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
                  int32_t step, int32_t *state, hipStream_t s);
 void launch_loss(const void *d_desc, const void *h_desc, void *ws, const pgsag_loss_config &lc,
-                 const float *const *gt, float *out, hipStream_t s);
+                 const float *const *gt, const float *const *weight, float *out, hipStream_t s);
 void launch_luminance_weights(const void *d_desc, const void *h_desc, void *ws, int r, const float *gt,
                               float *weight, hipStream_t s);
 void launch_load_stats(const void *d_desc, const Header &h, const void *ws, int r,

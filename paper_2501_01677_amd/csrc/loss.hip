@@ -9,7 +9,11 @@
 //           w * || n_depth - N / |N| ||  (L1, or squared L2),
 //           w = boundary weight on the mask boundary, 1 elsewhere
 //   L     = (1 - lambda_load) (lambda_rgb L_rgb + lambda_normal L_ban)
-//           + lambda_load Var(pairs per active tile)   (value only)
+//           + lambda_load L_load
+//   L_load: load_term 0: Var(pairs per active tile)   (value only)
+//           load_term 1: GC-load of Eq. 9, std over masked pixels of
+//           x = n_contrib / w; its gradient goes to the soft count (the sum
+//           of the blended alphas): dL/ds = lambda_load (x - mean) / (M std w)
 // n_depth: pixels inside the mask with a positive depth are back-projected,
 // P = depth K^-1 p~; dPx = P(u+1) - P(u-1) and dPy = P(v+1) - P(v-1), a
 // neighbour that is not such a pixel being replaced by the pixel itself;
@@ -25,6 +29,7 @@
 //                of the 18 x 18 ring, then every pixel gathers the depth
 //                gradient from the up-to-five normals its point enters
 //   loss_final   per render: sum of the block partials, the four loss values
+//   gc_grad      per render, GC-load only: dL/d(soft count) at masked pixels
 // plus the luminance weights of Eq. 9 (weights_grad, weights_final).
 #include "internal.h"
 
@@ -40,8 +45,9 @@ constexpr int kSlots = 64;              // partial-sum slots per render (blocks 
 
 struct LossParams {
   float lambda_rgb, lambda_normal, boundary_weight, lambda_load, eps;
-  int norm;
+  int norm, load_term;
 };
+constexpr int kPart = 4;  // doubles per partial-sum slot: |rgb - gt|, w e, sum x, sum x^2
 
 __device__ __forceinline__ double wave_sum_d(double x) {
 #pragma unroll
@@ -105,14 +111,15 @@ __device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f
 // render's 64 partial-sum slots (block index mod 64: no address sees more
 // than 1/64 of the blocks).  One block per 16 x 16 pixels.
 __global__ void __launch_bounds__(256) loss_pixels_kernel(const void *__restrict__ desc, void *__restrict__ ws, int r,
-                                                          const float *__restrict__ gt, LossParams lp) {
+                                                          const float *__restrict__ gt,
+                                                          const float *__restrict__ weight, LossParams lp) {
   const Header &h = *header(desc);
   const DevRender &rd = renders_of(desc)[r];
   const int W = rd.cam.W, H = rd.cam.H;
   const int bpr = (W + kLB - 1) / kLB;
   const int x0 = (blockIdx.x % bpr) * kLB, y0 = (blockIdx.x / bpr) * kLB;
   const double *acc = ws_ptr<double>(ws, h.ws.loss) + kAcc * r;
-  double *part = ws_ptr<double>(ws, h.ws.loss_part) + 2 * ((uint64_t)r * kSlots + blockIdx.x % kSlots);
+  double *part = ws_ptr<double>(ws, h.ws.loss_part) + kPart * ((uint64_t)r * kSlots + blockIdx.x % kSlots);
   const uint64_t plane = (uint64_t)W * H;
 
   __shared__ float sP[3][kSX * kSX];
@@ -265,8 +272,9 @@ __global__ void __launch_bounds__(256) loss_pixels_kernel(const void *__restrict
   }
   __syncthreads();
 
-  // one pixel per thread: colour term, depth gradient
+  // one pixel per thread: colour term, depth gradient, GC-load moments
   float r_sum = 0.f;
+  double x_sum = 0.0, x_sq = 0.0;
   {
     const int iu = threadIdx.x % kLB, iv = threadIdx.x / kLB;
     const int u = x0 + iu, v = y0 + iv;
@@ -302,38 +310,86 @@ __global__ void __launch_bounds__(256) loss_pixels_kernel(const void *__restrict
       const_cast<float *>(rd.g_depth)[p] = gd;
       if (rd.g_dist) const_cast<float *>(rd.g_dist)[p] = 0.f;
       if (rd.g_alpha) const_cast<float *>(rd.g_alpha)[p] = 0.f;
+      if (lp.load_term == 1) {
+        const float x = (float)rd.o_ncontrib[p] / (weight ? weight[p] : 1.f);
+        x_sum = (double)x;
+        x_sq = (double)x * (double)x;
+      } else if (rd.g_count) {
+        const_cast<float *>(rd.g_count)[p] = 0.f;  // the tile-variance term has no gradient
+      }
     }
   }
   const double a = block_sum_d((double)r_sum);
   const double b = block_sum_d((double)e_sum);
+  double c = 0.0, d = 0.0;
+  if (lp.load_term == 1) {
+    c = block_sum_d(x_sum);
+    d = block_sum_d(x_sq);
+  }
   if (threadIdx.x == 0) {
     atomicAdd(&part[0], a);
     atomicAdd(&part[1], b);
+    if (lp.load_term == 1) {
+      atomicAdd(&part[2], c);
+      atomicAdd(&part[3], d);
+    }
   }
 }
 
 // One wave per render: sum the render's partial-sum slots, then the four
-// loss values.
-__global__ void __launch_bounds__(64) loss_final_kernel(const void *__restrict__ desc, const void *__restrict__ ws,
+// loss values; for the GC-load term also the mean of x and the factor
+// lambda_load / (M std) of its gradient (acc[4], acc[5]).
+__global__ void __launch_bounds__(64) loss_final_kernel(const void *__restrict__ desc, void *__restrict__ ws,
                                                         LossParams lp, float *__restrict__ out) {
   const Header &h = *header(desc);
   const int r = blockIdx.x;
-  const double *part = ws_ptr<const double>(const_cast<void *>(ws), h.ws.loss_part) + 2 * (uint64_t)r * kSlots;
-  const double s_rgb = wave_sum_d(part[2 * threadIdx.x]);
-  const double s_n = wave_sum_d(part[2 * threadIdx.x + 1]);
+  const double *part = ws_ptr<const double>(ws, h.ws.loss_part) + kPart * (uint64_t)r * kSlots;
+  const double s_rgb = wave_sum_d(part[kPart * threadIdx.x]);
+  const double s_n = wave_sum_d(part[kPart * threadIdx.x + 1]);
+  const double s_x = wave_sum_d(part[kPart * threadIdx.x + 2]);
+  const double s_xx = wave_sum_d(part[kPart * threadIdx.x + 3]);
   if (threadIdx.x != 0) return;
-  const double *acc = ws_ptr<const double>(const_cast<void *>(ws), h.ws.loss) + kAcc * r;
+  double *acc = ws_ptr<double>(ws, h.ws.loss) + kAcc * r;
   const double M = acc[0] > 0 ? acc[0] : 1.0;
   const double l_rgb = s_rgb / (3.0 * M), l_ban = s_n / M;
-  const double nt = acc[1] > 0 ? acc[1] : 1.0;
-  const double mean = acc[2] / nt;
-  double var = acc[3] / nt - mean * mean;
-  if (var < 0) var = 0;
+  double load;
+  if (lp.load_term == 1) {
+    const double mean = s_x / M;
+    double var = s_xx / M - mean * mean;
+    if (var < 0) var = 0;
+    load = sqrt(var);
+    acc[4] = mean;
+    acc[5] = load > 0 && acc[0] > 0 ? (double)lp.lambda_load / (acc[0] * load) : 0.0;
+  } else {
+    const double nt = acc[1] > 0 ? acc[1] : 1.0;
+    const double mean = acc[2] / nt;
+    double var = acc[3] / nt - mean * mean;
+    if (var < 0) var = 0;
+    load = var;
+  }
   const double geo = (double)lp.lambda_rgb * l_rgb + (double)lp.lambda_normal * l_ban;
-  out[4 * r + 0] = (float)((1.0 - (double)lp.lambda_load) * geo + (double)lp.lambda_load * var);
+  out[4 * r + 0] = (float)((1.0 - (double)lp.lambda_load) * geo + (double)lp.lambda_load * load);
   out[4 * r + 1] = (float)l_rgb;
   out[4 * r + 2] = (float)l_ban;
-  out[4 * r + 3] = (float)var;
+  out[4 * r + 3] = (float)load;
+}
+
+// GC-load gradient at the masked pixels of render r:
+// dL/ds = lambda_load (x - mean) / (M std w), x = n_contrib / w.
+__global__ void __launch_bounds__(256) gc_grad_kernel(const void *__restrict__ desc, const void *__restrict__ ws,
+                                                      int r, const float *__restrict__ weight) {
+  const Header &h = *header(desc);
+  const DevRender &rd = renders_of(desc)[r];
+  const uint64_t plane = (uint64_t)rd.cam.W * rd.cam.H;
+  const double *acc = ws_ptr<const double>(ws, h.ws.loss) + kAcc * r;
+  const float mean = (float)acc[4], k = (float)acc[5];
+  float *gc = const_cast<float *>(rd.g_count);
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < plane; p += (uint64_t)gridDim.x * blockDim.x) {
+    if (rd.mask != nullptr && rd.mask[p] == 0) continue;
+    const float w = weight ? weight[p] : 1.f;
+    const float x = (float)rd.o_ncontrib[p] / w;
+    gc[p] = k * (x - mean) / w;
+  }
 }
 
 // Eq. 9 weights.  Pass 1: |grad Y| per pixel (central differences inside,
@@ -397,6 +453,7 @@ LossParams params_of(const pgsag_loss_config &lc) {
   p.lambda_load = lc.lambda_load;
   p.eps = lc.normal_eps;
   p.norm = lc.normal_norm;
+  p.load_term = lc.load_term;
   return p;
 }
 
@@ -408,13 +465,13 @@ unsigned grid_for(uint64_t n) {
 }  // namespace
 
 void launch_loss(const void *d_desc, const void *h_desc, void *ws, const pgsag_loss_config &lc,
-                 const float *const *gt, float *out, hipStream_t s) {
+                 const float *const *gt, const float *const *weight, float *out, hipStream_t s) {
   const Header &h = *header(h_desc);
   const DevRender *rd = renders_of(h_desc);
   double *acc = ws_ptr<double>(ws, h.ws.loss);
   const int n = h.n_renders * kAcc;
   hipLaunchKernelGGL(fill_f64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, acc, n);
-  const int np = h.n_renders * kSlots * 2;
+  const int np = h.n_renders * kSlots * kPart;
   hipLaunchKernelGGL(fill_f64_kernel, dim3((np + 255) / 256), dim3(256), 0, s, ws_ptr<double>(ws, h.ws.loss_part), np);
   uint64_t max_tiles = 1;
   for (int r = 0; r < h.n_renders; ++r) {
@@ -427,9 +484,17 @@ void launch_loss(const void *d_desc, const void *h_desc, void *ws, const pgsag_l
   const LossParams lp = params_of(lc);
   for (int r = 0; r < h.n_renders; ++r) {
     const unsigned blocks = (unsigned)(((rd[r].cam.W + kLB - 1) / kLB) * ((rd[r].cam.H + kLB - 1) / kLB));
-    if (blocks) hipLaunchKernelGGL(loss_pixels_kernel, dim3(blocks), dim3(256), 0, s, d_desc, ws, r, gt[r], lp);
+    if (blocks)
+      hipLaunchKernelGGL(loss_pixels_kernel, dim3(blocks), dim3(256), 0, s, d_desc, ws, r, gt[r],
+                         weight ? weight[r] : nullptr, lp);
   }
-  hipLaunchKernelGGL(loss_final_kernel, dim3(h.n_renders), dim3(64), 0, s, d_desc, (const void *)ws, lp, out);
+  hipLaunchKernelGGL(loss_final_kernel, dim3(h.n_renders), dim3(64), 0, s, d_desc, ws, lp, out);
+  if (lc.load_term == 1)
+    for (int r = 0; r < h.n_renders; ++r) {
+      const uint64_t plane = (uint64_t)rd[r].cam.W * rd[r].cam.H;
+      hipLaunchKernelGGL(gc_grad_kernel, dim3(grid_for(plane)), dim3(256), 0, s, d_desc, (const void *)ws, r,
+                         weight ? weight[r] : nullptr);
+    }
 }
 
 void launch_luminance_weights(const void *d_desc, const void *h_desc, void *ws, int r, const float *gt,

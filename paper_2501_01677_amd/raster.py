@@ -19,7 +19,12 @@ import torch
 from . import _abi as A
 
 OUTPUTS = (("rgb", 3), ("normal", 3), ("dist", 1), ("depth", 1), ("alpha", 1), ("n_contrib", 1))
-GRAD_OUTPUTS = ("rgb", "normal", "dist", "depth", "alpha")
+# upstream-gradient planes: the outputs' and that of the soft contributor
+# count (the sum of the blended alphas; the GC-load term's gradient)
+GRAD_OUTPUTS = ("rgb", "normal", "dist", "depth", "alpha", "count")
+_CHANNELS = dict(OUTPUTS, count=1)
+# the differentiable outputs of the autograd function
+DIFF_OUTPUTS = ("rgb", "normal", "dist", "depth", "alpha")
 PARAMS = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
 
@@ -63,10 +68,12 @@ class LossConfig:
     lambda_load: float = 0.0
     normal_norm: int = 1
     normal_eps: float = 1e-6
+    load_term: int = 0  # 0: tile-count variance (value only), 1: Eq. 9 GC-load through the soft count
 
     def to_c(self) -> A.LossConfig:
         c = A.LossConfig()
-        for k in ("lambda_rgb", "lambda_normal", "boundary_weight", "lambda_load", "normal_norm", "normal_eps"):
+        for k in ("lambda_rgb", "lambda_normal", "boundary_weight", "lambda_load", "normal_norm", "normal_eps",
+                  "load_term"):
             setattr(c, k, getattr(self, k))
         return c
 
@@ -147,10 +154,9 @@ class Batch:
             self.out.append(o)
             g = {}
             if want_grads:
-                for name, c in OUTPUTS:
-                    if name in grad_outputs:
-                        g[name] = torch.zeros((c, H, W) if c > 1 else (H, W), dtype=torch.float32,
-                                              device=device)
+                for name in grad_outputs:
+                    c = _CHANNELS[name]
+                    g[name] = torch.zeros((c, H, W) if c > 1 else (H, W), dtype=torch.float32, device=device)
             self.gout.append(g)
         self.grads = []
         if want_grads:
@@ -311,19 +317,27 @@ class Batch:
                                           _p(out), _stream(stream)), "pgsag_load_stats")
         return out
 
-    def loss(self, gt, lc: LossConfig | None = None, out=None, stream=None):
+    def loss(self, gt, lc: LossConfig | None = None, out=None, stream=None, weights=None):
         """Loss of the last forward against ground-truth images gt[r]
-        (float32 [3,H,W]); writes dL/d(rgb, normal, depth) into the batch's
-        gradient planes.  Returns device float [n_renders, 4] = (total,
-        L_rgb, L_ban, tile-load variance)."""
+        (float32 [3,H,W]); writes dL/d(rgb, normal, depth) (and, with the
+        GC-load term, dL/d(soft count)) into the batch's gradient planes.
+        ``weights``: per render the Eq. 9 pixel weights (float32 [H,W]) or
+        None (= 1).  Returns device float [n_renders, 4] = (total, L_rgb,
+        L_ban, load term)."""
         lc = lc or LossConfig()
         if out is None:
             out = torch.empty((len(self.renders), 4), dtype=torch.float32, device=self.device)
         for t in gt:
             assert t.dtype == torch.float32 and t.is_contiguous()
         arr = (C.c_void_p * len(self.renders))(*[t.data_ptr() for t in gt])
+        warr = None
+        if weights is not None:
+            for w in weights:
+                assert w is None or (w.dtype == torch.float32 and w.is_contiguous())
+            warr = (C.c_void_p * len(self.renders))(*[None if w is None else w.data_ptr() for w in weights])
         A.check(self.lib.pgsag_loss(C.byref(lc.to_c()), self.host_desc, _p(self.dev_desc), _p(self.workspace),
-                                    int(self.info.workspace_bytes), arr, _p(out), _stream(stream)), "pgsag_loss")
+                                    int(self.info.workspace_bytes), arr, warr, _p(out), _stream(stream)),
+                "pgsag_loss")
         return out
 
     def luminance_weights(self, render, gt, out=None, stream=None):
@@ -370,10 +384,10 @@ class _RasterizeFn(torch.autograd.Function):
         ctx.flat = flat
         outs = []
         for o in batch.out:
-            for name in GRAD_OUTPUTS:
+            for name in DIFF_OUTPUTS:
                 outs.append(o[name].clone())
             outs.append(o["n_contrib"].clone())
-        ctx.mark_non_differentiable(*outs[len(GRAD_OUTPUTS)::len(GRAD_OUTPUTS) + 1])
+        ctx.mark_non_differentiable(*outs[len(DIFF_OUTPUTS)::len(DIFF_OUTPUTS) + 1])
         return tuple(outs)
 
     @staticmethod
@@ -385,13 +399,14 @@ class _RasterizeFn(torch.autograd.Function):
         if [t._version for t in ctx.flat] != ctx.versions:
             raise RuntimeError("a Gaussian parameter tensor was modified in place between "
                                "the forward and the backward")
-        per = len(GRAD_OUTPUTS) + 1
+        per = len(DIFF_OUTPUTS) + 1
         gouts = []
         for i in range(len(batch.renders)):
             g = {}
-            for j, name in enumerate(GRAD_OUTPUTS):
+            for j, name in enumerate(DIFF_OUTPUTS):
                 gi = grads[i * per + j]
                 g[name] = None if gi is None else gi.contiguous()
+            g["count"] = None  # no soft-count gradient through autograd (zeroed)
             gouts.append(g)
         batch.backward(gouts)
         res = [None]
@@ -416,11 +431,11 @@ class MaskedRasterizer:
         for s in self.batch.sets:
             flat += [s[k] for k in PARAMS]
         outs = _RasterizeFn.apply(self.batch, *flat)
-        per = len(GRAD_OUTPUTS) + 1
+        per = len(DIFF_OUTPUTS) + 1
         res = []
         for i in range(len(self.batch.renders)):
-            d = {name: outs[i * per + j] for j, name in enumerate(GRAD_OUTPUTS)}
-            d["n_contrib"] = outs[i * per + len(GRAD_OUTPUTS)]
+            d = {name: outs[i * per + j] for j, name in enumerate(DIFF_OUTPUTS)}
+            d["n_contrib"] = outs[i * per + len(DIFF_OUTPUTS)]
             res.append(d)
         return res
 
@@ -456,7 +471,7 @@ class Trainer:
 
     def __init__(self, sets, renders, gt, cfg: RenderConfig | None = None, lc: LossConfig | None = None,
                  lr=1e-3, betas=(0.9, 0.999), eps=1e-8, pair_capacity=None, device="cuda", fused=True,
-                 keep_grads=False):
+                 keep_grads=False, weights=None):
         total = 0
         for s in sets:
             for _, shp in _param_sizes(int(s["means"].shape[1]), int(s["sh_degree"])):
@@ -487,6 +502,7 @@ class Trainer:
             grads.append(gv)
         self.batch = Batch(self.params, renders, cfg, pair_capacity=pair_capacity, device=device, grads=grads)
         self.gt = list(gt)
+        self.weights = None if weights is None else list(weights)  # Eq. 9 pixel weights per render
         self.lc = lc or LossConfig()
         self.lr, self.betas, self.eps = lr, betas, eps
         self.loss_out = torch.zeros((len(renders), 4), dtype=torch.float32, device=device)
@@ -501,7 +517,7 @@ class Trainer:
     def step(self, stream=None):
         b = self.batch
         b.forward(stream=stream, check_overflow=False)
-        b.loss(self.gt, self.lc, out=self.loss_out, stream=stream)
+        b.loss(self.gt, self.lc, out=self.loss_out, stream=stream, weights=self.weights)
         if self.fused:
             b.backward_adam(self.lr, self.state, self.total, 2 * self.total, self.betas[0], self.betas[1], self.eps,
                             write_grads=self.keep_grads, stream=stream)

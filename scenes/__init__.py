@@ -453,7 +453,9 @@ def config4(seed=4, n_regions=16, n_min=50_000, n_max=2_000_000, width=1600,
 
 # ---------------------------------------------------- upstream gradients
 
-OUTPUT_CHANNELS = (("rgb", 3), ("normal", 3), ("dist", 1), ("depth", 1), ("alpha", 1))
+# upstream-gradient planes: the rendered outputs, then the soft contributor
+# count (drawn last, so the other planes keep their draws)
+OUTPUT_CHANNELS = (("rgb", 3), ("normal", 3), ("dist", 1), ("depth", 1), ("alpha", 1), ("count", 1))
 
 
 def grad_outputs(seed, render: Render, channels=None, scale=None):

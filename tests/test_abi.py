@@ -38,12 +38,13 @@ STRUCTS = {
     "pgsag_gaussians": (A.Gaussians, ["n", "sh_degree", "means", "sh"]),
     "pgsag_grads": (A.Grads, ["means", "sh"]),
     "pgsag_outputs": (A.Outputs, ["rgb", "alpha", "n_contrib"]),
-    "pgsag_grad_outputs": (A.GradOutputs, ["rgb", "alpha"]),
+    "pgsag_grad_outputs": (A.GradOutputs, ["rgb", "alpha", "count"]),
     "pgsag_render": (A.Render, ["set", "cam", "mask", "out", "gout"]),
     "pgsag_config": (A.Config, ["tile", "alpha_min", "logit_min", "depth_guard", "bg", "bwd_reduce",
                                          "deterministic"]),
     "pgsag_adam_config": (A.AdamConfig, ["lr", "step_state", "m_offset", "v_offset", "write_grads"]),
-    "pgsag_loss_config": (A.LossConfig, ["lambda_rgb", "lambda_load", "normal_norm", "normal_eps", "reserved"]),
+    "pgsag_loss_config": (A.LossConfig, ["lambda_rgb", "lambda_load", "normal_norm", "normal_eps", "load_term",
+                                         "reserved"]),
     "pgsag_plan_info": (A.PlanInfo, ["workspace_bytes", "pair_capacity", "tile_bits"]),
     "pgsag_layout": (A.Layout, ["status", "records", "grad2d", "end"]),
     "pgsag_status": (A.Status, ["pairs_needed", "overflow", "n_visible", "error", "reserved"]),

@@ -80,29 +80,41 @@ def _unsafe(margin):
     return u, nb
 
 
-def _check_loss(sc, lc, tile=16, seed=0, expect_depth_grad=True):
+def _check_loss(sc, lc, tile=16, seed=0, expect_depth_grad=True, unit_weights=False):
     b = device_scene(sc, RenderConfig(tile=tile), pair_capacity=1 << 20)
     loads = _synthetic_binning(b, sc, tile, seed + 7)
     ins = [scenes.loss_inputs(seed + 100 + r, rd) for r, rd in enumerate(sc.renders)]
+    # counts and Eq. 9 weights for the GC-load term
+    cw = [scenes.load_inputs(seed + 200 + r, rd) for r, rd in enumerate(sc.renders)]
     for r, x in enumerate(ins):
         for k in ("rgb", "normal", "depth"):
             b.out[r][k].copy_(torch.from_numpy(x[k]))
+        b.out[r]["n_contrib"].copy_(torch.from_numpy(cw[r][0]))
         for k in b.gout[r]:
             b.gout[r][k].fill_(float("nan"))       # the loss must write every masked pixel
     gt = [torch.from_numpy(x["gt"]).cuda() for x in ins]
-    vals = b.loss(gt, lc).cpu().numpy()
+    weights = None if unit_weights else [torch.from_numpy(w).cuda() for _, w in cw]
+    vals = b.loss(gt, lc, weights=weights).cpu().numpy()
     olc = ol.LossConfig(lc.lambda_rgb, lc.lambda_normal, lc.boundary_weight, lc.lambda_load, lc.normal_norm,
-                        lc.normal_eps)
+                        lc.normal_eps, lc.load_term)
     for r, rd in enumerate(sc.renders):
         x = ins[r]
         var = ol.tile_load_variance(*loads[r])
-        ref = ol.loss_and_grads(x["rgb"], x["normal"], x["depth"], x["gt"], rd.mask, rd.camera, olc, load_var=var)
+        g_in, w_in = cw[r]
+        ref = ol.loss_and_grads(x["rgb"], x["normal"], x["depth"], x["gt"], rd.mask, rd.camera, olc, load_var=var,
+                                n_contrib=g_in, weight=None if unit_weights else w_in)
         want = np.array([ref["total"], ref["rgb"], ref["normal"], ref["load"]])
         np.testing.assert_allclose(vals[r], want, rtol=1e-5, atol=1e-7, err_msg=f"render {r} loss values")
         m = ol.as_mask(rd.mask, (rd.camera.height, rd.camera.width))
         g = {k: b.gout[r][k].cpu().numpy() for k in b.gout[r]}
         np.testing.assert_allclose(g["rgb"][:, m], ref["g_rgb"][:, m], rtol=1e-6, atol=0)
         assert np.all(g["dist"][m] == 0) and np.all(g["alpha"][m] == 0)
+        if lc.load_term == 1:
+            ok, ratio, rel = grad_tolerance_check(g["count"][m], ref["g_count"][m])
+            assert ok, ("count", r, ratio, rel)
+            assert np.abs(ref["g_count"][m]).max() > 0
+        else:
+            assert np.all(g["count"][m] == 0)
         margin = ol.sign_margins(x["rgb"], x["normal"], x["depth"], x["gt"], rd.mask, rd.camera, olc)
         u, nb = _unsafe(margin) if lc.normal_norm == 1 else (np.zeros_like(m), np.zeros_like(m))
         assert u[m].mean() < 0.02, u[m].mean()
@@ -122,6 +134,18 @@ def test_loss_matches_oracle_two_renders(norm):
     sc = scenes.Scene([s.sets[0] for s in subs], [scenes.Render(k, s.renders[0].camera, s.renders[0].mask)
                                                   for k, s in enumerate(subs)])
     _check_loss(sc, LossConfig(normal_norm=norm, lambda_normal=0.3, lambda_load=0.41), seed=norm)
+
+
+@pytest.mark.parametrize("unit_weights", [False, True])
+def test_gc_load_term_matches_oracle(unit_weights):
+    """Eq. 9 GC-load as the balance-load term of Eq. 11: its value (the std
+    of n_contrib / w over masked pixels) and its gradient to the soft count,
+    with luminance-style weights and with unit weights."""
+    print(f"[case] GC-load term unit_weights={unit_weights}", flush=True)
+    subs = [scenes.small_scene(310 + k, n=200, width=64 + 30 * k, height=48 + 7 * k, sh_degree=0) for k in range(2)]
+    sc = scenes.Scene([s.sets[0] for s in subs], [scenes.Render(k, s.renders[0].camera, s.renders[0].mask)
+                                                  for k, s in enumerate(subs)])
+    _check_loss(sc, LossConfig(lambda_load=0.41, load_term=1), seed=21, unit_weights=unit_weights)
 
 
 def test_loss_matches_oracle_full_frame_1080p():

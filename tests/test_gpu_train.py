@@ -47,17 +47,18 @@ def _prepared_scene(seed, sh_degree=2):
     return scenes.Scene(sc.sets, renders), gts, refs
 
 
-def _oracle_step_grads(sc, gts, refs, olc):
+def _oracle_step_grads(sc, gts, refs, olc, weights=None):
     gs = sc.sets[0]
     total = {k: np.zeros(getattr(gs, k).shape) for k in PARAMS}
     losses = []
-    for rd, gt, ref in zip(sc.renders, gts, refs):
+    for r, (rd, gt, ref) in enumerate(zip(sc.renders, gts, refs)):
         im = ref["images"]
         planes = {k: im[k].astype(np.float32) for k in ("rgb", "normal", "depth")}
-        lg = ol.loss_and_grads(planes["rgb"], planes["normal"], planes["depth"], gt, rd.mask, rd.camera, olc)
-        losses.append(lg["total"])
-        g = oc.render_grad(gs, rd.camera, rd.mask, CFG,
-                           {"rgb": lg["g_rgb"], "normal": lg["g_normal"], "depth": lg["g_depth"]})
+        lg = ol.loss_and_grads(planes["rgb"], planes["normal"], planes["depth"], gt, rd.mask, rd.camera, olc,
+                               n_contrib=im["n_contrib"], weight=None if weights is None else weights[r])
+        losses.append(lg)
+        g = oc.render_grad(gs, rd.camera, rd.mask, CFG, {"rgb": lg["g_rgb"], "normal": lg["g_normal"],
+                                                        "depth": lg["g_depth"], "count": lg["g_count"]})
         for k in PARAMS:
             total[k] += g[k]
     return total, losses
@@ -81,13 +82,13 @@ def test_training_step_gradient_matches_oracle_chain(reduce):
     sc, gts, refs = _prepared_scene(401)
     lc = LossConfig(lambda_normal=0.2, normal_norm=2, lambda_load=0.41)
     olc = ol.LossConfig(lambda_normal=0.2, normal_norm=2, lambda_load=0.41)
-    ref, losses = _oracle_step_grads(sc, gts, refs, olc)
+    ref, lgs = _oracle_step_grads(sc, gts, refs, olc)
     t = _trainer(sc, gts, lc, lr=0.0, cfg=RenderConfig(tile=16, bwd_reduce=reduce), keep_grads=True)
     out = t.step().cpu().numpy()
     torch.cuda.synchronize()
     # the geometric terms (the load term is a value of the binning only)
     geo_gpu = (1 - 0.41) * (out[:, 1].astype(np.float64) + 0.2 * out[:, 2])
-    np.testing.assert_allclose(geo_gpu, losses, rtol=1e-4)
+    np.testing.assert_allclose(geo_gpu, [lg["total"] for lg in lgs], rtol=1e-4)
     ex = np.zeros(sc.sets[0].n, bool)
     for rd in sc.renders:
         dec = op.decide(sc.sets[0], rd.camera, CFG)
@@ -99,6 +100,39 @@ def test_training_step_gradient_matches_oracle_chain(reduce):
     # lr = 0: the parameters are unchanged, the step counter advanced
     np.testing.assert_array_equal(t.params[0]["means"].cpu().numpy(), sc.sets[0].means)
     assert int(t.state[0]) == 1
+
+
+@pytest.mark.parametrize("reduce", [0, 1])
+def test_training_step_with_gc_load_matches_oracle_chain(reduce):
+    """The GC-load of Eq. 9 as the balance-load term (lambda 0.41) with
+    luminance weights: its value from the integer counts, its gradient
+    through the soft count into every blended fragment's alpha, against the
+    oracle's chain."""
+    print(f"[case] train step with GC-load reduce={reduce}", flush=True)
+    sc, gts, refs = _prepared_scene(403)
+    ws = [ol.luminance_weights(gt, rd.mask).astype(np.float32) for gt, rd in zip(gts, sc.renders)]
+    lc = LossConfig(lambda_normal=0.2, normal_norm=2, lambda_load=0.41, load_term=1)
+    olc = ol.LossConfig(lambda_normal=0.2, normal_norm=2, lambda_load=0.41, load_term=1)
+    ref, lgs = _oracle_step_grads(sc, gts, refs, olc, weights=ws)
+    ref0, _ = _oracle_step_grads(sc, gts, refs, ol.LossConfig(lambda_normal=0.2, normal_norm=2, lambda_load=0.41))
+    t = _trainer(sc, gts, lc, lr=0.0, cfg=RenderConfig(tile=16, bwd_reduce=reduce), keep_grads=True,
+                 weights=[torch.from_numpy(w).cuda() for w in ws])
+    out = t.step().cpu().numpy()
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(out[:, 3], [lg["load"] for lg in lgs], rtol=1e-5)
+    np.testing.assert_allclose(out[:, 0], [lg["total"] for lg in lgs], rtol=1e-4)
+    ex = np.zeros(sc.sets[0].n, bool)
+    for rd in sc.renders:
+        dec = op.decide(sc.sets[0], rd.camera, CFG)
+        ex |= (dec.colour_min < 1e-5) | (dec.clamp_margin < 1e-5) | (dec.flip_margin < 1e-5)
+    for k in PARAMS:
+        got = t.batch.grads[0][k].cpu().numpy()
+        ok, ratio, rel = grad_tolerance_check(got, ref[k], exclude=ex)
+        assert ok, (k, ratio, rel)
+    # the term does steer the counts: the opacity gradient differs from the
+    # value-only (tile-variance) term's
+    d = np.abs(ref["opacity_logits"] - ref0["opacity_logits"]).max()
+    assert d > 1e-3 * np.abs(ref0["opacity_logits"]).max()
 
 
 @pytest.mark.parametrize("det", [False, True])

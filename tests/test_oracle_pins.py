@@ -461,10 +461,13 @@ def _loss64(gs, p64, cam, gout):
         g = oc._geo(proj, dec)
         pix = oc._pixel_list(cam, None, None)
         pixf = torch.tensor(pix[:, ::-1] + 0.5, dtype=torch.float64)
-        F, T, n, _, _, _ = oc.composite_block(pixf[:, 0], pixf[:, 1], g, CFG, want_allow=False)
+        F, T, n, _, _, count = oc.composite_block(pixf[:, 0], pixf[:, 1], g, CFG, want_allow=False)
         rgb, nrm, dist, depth, alpha, _, _ = oc._pixel_outputs(F, T, pixf, cam, CFG)
     tot = 0.0
-    for name, val in (("rgb", rgb), ("normal", nrm), ("dist", dist), ("depth", depth), ("alpha", alpha)):
+    for name, val in (("rgb", rgb), ("normal", nrm), ("dist", dist), ("depth", depth), ("alpha", alpha),
+                      ("count", count)):
+        if name not in gout:
+            continue
         c = 3 if val.dim() == 2 else 1
         gp = np.asarray(gout[name], np.float64).reshape(c, cam.height, cam.width)
         gv = gp[:, pix[:, 0], pix[:, 1]].T.reshape(val.shape)
