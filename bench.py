@@ -257,6 +257,30 @@ def step_roofline(stage, batch, scene, step_ms):
                     "over the measured step; peaks 157.3 TFLOP/s published and 78.6 single-issue"}
 
 
+def compositing_work(batch, torch, tile):
+    """Evaluated list entries against blended pairs, from the per-(tile,
+    wave) work counters the compositing kernels write: every entry a wave
+    evaluates costs all 64 of its lanes, so E/C = 64 x entries / blended
+    pairs is the lane-slots spent per blended (pixel, Gaussian) pair, the
+    lever the per-block culling works on."""
+    wpt = (tile // 8) ** 2
+    n = int(batch.info.n_tiles)
+    w = batch.view("work", torch.int32, n * wpt, 3).cpu().numpy().astype(np.int64)
+    cnt = batch.view("tile_count", torch.int32, n).cpu().numpy()
+    active = np.repeat(cnt > 0, wpt)
+    blends = float(sum(int(o["n_contrib"].sum().item()) for o in batch.out))
+    fwd, bwd, act = w[:, 0].sum(), w[:, 1].sum(), w[:, 2].sum()
+    waves = int(active.sum())
+    return {"waves": waves, "blended_pairs": int(blends),
+            "fwd_entries": int(fwd), "fwd_E_per_lane": round(fwd / max(waves, 1), 1),
+            "fwd_E_over_C": round(64 * fwd / max(blends, 1), 3),
+            "bwd_entries": int(bwd), "bwd_E_per_lane": round(bwd / max(waves, 1), 1),
+            "bwd_E_over_C": round(64 * bwd / max(blends, 1), 3),
+            "bwd_entries_contributing": int(act), "bwd_contributing_share": round(act / max(bwd, 1), 4),
+            "note": "E = list entries a wave evaluates (each for all 64 lanes) per wave of a tile holding masked "
+                    "pixels; E/C = 64 E summed over waves / blended pairs"}
+
+
 def tile_lists(batch, torch):
     """Per-tile list lengths over tiles holding masked pixels: the workload
     each compositing workgroup walks, whose spread is the thread-waiting
@@ -491,6 +515,7 @@ def batched_speedup(torch, steps=5, scale=1.0):
                            "workgroups_per_cu": cfg.workgroups_per_cu, "bwd_reduce": cfg.bwd_reduce}
     out["graph_stages_ms"] = {k: round(v, 3) for k, v in stage.items()}
     out["tile_lists"] = tile_lists(bb, torch)
+    out["compositing_work"] = compositing_work(bb, torch, cfg.tile)
     out["hbm_kernels"] = hbm_kernels(stage, bb, sc)
     out["step_roofline"] = step_roofline(stage, bb, sc, best * 1e3)
     del bb.workspace
@@ -630,6 +655,7 @@ def main():
     value = masked / (ms_wall * 1e-3) / 1e6
     summary = stage.pop("_summary", None)
     lists = tile_lists(batch, torch)
+    work = compositing_work(batch, torch, args.tile)
     dom, roof = roofline(stage, batch, sc, torch, args.tile)
     hbm = hbm_kernels(stage, batch, sc)
     step_roof = step_roofline(stage, batch, sc, ms_wall)
@@ -662,6 +688,7 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in stage.items()},
         "step_event_ms": summary,
         "tile_lists": lists,
+        "compositing_work": work,
         "device": {"name": torch.cuda.get_device_name(0), "hip": torch.version.hip, "torch": torch.__version__},
         "with_loss": {"ms_per_step": round(ms_loss, 4), "mpix_s": round(masked / (ms_loss * 1e-3) / 1e6, 2),
                       "note": "same step with the loss kernels in the graph (ground truth: the render of the "

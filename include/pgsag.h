@@ -205,6 +205,10 @@ typedef struct pgsag_layout {
   uint64_t pixel_T;    /* float [n_pixels] final transmittance */
   uint64_t pixel_last; /* int32 [n_pixels] last blended pair index, -1 none */
   uint64_t grad2d;     /* float [n_records][16] per-record pixel sums of the backward compositing pass */
+  uint64_t work;       /* uint32 [n_tiles][(tile/8)^2][3] per (tile, 8x8-pixel wave): list entries the
+                          forward compositing evaluated, entries the backward evaluated, and backward
+                          entries with at least one contributing pixel (each entry is evaluated for all
+                          64 pixels of the wave); written by every forward / backward */
   uint64_t end;
 } pgsag_layout;
 

@@ -66,7 +66,7 @@ class PlanInfo(C.Structure):
 class Layout(C.Structure):
     _fields_ = [(name, C.c_uint64) for name in
                 ("status", "tile_count", "sat", "ranges", "queue", "records", "depth_key", "rect",
-                 "n_active", "pair_tile", "pair_record", "pixel_T", "pixel_last", "grad2d", "end")]
+                 "n_active", "pair_tile", "pair_record", "pixel_T", "pixel_last", "grad2d", "work", "end")]
 
 
 class LossConfig(C.Structure):

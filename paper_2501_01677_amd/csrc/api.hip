@@ -145,6 +145,7 @@ Layout make_layout(const pgsag_config &cfg, const Sizes &z, uint64_t cap, int n_
   L.pix_T = take(z.n_pixels * 4);
   L.pix_last = take(z.n_pixels * 4);
   L.g2 = take(z.n_records * kG2 * 4);
+  L.work = take(z.n_tiles * (uint64_t)waves_per_tile(cfg.tile) * 3 * 4);
   if (cfg.deterministic) {
     L.pair_rec = take(cap * 4);
     L.part = take(cap * (uint64_t)waves_per_tile(cfg.tile) * kG2 * 4);
@@ -447,6 +448,7 @@ int pgsag_layout_of(const void *host_desc, pgsag_layout *out) {
   out->pixel_T = L.pix_T;
   out->pixel_last = L.pix_last;
   out->grad2d = L.g2;
+  out->work = L.work;
   out->end = L.end;
   return PGSAG_OK;
 }

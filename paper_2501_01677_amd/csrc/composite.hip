@@ -4,17 +4,21 @@
 // Shape: one workgroup per tile of T x T pixels, one lane per pixel (each
 // pixel is a GPU thread, Sec. 4.3); a wave covers an 8 x 8 pixel block.  The
 // tile's depth-ordered list of projected records is staged through LDS in
-// batches (one coalesced 64-byte record load per lane).  After each batch
-// load every wave builds its own list of the records that can reach the
-// alpha cut-off somewhere in its block -- an exact minimum of the record's
-// quadratic form over the block's pixel centres -- compacted with ballots.
-// A list entry carries the record's exponent expanded around the block
-// origin, so that a lane evaluates
+// batches (one coalesced 64-byte record load per lane), field-major: plane j
+// holds 16-byte field j of every slot, so the lanes that stage or scan
+// consecutive slots touch consecutive banks.  After each batch load every
+// wave builds its own list of the records that can reach the alpha cut-off
+// somewhere in its block -- an exact minimum of the record's quadratic form
+// over the block's pixel centres -- compacted with ballots.  A list entry
+// carries the record's exponent expanded around the block origin, so that a
+// lane evaluates
 //     e = log2(o) - q/2 * log2(e)  as  F + D lx + E ly + A lx^2 + B lx ly + C ly^2
-// with five FMAs from its constant (lx, ly) offsets, compares e with
-// log2(alpha_min) and calls exp2 only when the fragment passes.  Lanes whose
-// pixel is unmasked or whose transmittance has stopped idle; the workgroup
-// leaves the tile when no lane is alive (__syncthreads_count).
+// with five FMAs from its constant (lx, ly) offsets, and compares e with
+// log2(alpha_min).  Forward entries hold all six coefficients and the slot's
+// byte offset (no dependent LDS read per entry), and the entry loop is
+// unrolled by two so that its prefetch needs no register copies.  Lanes
+// whose pixel is unmasked or whose transmittance has stopped idle; the
+// workgroup leaves the tile when no lane is alive (__syncthreads_count).
 //
 // The backward pass walks the same list back to front from the tile's
 // largest last-blended index, recovering each pixel's transmittance before a
@@ -43,16 +47,53 @@ constexpr float kHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
 // Records staged per LDS batch (64 for 8x8 tiles, else 128: keeps several
 // workgroups resident per CU).
 template <int T>
-constexpr int batch_of() { return T == 8 ? 64 : 128; }
+constexpr int batch_of() { return T == 8 ? 64 : (T == 16 ? 96 : 64); }
 // Backward batches: 96 records with the matrix-core reduction at T = 16 (its
 // per-wave buffers leave room for 5 workgroups per CU only then).
 template <int T, bool MM>
-constexpr int bwd_batch_of() { return MM && T == 16 ? 96 : batch_of<T>(); }
+constexpr int bwd_batch_of() { return MM && T == 16 ? 96 : (T == 8 ? 64 : 128); }
 
-struct Entry {   // one record in one wave's list (16 bytes)
+struct Entry {   // one record in one wave's list of the backward pass (16 bytes)
   float F, D, E;
   uint32_t k;    // slot of the record in the batch
 };
+
+// One record in one wave's list of the forward pass (32 bytes, two 16-byte
+// LDS reads): all six exponent coefficients, so evaluating it needs no
+// second, dependent LDS read, and the slot as a byte offset into a field
+// plane of the staged batch.
+struct FwdEntry {
+  float F, D, E, A;  // exponent F + D lx + E ly + A lx^2 + B lx ly + C ly^2
+  float B, C;
+  uint32_t koff;     // slot * 16
+  uint32_t pad;
+};
+
+// Field j (0..3) of the record of a forward entry in the staged batch
+// (field-major, at LDS offset 0 of the forward kernel).
+template <int NT>
+__device__ __forceinline__ float4 field_of(const float4 *sb, const FwdEntry &e, int j) {
+  return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(sb) + e.koff + j * NT * 16);
+}
+
+__device__ __forceinline__ void set_entry(Entry &e, const float4 *sb, int NT, int k, float F, float D, float E) {
+  e.F = F;
+  e.D = D;
+  e.E = E;
+  e.k = (uint32_t)k;
+}
+
+__device__ __forceinline__ void set_entry(FwdEntry &e, const float4 *sb, int NT, int k, float F, float D, float E) {
+  const float4 r0 = sb[k];
+  e.F = F;
+  e.D = D;
+  e.E = E;
+  e.A = -kHalfLog2e * r0.z;
+  e.B = -2.f * kHalfLog2e * r0.w;
+  e.C = -kHalfLog2e * sb[NT + k].x;
+  e.koff = (uint32_t)k * 16u;
+  e.pad = 0u;
+}
 
 // Minimum of a x^2 + 2 b x y + c y^2 (a, c > 0, ac > b^2) over the box
 // [x0, x1] x [y0, y1]: zero when the box holds the origin, otherwise the
@@ -84,8 +125,9 @@ __device__ __forceinline__ float qmin_box(float a, float b, float c, float x0, f
 // can reach log2(alpha_min) (with a small margin) at one of the block's
 // pixel centres, with their exponent expansion around the block origin
 // (ox, oy).  Returns the list length (uniform across the wave).
-__device__ __forceinline__ int build_list(const float4 (*srec)[4], int cnt, float ox, float oy, float l2min,
-                                          Entry *list) {
+template <int NT, typename EntryT>
+__device__ __forceinline__ int build_list(const float4 *sb, int cnt, float ox, float oy, float l2min,
+                                          EntryT *list) {
   const int lane = threadIdx.x & 63;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   int len = 0;
@@ -94,9 +136,9 @@ __device__ __forceinline__ int build_list(const float4 (*srec)[4], int cnt, floa
     bool pass = false;
     float F = 0.f, D = 0.f, E = 0.f;
     if (k < cnt) {
-      const float4 r0 = srec[k][0];
-      const float4 r1 = srec[k][1];
-      const float4 r3 = srec[k][3];
+      const float4 r0 = sb[k];
+      const float4 r1 = sb[NT + k];
+      const float4 r3 = sb[3 * NT + k];
       const float a = r0.z, b = r0.w, c = r1.x, l2o = r3.w;
       const float dx0 = ox - r0.x, dy0 = oy - r0.y;
       const float qm = qmin_box(a, b, c, dx0, dx0 + 7.f, dy0, dy0 + 7.f);
@@ -110,11 +152,8 @@ __device__ __forceinline__ int build_list(const float4 (*srec)[4], int cnt, floa
     }
     const uint64_t m = __ballot(pass);
     if (pass) {
-      Entry e;
-      e.F = F;
-      e.D = D;
-      e.E = E;
-      e.k = (uint32_t)k;
+      EntryT e;
+      set_entry(e, sb, NT, k, F, D, E);
       list[len + __popcll(m & lt)] = e;
     }
     len += __popcll(m);
@@ -131,6 +170,16 @@ __device__ __forceinline__ int build_list(const float4 (*srec)[4], int cnt, floa
 struct LaneOffsets {
   float lx, ly;
 };
+
+__device__ __forceinline__ float lane_exponent(const FwdEntry &e, const LaneOffsets &L) {
+#pragma clang fp contract(off)
+  float u = __builtin_fmaf(e.A, L.lx, e.D);
+  u = __builtin_fmaf(e.B, L.ly, u);
+  const float w = __builtin_fmaf(e.C, L.ly, e.E);
+  float v = __builtin_fmaf(L.lx, u, e.F);
+  v = __builtin_fmaf(L.ly, w, v);
+  return v;
+}
 
 __device__ __forceinline__ float lane_exponent(const Entry &e, const float4 &abc, const LaneOffsets &L) {
 #pragma clang fp contract(off)
@@ -173,27 +222,28 @@ __device__ __forceinline__ void tile_geom(const void *desc, const Header &h, uin
 
 // Stages batch records [j0, j1) into LDS: the raw 64-byte records and the
 // per-record exponent coefficients (A, B, C).
-template <int NT>
+template <int NT, bool ABC>
 __device__ __forceinline__ void stage_batch(const float4 *__restrict__ rec4, const uint32_t *__restrict__ vals,
-                                            uint32_t j0, uint32_t j1, float4 (*srec)[4], float4 *sabc,
-                                            uint32_t *sid) {
+                                            uint32_t j0, uint32_t j1, float4 *sb, uint32_t *sid) {
   const uint32_t j = j0 + threadIdx.x;
   if (threadIdx.x < NT && j < j1) {
     const uint32_t rid = vals[j];
     const float4 *src = rec4 + (uint64_t)rid * 4;
     const float4 r0 = src[0], r1 = src[1];
-    srec[threadIdx.x][0] = r0;
-    srec[threadIdx.x][1] = r1;
-    srec[threadIdx.x][2] = src[2];
-    srec[threadIdx.x][3] = src[3];
-    sabc[threadIdx.x] = make_float4(-kHalfLog2e * r0.z, -2.f * kHalfLog2e * r0.w, -kHalfLog2e * r1.x, 0.f);
+    const float4 r2 = src[2], r3 = src[3];
+    sb[threadIdx.x] = r0;
+    sb[NT + threadIdx.x] = r1;
+    sb[2 * NT + threadIdx.x] = r2;
+    sb[3 * NT + threadIdx.x] = r3;
+    if constexpr (ABC)
+      sb[4 * NT + threadIdx.x] = make_float4(-kHalfLog2e * r0.z, -2.f * kHalfLog2e * r0.w, -kHalfLog2e * r1.x, 0.f);
     if (sid) sid[threadIdx.x] = rid;
   }
 }
 
 template <int T>
 __device__ void forward_tile(const void *__restrict__ desc, const Header &h, void *__restrict__ ws, uint32_t tile,
-                             float4 (*srec)[4], float4 *sabc, Entry (*lists)[batch_of<T>()],
+                             float4 *srec, FwdEntry (*lists)[batch_of<T>()],
                              const uint32_t *__restrict__ vals) {
   constexpr int NT = batch_of<T>();
   TileGeom g;
@@ -208,54 +258,68 @@ __device__ void forward_tile(const void *__restrict__ desc, const Header &h, voi
   const float4 *rec4 = ws_ptr<float4>(ws, h.ws.rec);
   const float amax = h.cfg.alpha_max, tmin = h.cfg.t_min;
   const float l2min = __log2f(h.cfg.alpha_min);
-  Entry *list = lists[threadIdx.x >> 6];
+  FwdEntry *list = lists[threadIdx.x >> 6];
   bool done = !masked;
+  uint32_t nev = 0;  // list entries this wave evaluated (each for all its 64 lanes)
   float Tr = 1.f;
   float F[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   int32_t n = 0, last = -1;
   for (uint32_t b = rg.x; b < rg.y; b += NT) {
     if (__syncthreads_count(!done) == 0) break;
     const uint32_t b1 = min(rg.y, b + NT);
-    stage_batch<NT>(rec4, vals, b, b1, srec, sabc, nullptr);
+    stage_batch<NT, false>(rec4, vals, b, b1, srec, nullptr);
     __syncthreads();
     if (__ballot(!done) == 0ull) continue;
-    const int len = build_list(srec, (int)(b1 - b), g.ox, g.oy, l2min, list);
-    // Branch-free over the lanes (selects, no divergent blocks); the next
-    // entry and its coefficients are loaded while this one is evaluated.
-    Entry e = list[0];
-    float4 abc = sabc[len > 0 ? e.k : 0];
-    for (int t = 0; t < len; ++t) {
-      const int tn = t + 1 < len ? t + 1 : t;
-      const Entry en = list[tn];
-      const float4 abcn = sabc[en.k];
-      const float ex = lane_exponent(e, abc, g.L);
+    const int len = build_list<NT>(srec, (int)(b1 - b), g.ox, g.oy, l2min, list);
+    // Branch-free over the lanes (selects, no divergent blocks).  The slot
+    // of the last blended record of this batch is kept and turned into the
+    // pair index once per batch.
+    int lastk = -1;
+    const auto eval = [&](const FwdEntry &e) {
+      const float ex = lane_exponent(e, g.L);
       const bool pass = !done && ex >= l2min;
-      {  // the wave's list is culled to its block: evaluate without a branch
-        // exp2 >= 0: the median of (x, 0, amax) is min(x, amax) in one instruction
-        const float a = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(ex), 0.f, amax);
-        const float Tn = Tr * (1.f - a);
-        const bool stop = pass && Tn < tmin;
-        const bool blend = pass && !stop;
-        const float4 r1 = srec[e.k][1], r2 = srec[e.k][2];
-        const float d = srec[e.k][3].x;
-        const float w = blend ? a * Tr : 0.f;
-        F[0] = fmaf(w, r1.z, F[0]);
-        F[1] = fmaf(w, r1.w, F[1]);
-        F[2] = fmaf(w, r2.x, F[2]);
-        F[3] = fmaf(w, r2.y, F[3]);
-        F[4] = fmaf(w, r2.z, F[4]);
-        F[5] = fmaf(w, r2.w, F[5]);
-        F[6] = fmaf(w, d, F[6]);
-        Tr = blend ? Tn : Tr;
-        n += blend ? 1 : 0;
-        last = blend ? (int32_t)(b + e.k) : last;
-        done = done || stop;
+      // exp2 >= 0: the median of (x, 0, amax) is min(x, amax) in one instruction
+      const float a = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(ex), 0.f, amax);
+      const float Tn = Tr * (1.f - a);
+      const bool stop = pass && Tn < tmin;
+      const bool blend = pass && !stop;
+      const float4 r1 = field_of<NT>(srec, e, 1), r2 = field_of<NT>(srec, e, 2);
+      const float d = field_of<NT>(srec, e, 3).x;
+      const float w = blend ? a * Tr : 0.f;
+      F[0] = fmaf(w, r1.z, F[0]);
+      F[1] = fmaf(w, r1.w, F[1]);
+      F[2] = fmaf(w, r2.x, F[2]);
+      F[3] = fmaf(w, r2.y, F[3]);
+      F[4] = fmaf(w, r2.z, F[4]);
+      F[5] = fmaf(w, r2.w, F[5]);
+      F[6] = fmaf(w, d, F[6]);
+      Tr = blend ? Tn : Tr;
+      n += blend ? 1 : 0;
+      lastk = blend ? (int)e.koff : lastk;
+      done = done || stop;
+    };
+    // two entries per iteration: `e` is loop-carried and reloaded after
+    // its evaluation, `f` is loaded and used within the iteration
+    FwdEntry e = list[0];
+    int t = 0;
+    while (t < len) {
+      const FwdEntry f = list[t + 1 < len ? t + 1 : t];
+      eval(e);
+      if (t + 1 >= len) {
+        t += 1;
+        break;
       }
-      e = en;
-      abc = abcn;
-      if ((t & 7) == 7 && __ballot(!done) == 0ull) break;
+      e = list[t + 2 < len ? t + 2 : t + 1];
+      eval(f);
+      t += 2;
+      if ((t & 7) == 0 && __ballot(!done) == 0ull) break;
     }
+    nev += (uint32_t)t;
+    if (lastk >= 0) last = (int32_t)(b + ((uint32_t)lastk >> 4));
   }
+  // work counter of this (tile, wave): [0] forward entries evaluated
+  if ((threadIdx.x & 63) == 0)
+    ws_ptr<uint32_t>(ws, h.ws.work)[((uint64_t)tile * ((T / 8) * (T / 8)) + (threadIdx.x >> 6)) * 3] = nev;
   if (!g.inside) return;
   const uint64_t HW = (uint64_t)rd.cam.H * W;
   float rgb0 = 0.f, rgb1 = 0.f, rgb2 = 0.f, alpha = 0.f, depth = 0.f;
@@ -444,13 +508,19 @@ __device__ __forceinline__ uint32_t slot_fields(int kk) {
 // index, wave); det_reduce_kernel adds them per record in a fixed order.
 template <int T, bool MM, bool DET>
 __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, const Header &h, void *__restrict__ ws, uint32_t tile,
-                              float4 (*srec)[4], float4 *sabc, uint32_t *sid, Entry (*lists)[bwd_batch_of<T, MM>()],
+                              float4 *sb, uint32_t *sid, Entry (*lists)[bwd_batch_of<T, MM>()],
                               WaveAcc *accs, int *smax, const uint32_t *__restrict__ vals) {
   constexpr int NT = bwd_batch_of<T, MM>();
   constexpr int WPT = (T / 8) * (T / 8);
   constexpr int STRIDE = DET ? WPT * kG2 : kG2;
+  // work counters of this (tile, wave): [1] backward entries evaluated, [2]
+  // of them with a contributing lane
+  uint32_t *work = ws_ptr<uint32_t>(ws, h.ws.work) + ((uint64_t)tile * WPT + (threadIdx.x >> 6)) * 3;
   // nothing to do for a tile without masked pixels (uniform over the workgroup)
-  if (ws_ptr<const uint32_t>(ws, h.ws.tile_count)[tile] == 0) return;
+  if (ws_ptr<const uint32_t>(ws, h.ws.tile_count)[tile] == 0) {
+    if ((threadIdx.x & 63) == 0) work[1] = work[2] = 0u;
+    return;
+  }
   TileGeom g;
   tile_geom<T>(desc, h, tile, g);
   const DevRender &rd = *g.rd;
@@ -526,7 +596,11 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
   if ((threadIdx.x & 63) == 0 && wlast >= 0) atomicMax(smax, wlast);
   __syncthreads();
   const int maxlast = *smax;
-  if (maxlast < (int)rg.x) return;  // uniform: no pixel blended anything
+  if (maxlast < (int)rg.x) {  // uniform: no pixel blended anything
+    if ((threadIdx.x & 63) == 0) work[1] = work[2] = 0u;
+    return;
+  }
+  uint32_t nev = 0, nact = 0;
   const uint32_t end = (uint32_t)maxlast + 1;
   // With MM, records past the wave's own largest last-blended index
   // contribute to none of its pixels and stay out of its lists.  (The
@@ -559,22 +633,24 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
     const uint32_t bstart = (uint32_t)max((int64_t)rg.x, bend - NT);
     const int cnt = (int)((uint32_t)bend - bstart);
     __syncthreads();
-    stage_batch<NT>(rec4, vals, bstart, (uint32_t)bend, srec, sabc, sid);
+    stage_batch<NT, true>(rec4, vals, bstart, (uint32_t)bend, sb, sid);
     __syncthreads();
     if (MM ? wlast >= (int32_t)bstart : __ballot(last >= (int32_t)bstart) != 0ull) {
-      const int len = build_list(srec, MM ? min(cnt, wlast - (int32_t)bstart + 1) : cnt, g.ox, g.oy, l2min, list);
+      const int len = build_list<NT>(sb, MM ? min(cnt, wlast - (int32_t)bstart + 1) : cnt, g.ox, g.oy, l2min, list);
+      nev += (uint32_t)len;
       if constexpr (!MM) {
         for (int t = len - 1; t >= 0; --t) {
           const Entry cur = list[t];
           const int32_t idx = (int32_t)(bstart + cur.k);
           // Every lane evaluates the fragment (the wave executes it anyway when
           // any lane contributes); lanes that do not contribute get zero weight.
-          const float ex = lane_exponent(cur, sabc[cur.k], g.L);
+          const float ex = lane_exponent(cur, sb[4 * NT + cur.k], g.L);
           const bool contrib = idx <= last && ex >= l2min;
           if (__ballot(contrib) == 0ull) continue;
+          ++nact;
           const float raw = __builtin_amdgcn_exp2f(ex);
           const float a = __builtin_amdgcn_fmed3f(raw, 0.f, amax);  // min(raw, amax), raw >= 0
-          const float4 r0 = srec[cur.k][0], r1 = srec[cur.k][1], r2 = srec[cur.k][2], r3 = srec[cur.k][3];
+          const float4 r0 = sb[cur.k], r1 = sb[NT + cur.k], r2 = sb[2 * NT + cur.k], r3 = sb[3 * NT + cur.k];
           const float f[7] = {r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
           const float iom = __builtin_amdgcn_rcpf(1.f - a);  // 1 / (1 - alpha), alpha <= 0.99
           const float Tp = Tr * iom;
@@ -616,17 +692,17 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
         // back to front; the next entry and its coefficients are loaded while
         // this one is evaluated
         Entry e = list[len > 0 ? len - 1 : 0];
-        float4 abc = sabc[len > 0 ? e.k : 0];
+        float4 abc = sb[4 * NT + (len > 0 ? e.k : 0)];
         for (int t = len - 1; t >= 0; --t) {
           const Entry en = list[t > 0 ? t - 1 : 0];
-          const float4 abcn = sabc[en.k];
+          const float4 abcn = sb[4 * NT + en.k];
           const int32_t idx = (int32_t)(bstart + e.k);
           // Every lane evaluates the fragment (the wave executes it anyway when
           // any lane contributes); lanes that do not contribute get zero weight.
           const float ex = lane_exponent(e, abc, g.L);
           const bool contrib = idx <= last && ex >= l2min;
           if (__ballot(contrib) != 0ull) {
-            const float4 r0 = srec[e.k][0], r1 = srec[e.k][1], r2 = srec[e.k][2], r3 = srec[e.k][3];
+            const float4 r0 = sb[e.k], r1 = sb[NT + e.k], r2 = sb[2 * NT + e.k], r3 = sb[3 * NT + e.k];
             const uint32_t rid = sid[e.k];
             const float raw = __builtin_amdgcn_exp2f(ex);
             const float a = __builtin_amdgcn_fmed3f(raw, 0.f, amax);  // min(raw, amax), raw >= 0
@@ -656,6 +732,7 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
             icx = mine ? r0.x : icx;
             icy = mine ? r0.y : icy;
             if (++nb == 8) {
+              nact += 8;
               __builtin_amdgcn_wave_barrier();
               flush_records<STRIDE, DET>(acc, 8, bf, fields, isid, icx, icy, bcx, bcy, dst);
               __builtin_amdgcn_wave_barrier();
@@ -669,8 +746,13 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
     }
   }
   if (MM && nb > 0) {
+    nact += (uint32_t)nb;
     __builtin_amdgcn_wave_barrier();
     flush_records<STRIDE, DET>(acc, nb, bf, fields, isid, icx, icy, bcx, bcy, dst);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    work[1] = nev;
+    work[2] = nact;
   }
 }
 
@@ -685,16 +767,25 @@ __device__ __forceinline__ uint32_t queue_chunk_for(const Header &h, void *ws) {
 }
 
 template <int T>
-__global__ void __launch_bounds__(T *T) forward_kernel(const void *__restrict__ desc, void *__restrict__ ws,
+__global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(8))) forward_kernel(const void *__restrict__ desc, void *__restrict__ ws,
                                                         const uint32_t *__restrict__ vals) {
   constexpr int NT = batch_of<T>();
-  __shared__ float4 srec[NT][4];
-  __shared__ float4 sabc[NT];
-  __shared__ Entry lists[T * T / 64][NT];
-  __shared__ uint32_t s_item;
+  // one LDS block with the staged batch first, at offset 0 (forward
+  // entries hold byte offsets into it); the batch is field-major: plane j
+  // (0..3) holds field j of every slot, so a wave reading or writing
+  // consecutive slots touches consecutive banks
+  struct Smem {
+    float4 sb[4 * NT];
+    FwdEntry lists[T * T / 64][NT];
+    uint32_t item;
+  };
+  __shared__ Smem sm;
+  float4 *sb = sm.sb;
+  FwdEntry (*lists)[NT] = sm.lists;
+  uint32_t &s_item = sm.item;
   const Header &h = *header(desc);
   if (!h.cfg.persistent) {
-    forward_tile<T>(desc, h, ws, blockIdx.x, srec, sabc, lists, vals);
+    forward_tile<T>(desc, h, ws, blockIdx.x, sb, lists, vals);
     return;
   }
   uint32_t *ctr = ws_ptr<uint32_t>(ws, h.ws.status) + S_QUEUE_FWD;
@@ -710,7 +801,7 @@ __global__ void __launch_bounds__(T *T) forward_kernel(const void *__restrict__ 
     const uint32_t stop = min(ntiles, base + chunk);
     for (uint32_t it = base; it < stop; ++it) {
       __syncthreads();
-      forward_tile<T>(desc, h, ws, queue[it], srec, sabc, lists, vals);
+      forward_tile<T>(desc, h, ws, queue[it], sb, lists, vals);
     }
   }
 }
@@ -723,8 +814,7 @@ template <int T, bool MM, bool DET>
 __global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(MM ? (T == 16 ? 5 : 4) : 8))) backward_kernel(const void *__restrict__ desc, void *__restrict__ ws,
                                                          const uint32_t *__restrict__ vals) {
   constexpr int NT = bwd_batch_of<T, MM>();
-  __shared__ float4 srec[NT][4];
-  __shared__ float4 sabc[NT];
+  __shared__ float4 sb[5 * NT];  // field-major staged batch (see forward_kernel)
   __shared__ uint32_t sid[NT];
   __shared__ Entry lists[T * T / 64][NT];
   __shared__ std::conditional_t<MM, WaveAcc, uint32_t> accs_[T * T / 64];
@@ -733,7 +823,7 @@ __global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(MM ? 
   __shared__ uint32_t s_item;
   const Header &h = *header(desc);
   if (!h.cfg.persistent) {
-    backward_tile<T, MM, DET>(desc, h, ws, blockIdx.x, srec, sabc, sid, lists, accs, &smax, vals);
+    backward_tile<T, MM, DET>(desc, h, ws, blockIdx.x, sb, sid, lists, accs, &smax, vals);
     return;
   }
   uint32_t *ctr = ws_ptr<uint32_t>(ws, h.ws.status) + S_QUEUE_BWD;
@@ -749,7 +839,7 @@ __global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(MM ? 
     const uint32_t stop = min(ntiles, base + chunk);
     for (uint32_t it = base; it < stop; ++it) {
       __syncthreads();
-      backward_tile<T, MM, DET>(desc, h, ws, queue[it], srec, sabc, sid, lists, accs, &smax, vals);
+      backward_tile<T, MM, DET>(desc, h, ws, queue[it], sb, sid, lists, accs, &smax, vals);
     }
   }
 }

@@ -86,6 +86,10 @@ struct Layout {
   uint64_t pair_key[2], pair_val[2];
   uint64_t sorted_key, sorted_val;  // the pair buffers holding the tile-sorted result
   uint64_t pix_T, pix_last, g2;
+  // uint32 [n_tiles][waves per tile][3] compositing work per (tile, wave):
+  // forward list entries evaluated, backward entries evaluated, backward
+  // entries with a contributing lane
+  uint64_t work;
   // Deterministic backward only (0 otherwise): the record of every emitted
   // pair (uint32 [capacity], emission order), and one 16-float slot per
   // (tile-sorted pair, wave of the tile) for the backward compositing sums.

@@ -46,7 +46,7 @@ STRUCTS = {
     "pgsag_loss_config": (A.LossConfig, ["lambda_rgb", "lambda_load", "normal_norm", "normal_eps", "load_term",
                                          "reserved"]),
     "pgsag_plan_info": (A.PlanInfo, ["workspace_bytes", "pair_capacity", "tile_bits"]),
-    "pgsag_layout": (A.Layout, ["status", "records", "grad2d", "end"]),
+    "pgsag_layout": (A.Layout, ["status", "records", "grad2d", "work", "end"]),
     "pgsag_status": (A.Status, ["pairs_needed", "overflow", "n_visible", "error", "reserved"]),
     "pgsag_vote_view": (A.VoteView, ["cam", "mask"]),
     "pgsag_volume": (A.Volume, ["origin", "voxel", "nx", "nz", "trunc"]),

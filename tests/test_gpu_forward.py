@@ -222,6 +222,39 @@ def _all_outputs(b):
     return [outputs_numpy(b, r) for r in range(len(b.renders))]
 
 
+@pytest.mark.parametrize("tile,reduce", [(8, 0), (16, 0), (16, 1), (32, 0)])
+def test_compositing_work_counters_bound_the_blending(tile, reduce):
+    """The per-(tile, wave) work counters: a wave evaluates at least as many
+    list entries as any of its pixels blends fragments; in the backward the
+    entries with a contributing pixel number at least that maximum and at
+    most the wave's blended pairs and its evaluated entries; waves of tiles
+    without masked pixels count nothing."""
+    print(f"[case] work counters tile={tile} reduce={reduce}", flush=True)
+    sc = scenes.small_scene(151, n=600, width=90, height=70, sh_degree=1)
+    b = device_scene(sc, RenderConfig(tile=tile, bwd_reduce=reduce))
+    b.forward()
+    b.backward([{k: torch.from_numpy(v).cuda() for k, v in scenes.grad_outputs(3, rd).items()}
+                for rd in sc.renders])
+    torch.cuda.synchronize()
+    rd = sc.renders[0]
+    W, H = rd.camera.width, rd.camera.height
+    tx, ty = (W + tile - 1) // tile, (H + tile - 1) // tile
+    sb = tile // 8
+    wpt = sb * sb
+    work = b.view("work", torch.int32, tx * ty * wpt, 3).cpu().numpy().astype(np.int64)
+    tc = b.view("tile_count", torch.int32, tx * ty).cpu().numpy()
+    nc = np.zeros((ty * tile, tx * tile), np.int64)
+    nc[:H, :W] = b.out[0]["n_contrib"].cpu().numpy()
+    # per wave (8x8 block): max and sum of n_contrib
+    blocks = nc.reshape(ty, sb, 8, tx, sb, 8).transpose(0, 3, 1, 4, 2, 5).reshape(ty * tx * wpt, 64)
+    mx, sm = blocks.max(1), blocks.sum(1)
+    active = np.repeat(tc > 0, wpt)
+    assert np.all(work[~active] == 0)
+    assert np.all(work[:, 0] >= mx)
+    assert np.all(work[:, 2] >= mx) and np.all(work[:, 2] <= sm) and np.all(work[:, 2] <= work[:, 1])
+    assert sm.sum() == int(b.out[0]["n_contrib"].sum()) and sm.sum() > 0
+
+
 def test_invariants_tiles_persistent_mask_determinism():
     print("[case] invariants", flush=True)
     sc = scenes.small_scene(71, n=700, width=97, height=75, sh_degree=2, n_views=2)
