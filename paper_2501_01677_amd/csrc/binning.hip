@@ -385,6 +385,26 @@ __global__ void __launch_bounds__(kCompactBlock) compact_kernel(const void *__re
       if (hs[p][threadIdx.x]) atomicAdd(&dh[p * kRadixBins + threadIdx.x], hs[p][threadIdx.x]);
 }
 
+// Which depth passes are real, decided once from the complete histograms
+// (a pass whose digit is the same for every key is skipped), for every
+// workgroup of the pass kernels: one wave.
+__global__ void __launch_bounds__(64) depth_plan_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+  const Header &h = *header(desc);
+  uint32_t *st = status_of(ws, h);
+  const uint32_t *dh = ws_ptr<const uint32_t>(ws, h.ws.dhist);
+  const uint32_t n = st[S_NVIS];
+  const int lane = threadIdx.x;
+  uint32_t skip = 0;
+#pragma unroll
+  for (int p = 0; p < kDepthPasses; ++p) {
+    bool one = false;
+#pragma unroll
+    for (int q = 0; q < kRadixBins / 64; ++q) one |= dh[p * kRadixBins + q * 64 + lane] == n;
+    if (n > 0 && __ballot(one)) skip |= 1u << p;
+  }
+  if (lane == 0) st[S_PLAN_DEPTH] = skip;
+}
+
 // ------------------------------------------------------- radix sort
 
 // Digit histograms of every pass in one read of the keys.
@@ -405,31 +425,19 @@ __global__ void __launch_bounds__(256) digit_hist_kernel(const uint32_t *__restr
     if (hs[p][threadIdx.x]) atomicAdd(&hist[p * kRadixBins + threadIdx.x], hs[p][threadIdx.x]);
 }
 
-// Which passes of a sort are real.  With `dynamic`, a pass whose digit is
-// the same for every key (one histogram bin holds all n keys) is skipped and
-// the ping-pong buffer of each pass follows the number of real passes before
-// it.  Evaluated identically by every workgroup of every pass kernel.
+// Which passes of a sort are real.  With a plan word (bit p set: pass p is
+// skipped because its digit is the same for every key), the ping-pong buffer
+// of each pass follows the number of real passes before it; without one,
+// every pass is real.
 struct PassPlan {
   int skip, parity, final_parity;
 };
 
-__device__ inline PassPlan plan_pass(const uint32_t *hist, uint64_t n, int pass, int passes, int dynamic) {
-  PassPlan pp{0, pass & 1, passes & 1};
-  if (!dynamic) return pp;
-  int np = 0, before = 0;
-  for (int p = 0; p < passes; ++p) {
-    const int trivial =
-        __syncthreads_or(n > 0 && threadIdx.x < kRadixBins && hist[p * kRadixBins + threadIdx.x] == n);
-    if (!trivial) {
-      if (p < pass) ++before;
-      ++np;
-    } else if (p == pass) {
-      pp.skip = 1;
-    }
-  }
-  pp.parity = before & 1;
-  pp.final_parity = np & 1;
-  return pp;
+__device__ inline PassPlan plan_pass(const uint32_t *plan_word, int pass, int passes) {
+  if (!plan_word) return PassPlan{0, pass & 1, passes & 1};
+  const uint32_t plan = *plan_word;
+  const uint32_t real = ~plan & ((1u << passes) - 1u);
+  return PassPlan{(int)((plan >> pass) & 1u), (int)(__popc(real & ((1u << pass) - 1u)) & 1u), (int)(__popc(real) & 1u)};
 }
 
 // Pass part 1: digit counts of every chunk -> table[digit][chunk].  NW
@@ -437,25 +445,31 @@ __device__ inline PassPlan plan_pass(const uint32_t *hist, uint64_t n, int pass,
 template <int RI, int NW>
 __global__ void __launch_bounds__(64 * NW) chunk_count_kernel(const uint32_t *keys0, const uint32_t *keys1,
                                                               const uint32_t *n_dev, uint64_t n_bound, int pass,
-                                                              int passes, int dbits, int dynamic, const uint32_t *hist,
+                                                              int passes, int dbits, const uint32_t *plan_word,
                                                               uint32_t *table, uint32_t nb_bound) {
   constexpr int NT = 64 * NW;
   __shared__ uint32_t hs[kRadixBins];
-  const uint64_t n = bounded_count(n_dev, n_bound);
-  const PassPlan pp = plan_pass(hist, n, pass, passes, dynamic);
+  const PassPlan pp = plan_pass(plan_word, pass, passes);
   if (pp.skip) return;
+  const uint64_t n = bounded_count(n_dev, n_bound);
   const uint32_t c = blockIdx.x;
+  if ((uint64_t)c * (RI * NT) >= n) return;  // (the scan reads only the chunks that hold keys)
   if (threadIdx.x < kRadixBins) hs[threadIdx.x] = 0;
   __syncthreads();
   const uint32_t *kin = pp.parity ? keys1 : keys0;
   const int shift = dbits * pass;
   const uint32_t dmask = (1u << dbits) - 1u;
   const uint64_t base = (uint64_t)c * (RI * NT);
+  // all keys are loaded before the first LDS atomic (one round trip)
+  uint32_t kk[RI];
 #pragma unroll
   for (int r = 0; r < RI; ++r) {
     const uint64_t i = base + (uint64_t)r * NT + threadIdx.x;
-    if (i < n) atomicAdd(&hs[(kin[i] >> shift) & dmask], 1u);
+    kk[r] = i < n ? kin[i] : 0u;
   }
+#pragma unroll
+  for (int r = 0; r < RI; ++r)
+    if (base + (uint64_t)r * NT + threadIdx.x < n) atomicAdd(&hs[(kk[r] >> shift) & dmask], 1u);
   __syncthreads();
   if (threadIdx.x <= dmask) table[(uint64_t)threadIdx.x * nb_bound + c] = hs[threadIdx.x];
 }
@@ -469,14 +483,15 @@ __global__ void __launch_bounds__(64 * NW) chunk_count_kernel(const uint32_t *ke
 constexpr int kScanRound = 32;      // entries loaded per round: kScanRound x 256
 constexpr int kDigitScanBlock = 1024;  // threads per digit (few entries per thread)
 __global__ void __launch_bounds__(kDigitScanBlock) chunk_scan_kernel(const uint32_t *n_dev, uint64_t n_bound, int pass,
-                                                                     int passes, int dynamic, const uint32_t *hist,
-                                                                     uint32_t *table, uint32_t nb_bound, uint32_t chunk) {
+                                                                     int passes, const uint32_t *plan_word,
+                                                                     const uint32_t *hist, uint32_t *table,
+                                                                     uint32_t nb_bound, uint32_t chunk) {
   constexpr int NW = kDigitScanBlock / 64;
   __shared__ uint32_t seg[kScanRound * kScanBlock];
   __shared__ uint32_t red[NW];
-  const uint64_t n = bounded_count(n_dev, n_bound);
-  const PassPlan pp = plan_pass(hist, n, pass, passes, dynamic);
+  const PassPlan pp = plan_pass(plan_word, pass, passes);
   if (pp.skip) return;
+  const uint64_t n = bounded_count(n_dev, n_bound);
   const uint32_t nb = (uint32_t)((n + chunk - 1) / chunk);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int d = blockIdx.x;
@@ -526,14 +541,13 @@ template <int RI, int NW>
 __global__ void __launch_bounds__(64 * NW) chunk_scatter_kernel(uint32_t *keys0, uint32_t *vals0, uint32_t *keys1,
                                                                 uint32_t *vals1, const uint32_t *n_dev,
                                                                 uint64_t n_bound, int pass, int passes, int dbits,
-                                                                int dynamic, const uint32_t *hist,
-                                                                const uint32_t *table, uint32_t nb_bound, uint32_t *st,
-                                                                int cur_word) {
+                                                                const uint32_t *plan_word, const uint32_t *table,
+                                                                uint32_t nb_bound, uint32_t *st, int cur_word) {
   __shared__ uint32_t wrun[NW][kRadixBins];  // per-wave running digit counts
   __shared__ uint32_t woff[NW][kRadixBins];  // output position of each wave's first key of a digit
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint64_t n = bounded_count(n_dev, n_bound);
-  const PassPlan pp = plan_pass(hist, n, pass, passes, dynamic);
+  const PassPlan pp = plan_pass(plan_word, pass, passes);
   const uint32_t c = blockIdx.x;
   if (c == 0 && tid == 0 && cur_word >= 0) st[cur_word] = (uint32_t)pp.final_parity;
   constexpr int CH = RI * 64 * NW;
@@ -631,96 +645,80 @@ __global__ void __launch_bounds__(64 * NW) chunk_scatter_kernel(uint32_t *keys0,
   }
 }
 
-// Sorts (keys, vals) in buffers [0] by `bits` low key bits; with `dynamic`
-// the result buffer is published in st[cur_word], otherwise it is buffer
-// (passes & 1).  With `hist_ready` the digit histograms were accumulated by
-// the kernel that produced the keys.  `table` holds uint32 [256][chunks].
+// Sorts (keys, vals) in buffers [0] by `bits` low key bits, stably.  With a
+// plan word (written on the device before the sort) passes it marks are
+// skipped and the result buffer is published in st[cur_word]; otherwise it
+// is buffer (passes & 1).  With `hist_ready` the digit histograms were
+// accumulated by the kernel that produced the keys.  `table` holds uint32
+// [256][chunks].
+template <int RI>
+void radix_passes(uint32_t *keys[2], uint32_t *vals[2], uint64_t n_bound, const uint32_t *n_dev, int passes, int dbits,
+                  const uint32_t *plan_word, uint32_t *hist, uint32_t *table, uint32_t *st, int cur_word,
+                  hipStream_t s) {
+  // eight waves per chunk: each ranks 64 RI keys of the chunk
+  constexpr uint32_t chunk = RI * 64 * 8;
+  const uint32_t nb = (uint32_t)((n_bound + chunk - 1) / chunk);
+  for (int p = 0; p < passes; ++p) {
+    hipLaunchKernelGGL((chunk_count_kernel<RI, 8>), dim3(nb), dim3(512), 0, s, keys[0], keys[1], n_dev, n_bound, p,
+                       passes, dbits, plan_word, table, nb);
+    hipLaunchKernelGGL(chunk_scan_kernel, dim3(1u << dbits), dim3(kDigitScanBlock), 0, s, n_dev, n_bound, p, passes,
+                       plan_word, (const uint32_t *)hist, table, nb, chunk);
+    hipLaunchKernelGGL((chunk_scatter_kernel<RI, 8>), dim3(nb), dim3(512), 0, s, keys[0], vals[0], keys[1], vals[1],
+                       n_dev, n_bound, p, passes, dbits, plan_word, (const uint32_t *)table, nb, st, cur_word);
+  }
+}
+
+// `big`: chunks of 4096 keys (fewer workgroups, longer per-digit runs,
+// better coalesced scatters) rather than 1024 (more workgroups).
 void radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint64_t n_bound, const uint32_t *n_dev, int bits,
-                int dynamic, int hist_ready, uint32_t *hist, uint32_t *table, uint32_t *st, int cur_word,
-                hipStream_t s) {
+                const uint32_t *plan_word, int hist_ready, uint32_t *hist, uint32_t *table, uint32_t *st,
+                int cur_word, bool big, hipStream_t s) {
   const int passes = (bits + kRadixBits - 1) / kRadixBits;
   const int dbits = digit_bits_for((uint32_t)bits);
-  // large sorts take 2048-key chunks (longer per-digit runs, better
-  // coalesced scatters); smaller ones 1024 (more workgroups)
-  const bool big = n_bound >= (1ull << 21);
-  const uint32_t chunk = big ? 2 * kRadixChunk : kRadixChunk;
-  const uint32_t nb = (uint32_t)((n_bound + chunk - 1) / chunk);
-  if (nb == 0 || passes == 0) return;
+  if (n_bound == 0 || passes == 0) return;
   if (!hist_ready) {
-    unsigned hb = nb < 2048 ? nb : 2048;
+    const uint64_t hb64 = (n_bound + kRadixChunk - 1) / kRadixChunk;
+    const unsigned hb = hb64 < 2048 ? (unsigned)hb64 : 2048u;
     hipLaunchKernelGGL(digit_hist_kernel, dim3(hb), dim3(256), 0, s, keys[0], n_dev, n_bound, passes, dbits, hist);
   }
-  // eight waves per chunk: each ranks 64 RI keys of the chunk
-  for (int p = 0; p < passes; ++p) {
-    if (big)
-      hipLaunchKernelGGL((chunk_count_kernel<kRadixItems, 8>), dim3(nb), dim3(512), 0, s, keys[0], keys[1], n_dev,
-                         n_bound, p, passes, dbits, dynamic, hist, table, nb);
-    else
-      hipLaunchKernelGGL((chunk_count_kernel<kRadixItems / 2, 8>), dim3(nb), dim3(512), 0, s, keys[0], keys[1], n_dev,
-                         n_bound, p, passes, dbits, dynamic, hist, table, nb);
-    hipLaunchKernelGGL(chunk_scan_kernel, dim3(1u << dbits), dim3(kDigitScanBlock), 0, s, n_dev, n_bound, p, passes,
-                       dynamic, hist, table, nb, chunk);
-    if (big)
-      hipLaunchKernelGGL((chunk_scatter_kernel<kRadixItems, 8>), dim3(nb), dim3(512), 0, s, keys[0], vals[0], keys[1],
-                         vals[1], n_dev, n_bound, p, passes, dbits, dynamic, hist, table, nb, st, cur_word);
-    else
-      hipLaunchKernelGGL((chunk_scatter_kernel<kRadixItems / 2, 8>), dim3(nb), dim3(512), 0, s, keys[0], vals[0],
-                         keys[1], vals[1], n_dev, n_bound, p, passes, dbits, dynamic, hist, table, nb, st, cur_word);
-  }
+  if (big)
+    radix_passes<8>(keys, vals, n_bound, n_dev, passes, dbits, plan_word, hist, table, st, cur_word, s);
+  else
+    radix_passes<2>(keys, vals, n_bound, n_dev, passes, dbits, plan_word, hist, table, st, cur_word, s);
 }
 
 // -------------------------------------------------------------- emission
 
 
-// Exclusive scan of the active-tile counts of the depth-sorted visible
-// records -> pair_off[], and the pair total / overflow in the status word.
-__global__ void __launch_bounds__(kCompactBlock) pair_scan_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+// Pairs of every kEmitChunk depth-sorted visible records (the pairs one
+// emission workgroup writes): each thread sums the active-tile counts of 4
+// consecutive records.
+__global__ void __launch_bounds__(kEmitChunk / 4) chunk_pairs_kernel(const void *__restrict__ desc,
+                                                                     void *__restrict__ ws) {
   const Header &h = *header(desc);
-  uint32_t *st = status_of(ws, h);
-  const uint64_t nvis = st[S_NVIS];
-  const uint32_t nb = (uint32_t)chunks_of(nvis);
-  const uint32_t vid = virtual_block(st + S_CTR_EMIT);
-  if (vid >= nb) return;
-  const uint32_t *order = ws_ptr<uint32_t>(ws, h.ws.vis_val[st[S_DEPTH_CUR] ? 1 : 0]);
-  const uint32_t *nact = ws_ptr<uint32_t>(ws, h.ws.nact);
-  const uint64_t base = (uint64_t)vid * kScanChunk + (uint64_t)threadIdx.x * kCompactItems;
-  uint32_t cnt[kCompactItems];
-  uint32_t ts = 0;
+  const uint32_t *st = status_of(ws, h);
+  const uint32_t nvis = st[S_NVIS];
+  const uint32_t vid = blockIdx.x;
+  if ((uint64_t)vid * kEmitChunk >= nvis) return;
+  const uint32_t *order = ws_ptr<const uint32_t>(ws, h.ws.vis_val[st[S_DEPTH_CUR] ? 1 : 0]);
+  const uint32_t *nact = ws_ptr<const uint32_t>(ws, h.ws.nact);
+  const uint32_t i0 = vid * kEmitChunk + threadIdx.x * 4;
+  uint32_t rec[4], c = 0;
 #pragma unroll
-  for (int k = 0; k < kCompactItems; ++k) {
-    const uint64_t i = base + k;
-    cnt[k] = i < nvis ? nact[order[i]] : 0u;
-    ts += cnt[k];
-  }
+  for (int k = 0; k < 4; ++k) rec[k] = i0 + k < nvis ? order[i0 + k] : 0xffffffffu;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) c += rec[k] != 0xffffffffu ? nact[rec[k]] : 0u;
   uint32_t tot;
-  const uint32_t ex = block_exclusive_scan<kCompactBlock / 64>(ts, &tot);
-  __shared__ uint64_t s_prefix;
-  if (threadIdx.x < 64) {
-    const uint64_t p = lookback64(ws_ptr<uint64_t>(ws, h.ws.lb_emit), vid, tot, st + S_ERROR);
-    if (threadIdx.x == 0) s_prefix = p;
-  }
-  __syncthreads();
-  const uint64_t prefix = s_prefix;
-  const uint64_t cap = h.pair_capacity;
-  if (vid == nb - 1 && threadIdx.x == 0) {
-    const uint64_t need = prefix + tot;
-    st[S_PAIRS_LO] = (uint32_t)need;
-    st[S_PAIRS_HI] = (uint32_t)(need >> 32);
-    st[S_OVERFLOW] = need > cap ? 1u : 0u;
-    st[S_NPAIRS] = (uint32_t)(need > cap ? cap : need);
-  }
-  uint32_t *off = ws_ptr<uint32_t>(ws, h.ws.pair_off);
-  uint64_t o = prefix + ex;
-#pragma unroll
-  for (int k = 0; k < kCompactItems; ++k) {
-    const uint64_t i = base + k;
-    if (i < nvis) off[i] = (uint32_t)(o < cap ? o : cap);
-    o += cnt[k];
-  }
+  block_exclusive_scan<kEmitChunk / 256>(c, &tot);
+  if (threadIdx.x == 0) ws_ptr<uint32_t>(ws, h.ws.chunk_pairs)[vid] = tot;
 }
 
-// Pair emission: one wave per 64 consecutive depth-sorted records.  Each
-// lane loads one record (id, pair offset, rectangle, render) once; the wave
+// Pair emission: one workgroup per kEmitChunk depth-sorted records, one
+// wave per 64 of them.  The workgroup's first pair is the sum of the pair
+// counts of the earlier chunks (summed by chunk_pairs_kernel), its
+// records' offsets the workgroup's exclusive scan of their counts; the last
+// workgroup writes the pair total and the overflow flag.  Each lane loads
+// one record (id, count, rectangle, render) once; the wave
 // then emits the records' pairs 64 at a time, every lane finding the record
 // of its pair with a six-step search over the lanes' prefix offsets
 // (shuffles) and the k-th active tile of that record's rectangle from the
@@ -731,10 +729,14 @@ constexpr uint32_t kSegRows = 8;  // rectangle rows staged per record in emissio
 // 16 waves per workgroup: the workgroup's digit histogram goes to the global
 // one once per 1024 records (these few hundred words take every workgroup's
 // atomics).
-constexpr int kEmitBlock = 1024;
+constexpr int kEmitBlock = kEmitChunk;
 __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
   const Header &h = *header(desc);
-  const uint32_t *st = status_of(ws, h);
+  uint32_t *st = status_of(ws, h);
+  const uint32_t nvis = st[S_NVIS];
+  const uint32_t nb = (uint32_t)emit_chunks_of(nvis);
+  const uint32_t vid = blockIdx.x;
+  if (vid >= nb) return;  // (uniform per workgroup)
   __shared__ uint32_t hs[4][kRadixBins];
   __shared__ uint32_t s_seg[kEmitBlock / 64][64][kSegRows];  // per wave, per owner record: row bits of its rectangle
   const int passes = tile_passes(h.tile_bits);
@@ -744,24 +746,42 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict
     for (int q = 0; q < 4; ++q) hs[q][threadIdx.x] = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const uint32_t nvis = st[S_NVIS];
   const uint64_t cap = h.pair_capacity;
-  const uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  const uint64_t i = (uint64_t)vid * kEmitBlock + threadIdx.x;
   const uint64_t wbase = i - lane;
-  if (wbase < nvis) {  // uniform per wave
-    const bool own = i < nvis;
-    const uint32_t rec = own ? ws_ptr<uint32_t>(ws, h.ws.vis_val[st[S_DEPTH_CUR] ? 1 : 0])[i] : 0u;
-    const uint32_t cnt = own ? ws_ptr<uint32_t>(ws, h.ws.nact)[rec] : 0u;
-    const uint64_t off0 = ws_ptr<uint32_t>(ws, h.ws.pair_off)[wbase];  // first pair of the wave
-    // inclusive prefix of the counts across the wave
-    uint32_t inc = cnt;
+  const bool own = i < nvis;
+  const uint32_t rec = own ? ws_ptr<uint32_t>(ws, h.ws.vis_val[st[S_DEPTH_CUR] ? 1 : 0])[i] : 0u;
+  const uint32_t cnt = own ? ws_ptr<uint32_t>(ws, h.ws.nact)[rec] : 0u;
+  // pairs of the earlier chunks, and the chunk's exclusive scan of counts
+  __shared__ uint64_t s_pre[kEmitBlock / 64];
+  {
+    const uint32_t *cp = ws_ptr<const uint32_t>(ws, h.ws.chunk_pairs);
+    uint64_t pre = 0;
+    for (uint32_t j = threadIdx.x; j < vid; j += kEmitBlock) pre += cp[j];
+    pre = wave_sum64(pre);
+    if (lane == 0) s_pre[threadIdx.x >> 6] = pre;
+  }
+  uint32_t chunk_total;
+  const uint32_t ex = block_exclusive_scan<kEmitBlock / 64>(cnt, &chunk_total);  // (its barriers publish s_pre)
+  uint64_t prefix = 0;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t t = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += t;
-    }
-    const uint32_t excl = inc - cnt;
-    const uint32_t total = __shfl(inc, 63, 64);
+  for (int w = 0; w < kEmitBlock / 64; ++w) prefix += s_pre[w];
+  if (vid == nb - 1 && threadIdx.x == 0) {
+    const uint64_t need = prefix + chunk_total;
+    st[S_PAIRS_LO] = (uint32_t)need;
+    st[S_PAIRS_HI] = (uint32_t)(need >> 32);
+    st[S_OVERFLOW] = need > cap ? 1u : 0u;
+    st[S_NPAIRS] = (uint32_t)(need > cap ? cap : need);
+  }
+  if (own) {
+    const uint64_t o = prefix + ex;
+    ws_ptr<uint32_t>(ws, h.ws.pair_off)[i] = (uint32_t)(o < cap ? o : cap);
+  }
+  if (wbase < nvis) {  // uniform per wave
+    const uint32_t ex0 = __shfl(ex, 0, 64);
+    const uint64_t off0 = prefix + ex0;  // first pair of the wave
+    const uint32_t excl = ex - ex0;      // this lane's first pair in the wave
+    const uint32_t total = __shfl(ex + cnt, 63, 64) - ex0;
     // this lane's record geometry
     uint32_t x0 = 0, y0 = 0, x1 = 0, y1 = 0, toff = 0, txn = 1, amoff = 0;
     if (own) {
@@ -985,24 +1005,29 @@ void launch_depth_sort(const void *d_desc, const Header &h, void *ws, hipStream_
   if (h.n_records == 0) return;
   uint32_t *st = ws_ptr<uint32_t>(ws, h.ws.status);
   hipLaunchKernelGGL(compact_kernel, dim3((unsigned)chunks_of(h.n_records)), dim3(kCompactBlock), 0, s, d_desc, ws);
+  hipLaunchKernelGGL(depth_plan_kernel, dim3(1), dim3(64), 0, s, d_desc, ws);
   uint32_t *keys[2] = {ws_ptr<uint32_t>(ws, h.ws.vis_key[0]), ws_ptr<uint32_t>(ws, h.ws.vis_key[1])};
   uint32_t *vals[2] = {ws_ptr<uint32_t>(ws, h.ws.vis_val[0]), ws_ptr<uint32_t>(ws, h.ws.vis_val[1])};
-  radix_sort(keys, vals, h.n_records, st + S_NVIS, 32, 1, 1, ws_ptr<uint32_t>(ws, h.ws.dhist),
-             ws_ptr<uint32_t>(ws, h.ws.rtable), st, S_DEPTH_CUR, s);
+  // (visible records rarely fill 4096-key chunks on every workgroup of the
+  // chip: the depth sort takes 1024)
+  radix_sort(keys, vals, h.n_records, st + S_NVIS, 32, st + S_PLAN_DEPTH, 1, ws_ptr<uint32_t>(ws, h.ws.dhist),
+             ws_ptr<uint32_t>(ws, h.ws.rtable), st, S_DEPTH_CUR, false, s);
 }
 
 void launch_emit(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
   if (h.n_records == 0) return;
-  hipLaunchKernelGGL(pair_scan_kernel, dim3((unsigned)chunks_of(h.n_records)), dim3(kCompactBlock), 0, s, d_desc, ws);
-  hipLaunchKernelGGL(emit_kernel, dim3(blocks_for(h.n_records, kEmitBlock)), dim3(kEmitBlock), 0, s, d_desc, ws);
+  const dim3 grid((unsigned)emit_chunks_of(h.n_records));
+  hipLaunchKernelGGL(chunk_pairs_kernel, grid, dim3(kEmitChunk / 4), 0, s, d_desc, ws);
+  hipLaunchKernelGGL(emit_kernel, grid, dim3(kEmitBlock), 0, s, d_desc, ws);
 }
 
 void launch_tile_sort(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
   uint32_t *st = ws_ptr<uint32_t>(ws, h.ws.status);
   uint32_t *keys[2] = {ws_ptr<uint32_t>(ws, h.ws.pair_key[0]), ws_ptr<uint32_t>(ws, h.ws.pair_key[1])};
   uint32_t *vals[2] = {ws_ptr<uint32_t>(ws, h.ws.pair_val[0]), ws_ptr<uint32_t>(ws, h.ws.pair_val[1])};
-  radix_sort(keys, vals, h.pair_capacity, st + S_NPAIRS, (int)h.tile_bits, 0, 1, ws_ptr<uint32_t>(ws, h.ws.thist),
-             ws_ptr<uint32_t>(ws, h.ws.rtable), st, -1, s);
+  radix_sort(keys, vals, h.pair_capacity, st + S_NPAIRS, (int)h.tile_bits, nullptr, 1,
+             ws_ptr<uint32_t>(ws, h.ws.thist), ws_ptr<uint32_t>(ws, h.ws.rtable), st, -1,
+             h.pair_capacity >= (1ull << 19), s);
   if (h.cfg.deterministic)
     hipLaunchKernelGGL(det_fixup_kernel, dim3(blocks_for(h.pair_capacity)), dim3(256), 0, s, d_desc, ws);
   const uint32_t *sorted_tiles = ws_ptr<uint32_t>(ws, h.ws.sorted_key);
@@ -1014,8 +1039,8 @@ void launch_tile_sort(const void *d_desc, const Header &h, void *ws, hipStream_t
     hipLaunchKernelGGL(queue_key_kernel, dim3(blocks_for(h.n_tiles)), dim3(256), 0, s, d_desc, ws);
     uint32_t *qk[2] = {ws_ptr<uint32_t>(ws, h.ws.qkey[0]), ws_ptr<uint32_t>(ws, h.ws.qkey[1])};
     uint32_t *qv[2] = {ws_ptr<uint32_t>(ws, h.ws.qval0), ws_ptr<uint32_t>(ws, h.ws.queue)};
-    radix_sort(qk, qv, h.n_tiles, nullptr, kRadixBits, 0, 0, ws_ptr<uint32_t>(ws, h.ws.qhist),
-               ws_ptr<uint32_t>(ws, h.ws.rtable), st, -1, s);
+    radix_sort(qk, qv, h.n_tiles, nullptr, kRadixBits, nullptr, 0, ws_ptr<uint32_t>(ws, h.ws.qhist),
+               ws_ptr<uint32_t>(ws, h.ws.rtable), st, -1, false, s);
   }
 }
 

@@ -100,10 +100,11 @@ struct Layout {
   // status words, single-pass scan look-back words, digit histograms,
   // radix look-back words and the queue buckets.
   uint64_t zero_begin;
-  uint64_t lb_compact, lb_emit;  // uint64 [blocks] look-back words of the scans
+  uint64_t lb_compact;  // uint64 [blocks] look-back words of the compaction scan
   uint64_t dhist, thist;         // uint32 [4][256] digit histograms (depth, tile)
   uint64_t qhist;                // histogram of the queue sort
   uint64_t zero_end;
+  uint64_t chunk_pairs;          // uint32 [records / kEmitChunk] pairs of each chunk of depth-sorted records
   uint64_t rtable;               // uint32 [256][chunks] radix chunk offsets
   uint64_t qkey[2], qval0;       // queue sort buffers (the result lands in `queue`)
   uint64_t stats;
@@ -118,6 +119,7 @@ enum StatusField {
   S_QUEUE_FWD = 4, S_QUEUE_BWD = 5, S_NPAIRS = 6, S_NQUEUE = 7,
   S_DEPTH_CUR = 8,   // which vis buffer holds the depth-sorted records
   S_ERROR = 9,       // non-zero if a look-back wait gave up (results invalid)
+  S_PLAN_DEPTH = 10, // bit p set: depth-sort pass p is skipped (one digit for every key)
   S_CTR_COMPACT = 16, S_CTR_EMIT = 17, S_CTR_QUEUE = 18,
   S_CTR_DEPTH = 24,  // 4 counters, one per depth-sort pass
   S_CTR_TILE = 28,   // 4 counters, one per tile-sort pass
@@ -234,6 +236,10 @@ void launch_load_stats(const void *d_desc, const Header &h, const void *ws, int 
 // Blocks of kScanChunk elements covering n.
 __host__ __device__ inline uint64_t chunks_of(uint64_t n) { return (n + kScanChunk - 1) / kScanChunk; }
 __host__ __device__ inline uint64_t radix_chunks_of(uint64_t n) { return (n + kRadixChunk - 1) / kRadixChunk; }
+// Depth-sorted visible records are emitted in chunks of kEmitChunk, one
+// workgroup each.
+constexpr int kEmitChunk = 1024;
+__host__ __device__ inline uint64_t emit_chunks_of(uint64_t n) { return (n + kEmitChunk - 1) / kEmitChunk; }
 constexpr int kDepthPasses = 4;
 __host__ __device__ inline int tile_passes(uint32_t tile_bits) { return (int)((tile_bits + kRadixBits - 1) / kRadixBits); }
 // Digit width of a sort over `bits` key bits: the passes of at most

@@ -151,17 +151,22 @@ def _emit_reference_inputs(b, sc, tile):
     return grids, offs, np.concatenate(active)
 
 
-@pytest.mark.parametrize("n,seed,wide", [(300, 1, False), (40_000, 2, False), (3_000, 3, True), (8_000, 4, True)])
-def test_binning_bit_exact_on_synthetic_rects(n, seed, wide):
+@pytest.mark.parametrize("n,seed,wide,det", [(300, 1, False, False), (40_000, 2, False, False),
+                                             (3_000, 3, True, False), (8_000, 4, True, False),
+                                             (8_000, 4, True, True), (60_000, 5, True, False),
+                                             (60_000, 6, True, True)])
+def test_binning_bit_exact_on_synthetic_rects(n, seed, wide, det):
     """wide: rectangles up to 48 x 14 tiles, so emission also takes its path
     for rectangles too large to stage (more than 8 rows or 32 columns).  The
     pair capacities (64 n or 700 n) select both radix chunk sizes (1024, and
-    2048 from two million keys)."""
-    print(f"[case] binning n={n} wide={wide}", flush=True)
+    2048 from two million keys); the 60000-record cases hold tile lists of
+    several thousand pairs.  det: the deterministic configuration, whose tile
+    sort carries emission indices."""
+    print(f"[case] binning n={n} wide={wide} det={det}", flush=True)
     tile = 16
     W, H = (1100, 300) if wide else (300, 200)
     sc = scenes.small_scene(50 + seed, n=n, width=W, height=H, sh_degree=0, n_views=2)
-    b = device_scene(sc, RenderConfig(tile=tile), pair_capacity=(700 if wide else 64) * n)
+    b = device_scene(sc, RenderConfig(tile=tile, deterministic=det), pair_capacity=(700 if wide else 64) * n)
     rng = np.random.default_rng(seed)
     nrec = int(b.info.n_records)
     grids, offs, active = _emit_reference_inputs(b, sc, tile)
