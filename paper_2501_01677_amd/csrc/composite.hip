@@ -584,6 +584,7 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
     }
     GS = Tf * (gch[0] * h.cfg.bg[0] + gch[1] * h.cfg.bg[1] + gch[2] * h.cfg.bg[2]);
   }
+  const float gaTf = ga * Tf;  // g_alpha T_final
   // the tile's largest last-blended index (with MM from a wave maximum by
   // lane exchanges and one LDS atomic per wave; the lane-exchange form keeps
   // per-lane atomics, whose registers it cannot spare)
@@ -664,7 +665,7 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
             Gf = fmaf(gch[c], f[c], Gf);
             v[6 + c] = w * gch[c];
           }
-          const float dLda = Tp * Gf + (ga * Tf - GS) * iom + gcount;
+          const float dLda = Tp * Gf + (gaTf - GS) * iom + gcount;
           GS = contrib ? fmaf(w, Gf, GS) : GS;
           Tr = contrib ? Tp : Tr;
           // alpha = o G with G = exp(-q/2): dalpha/do = G = alpha / o,
@@ -689,58 +690,57 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
             add_or_store<DET>(dst + (uint64_t)(DET ? bstart + cur.k : sid[cur.k]) * STRIDE + which, tot);
         }
       } else {
-        // back to front; the next entry and its coefficients are loaded while
-        // this one is evaluated
-        Entry e = list[len > 0 ? len - 1 : 0];
-        float4 abc = sb[4 * NT + (len > 0 ? e.k : 0)];
-        for (int t = len - 1; t >= 0; --t) {
-          const Entry en = list[t > 0 ? t - 1 : 0];
-          const float4 abcn = sb[4 * NT + en.k];
+        // Back to front.  A lane that does not blend the fragment takes alpha
+        // = 0: its weight w and its dL/dq entry vanish, its transmittance
+        // and suffix sum are unchanged (T / (1 - 0) = T and GS + 0 Gf = GS
+        // exactly), so the recurrences need no per-value selects.
+        auto step = [&](const Entry &e, const float4 &abc) {
           const int32_t idx = (int32_t)(bstart + e.k);
-          // Every lane evaluates the fragment (the wave executes it anyway when
-          // any lane contributes); lanes that do not contribute get zero weight.
           const float ex = lane_exponent(e, abc, g.L);
           const bool contrib = idx <= last && ex >= l2min;
-          if (__ballot(contrib) != 0ull) {
-            const float4 r0 = sb[e.k], r1 = sb[NT + e.k], r2 = sb[2 * NT + e.k], r3 = sb[3 * NT + e.k];
-            const uint32_t rid = sid[e.k];
-            const float raw = __builtin_amdgcn_exp2f(ex);
-            const float a = __builtin_amdgcn_fmed3f(raw, 0.f, amax);  // min(raw, amax), raw >= 0
-            const float f[7] = {r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
-            const float iom = __builtin_amdgcn_rcpf(1.f - a);  // 1 / (1 - alpha), alpha <= 0.99
-            const float Tp = Tr * iom;
-            const float w = contrib ? a * Tp : 0.f;
-            // dL/dalpha = sum_c g_c (T f_c - S_c / (1 - alpha)) + g_alpha T_final / (1 - alpha)
-            //            + g_count
-            float Gf = 0.f;
+          if (__ballot(contrib) == 0ull) return;
+          const float4 r0 = sb[e.k], r1 = sb[NT + e.k], r2 = sb[2 * NT + e.k], r3 = sb[3 * NT + e.k];
+          const uint32_t rid = sid[e.k];
+          const float raw = __builtin_amdgcn_exp2f(ex);
+          const float a = contrib ? __builtin_amdgcn_fmed3f(raw, 0.f, amax) : 0.f;  // min(raw, amax), raw >= 0
+          const float f[7] = {r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
+          const float iom = __builtin_amdgcn_rcpf(1.f - a);  // 1 / (1 - alpha), alpha <= 0.99
+          const float Tp = Tr * iom;
+          const float w = a * Tp;
+          // dL/dalpha = sum_c g_c (T f_c - S_c / (1 - alpha)) + g_alpha T_final / (1 - alpha)
+          //            + g_count
+          float Gf = 0.f;
 #pragma unroll
-            for (int c = 0; c < 7; ++c) Gf = fmaf(gch[c], f[c], Gf);
-            const float dLda = Tp * Gf + (ga * Tf - GS) * iom + gcount;
-            GS = contrib ? fmaf(w, Gf, GS) : GS;
-            Tr = contrib ? Tp : Tr;
-            // alpha = o G with G = exp(-q/2): dalpha/do = G = alpha / o,
-            // dalpha/dq = -alpha / 2 (zero on the clamped side of alpha_max)
-            const float gate = (contrib && raw <= amax) ? dLda : 0.f;
-            // buffer w and dL/dq; the record's sums over the wave's pixels
-            // are formed on the matrix cores once 8 records are buffered
-            // (granule (lane >> 2) of row nb lands at (lane >> 2) ^ nb)
-            const int col = lane ^ (nb << 2);
-            acc.a[nb][col] = w;
-            acc.a[8 + nb][col] = -0.5f * a * gate;
-            const bool mine = lane == nb;
-            isid = mine ? (DET ? bstart + e.k : rid) : isid;
-            icx = mine ? r0.x : icx;
-            icy = mine ? r0.y : icy;
-            if (++nb == 8) {
-              nact += 8;
-              __builtin_amdgcn_wave_barrier();
-              flush_records<STRIDE, DET>(acc, 8, bf, fields, isid, icx, icy, bcx, bcy, dst);
-              __builtin_amdgcn_wave_barrier();
-              nb = 0;
-            }
+          for (int c = 0; c < 7; ++c) Gf = fmaf(gch[c], f[c], Gf);
+          const float dLda = Tp * Gf + (gaTf - GS) * iom + gcount;
+          GS = fmaf(w, Gf, GS);
+          Tr = Tp;
+          // alpha = o G with G = exp(-q/2): dalpha/do = G = alpha / o,
+          // dalpha/dq = -alpha / 2 (zero on the clamped side of alpha_max)
+          const float gate = raw <= amax ? dLda : 0.f;
+          // buffer w and dL/dq; the record's sums over the wave's pixels
+          // are formed on the matrix cores once 8 records are buffered
+          // (granule (lane >> 2) of row nb lands at (lane >> 2) ^ nb)
+          const int col = lane ^ (nb << 2);
+          acc.a[nb][col] = w;
+          acc.a[8 + nb][col] = -0.5f * a * gate;
+          const bool mine = lane == nb;
+          isid = mine ? (DET ? bstart + e.k : rid) : isid;
+          icx = mine ? r0.x : icx;
+          icy = mine ? r0.y : icy;
+          if (++nb == 8) {
+            nact += 8;
+            __builtin_amdgcn_wave_barrier();
+            flush_records<STRIDE, DET>(acc, 8, bf, fields, isid, icx, icy, bcx, bcy, dst);
+            __builtin_amdgcn_wave_barrier();
+            nb = 0;
           }
-          e = en;
-          abc = abcn;
+        };
+        // (the entry's loads are not prefetched: the other resident waves
+        // cover their latency, and a prefetch costs register copies)
+        for (int t = len - 1; t >= 0; --t) {
+          const Entry e = list[t];
+          step(e, sb[4 * NT + e.k]);
         }
       }
     }
