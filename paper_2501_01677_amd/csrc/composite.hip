@@ -55,8 +55,15 @@ constexpr int bwd_batch_of() { return MM && T == 16 ? 96 : (T == 8 ? 64 : 128); 
 
 struct Entry {   // one record in one wave's list of the backward pass (16 bytes)
   float F, D, E;
-  uint32_t k;    // slot of the record in the batch
+  uint32_t koff; // slot of the record in the batch * 16 (a byte offset into a field plane)
 };
+
+// Field plane j of the staged batch at an entry's slot (planes 0..3: the raw
+// record, plane 4: the exponent coefficients A, B, C and the record id).
+template <int NT>
+__device__ __forceinline__ float4 plane_at(const float4 *sb, uint32_t koff, int j) {
+  return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(sb) + koff + j * NT * 16);
+}
 
 // One record in one wave's list of the forward pass (32 bytes, two 16-byte
 // LDS reads): all six exponent coefficients, so evaluating it needs no
@@ -80,7 +87,7 @@ __device__ __forceinline__ void set_entry(Entry &e, const float4 *sb, int NT, in
   e.F = F;
   e.D = D;
   e.E = E;
-  e.k = (uint32_t)k;
+  e.koff = (uint32_t)k * 16u;
 }
 
 __device__ __forceinline__ void set_entry(FwdEntry &e, const float4 *sb, int NT, int k, float F, float D, float E) {
@@ -220,11 +227,11 @@ __device__ __forceinline__ void tile_geom(const void *desc, const Header &h, uin
   g.L.ly = (float)ly;
 }
 
-// Stages batch records [j0, j1) into LDS: the raw 64-byte records and the
-// per-record exponent coefficients (A, B, C).
+// Stages batch records [j0, j1) into LDS: the raw 64-byte records and (ABC)
+// the per-record exponent coefficients (A, B, C) with the record id.
 template <int NT, bool ABC>
 __device__ __forceinline__ void stage_batch(const float4 *__restrict__ rec4, const uint32_t *__restrict__ vals,
-                                            uint32_t j0, uint32_t j1, float4 *sb, uint32_t *sid) {
+                                            uint32_t j0, uint32_t j1, float4 *sb) {
   const uint32_t j = j0 + threadIdx.x;
   if (threadIdx.x < NT && j < j1) {
     const uint32_t rid = vals[j];
@@ -236,8 +243,8 @@ __device__ __forceinline__ void stage_batch(const float4 *__restrict__ rec4, con
     sb[2 * NT + threadIdx.x] = r2;
     sb[3 * NT + threadIdx.x] = r3;
     if constexpr (ABC)
-      sb[4 * NT + threadIdx.x] = make_float4(-kHalfLog2e * r0.z, -2.f * kHalfLog2e * r0.w, -kHalfLog2e * r1.x, 0.f);
-    if (sid) sid[threadIdx.x] = rid;
+      sb[4 * NT + threadIdx.x] =
+          make_float4(-kHalfLog2e * r0.z, -2.f * kHalfLog2e * r0.w, -kHalfLog2e * r1.x, __uint_as_float(rid));
   }
 }
 
@@ -267,7 +274,7 @@ __device__ void forward_tile(const void *__restrict__ desc, const Header &h, voi
   for (uint32_t b = rg.x; b < rg.y; b += NT) {
     if (__syncthreads_count(!done) == 0) break;
     const uint32_t b1 = min(rg.y, b + NT);
-    stage_batch<NT, false>(rec4, vals, b, b1, srec, nullptr);
+    stage_batch<NT, false>(rec4, vals, b, b1, srec);
     __syncthreads();
     if (__ballot(!done) == 0ull) continue;
     const int len = build_list<NT>(srec, (int)(b1 - b), g.ox, g.oy, l2min, list);
@@ -407,12 +414,14 @@ __device__ __forceinline__ void add_or_store(float *p, float v) {
 
 // Per-wave LDS of the backward pass's per-record reduction.  For up to 8
 // contributing records the wave buffers every pixel's colour weight
-// w = alpha T (rows 0..7) and dL/dq (rows 8..15); columns are the wave's 64
-// pixels, stored in 4-float granules XOR-swizzled by (row & 7) so that the
-// matrix-layout reads of a flush spread over the banks.  Record slot b's id
-// and 2D mean are kept in registers of lane b.
+// w = alpha T (rows 0..7) and alpha times the dL/dalpha gate, i.e.
+// -2 dL/dq (rows 8..15); columns are the wave's 64 pixels, stored in 4-float
+// granules XOR-swizzled by (row & 7) so that the matrix-layout reads of a
+// flush spread over the banks.  info[b] holds buffered record b's id (bits)
+// and 2D mean.
 struct WaveAcc {
   float a[16][64];
+  float4 info[8];
 };
 
 // Feature slot n of a pixel in the per-record reduction: the 7 output
@@ -433,18 +442,19 @@ __device__ __forceinline__ float feature_slot(int n, float g, float x, float y) 
 // lane group kk being 16t + 4kk + j; bf holds the F operands).  Lane
 // (j, kk) receives slots 4kk..4kk+3 of buffered row j: for rows 0..7 (colour
 // weights of record j) slots 0..6 are its 7 feature gradients; for rows
-// 8..15 (dL/dq of record j - 8) slots 8..13 are the raw moments R_1, R_x,
-// R_y, R_xy, R_xx, R_yy about the block centre, which are moved to the
-// record's centre with its offset (cx, cy) from the block centre:
+// 8..15 (alpha gate = -2 dL/dq of record j - 8) slots 8..13 are the raw
+// moments R_1, R_x, R_y, R_xy, R_xx, R_yy about the block centre, which are
+// moved to the record's centre with its offset (cx, cy) from the block
+// centre:
 //   sum u dx = R_x - cx R_1,  sum u dx dy = R_xy - cx R_y - cy R_x + cx cy R_1,
 //   sum u dx^2 = R_xx - 2 cx R_x + cx^2 R_1  (lane group 3 takes R_1 from
-// group 2), and sum(alpha gate) = -2 R_1.  Every valid nonzero value of the
-// first nb records is then added to its slot (dst + id * STRIDE), or with
-// DET stored there (the slot belongs to this wave and record alone).
+// group 2), and scaled by -1/2 (exact) to moments of dL/dq, except
+// sum(alpha gate) = R_1 itself.  Every valid nonzero value of the first nb
+// records is then added to its slot (dst + id * STRIDE), or with DET stored
+// there (the slot belongs to this wave and record alone).
 template <int STRIDE, bool DET>
 __device__ __forceinline__ void flush_records(WaveAcc &acc, int nb, const float (&bf)[16], uint32_t fields,
-                                              uint32_t isid, float icx, float icy, float bcx, float bcy,
-                                              float *__restrict__ dst) {
+                                              float bcx, float bcy, float *__restrict__ dst) {
   const int lane = threadIdx.x & 63, j = lane & 15, kk = lane >> 4;
   floatx4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -456,7 +466,8 @@ __device__ __forceinline__ void flush_records(WaveAcc &acc, int nb, const float 
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * t + 3], av.w, c, 0, 0, 0);
   }
   const int b = j & 7;  // buffered record
-  const float cx = __shfl(icx, b, 64) - bcx, cy = __shfl(icy, b, 64) - bcy;
+  const float4 ib = acc.info[b];
+  const float cx = ib.y - bcx, cy = ib.z - bcy;
   // lane group 3 needs R_1 (slot 8, held in c[0] by group 2)
   const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(c[0]), __float_as_uint(c[0]), false, false);
   const float r1 = __uint_as_float(sw[0]);
@@ -469,6 +480,10 @@ __device__ __forceinline__ void flush_records(WaveAcc &acc, int nb, const float 
   o[1] = c[1] - cx2 * c[0] + cy3 * fmaf(cy, r1, -2.f * c[3]);
   o[2] = c[2] - cy2 * c[0];
   o[3] = c[3] - cx2 * fmaf(-cy, c[0], c[2]) - cy2 * c[1];
+  // (group 2's o[0] is -2 R_1 here: the common factor brings it back)
+  const float sc = kk >= 2 ? -0.5f : 1.f;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) o[r] *= sc;
   // The sums go out record-major: staged as 8 rows of 16 fields in the
   // buffer (free once read), then each atomic instruction covers 4 records,
   // so that a record's 13 additions fall in one instruction and cache line.
@@ -480,7 +495,7 @@ __device__ __forceinline__ void flush_records(WaveAcc &acc, int nb, const float 
   __builtin_amdgcn_wave_barrier();
   const int rb = lane >> 4, f = lane & 15;
   const float v0 = stage[rb * 16 + f], v1 = stage[(4 + rb) * 16 + f];
-  const uint32_t id0 = __shfl(isid, rb, 64), id1 = __shfl(isid, 4 + rb, 64);
+  const uint32_t id0 = __float_as_uint(acc.info[rb].x), id1 = __float_as_uint(acc.info[4 + rb].x);
   if (f < 13) {
     if (rb < nb && v0 != 0.f) add_or_store<DET>(dst + (uint64_t)id0 * STRIDE + f, v0);
     if (4 + rb < nb && v1 != 0.f) add_or_store<DET>(dst + (uint64_t)id1 * STRIDE + f, v1);
@@ -508,7 +523,7 @@ __device__ __forceinline__ uint32_t slot_fields(int kk) {
 // index, wave); det_reduce_kernel adds them per record in a fixed order.
 template <int T, bool MM, bool DET>
 __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, const Header &h, void *__restrict__ ws, uint32_t tile,
-                              float4 *sb, uint32_t *sid, Entry (*lists)[bwd_batch_of<T, MM>()],
+                              float4 *sb, Entry (*lists)[bwd_batch_of<T, MM>()],
                               WaveAcc *accs, int *smax, const uint32_t *__restrict__ vals) {
   constexpr int NT = bwd_batch_of<T, MM>();
   constexpr int WPT = (T / 8) * (T / 8);
@@ -628,13 +643,11 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
   const float bcx = g.ox + 3.5f, bcy = g.oy + 3.5f;  // block centre
   const uint32_t fields = slot_fields(lane >> 4);
   int nb = 0;  // buffered records (uniform)
-  uint32_t isid = 0u;  // lane b < nb: id and 2D mean of buffered record b
-  float icx = 0.f, icy = 0.f;
   for (int64_t bend = end; bend > (int64_t)rg.x; bend -= NT) {
     const uint32_t bstart = (uint32_t)max((int64_t)rg.x, bend - NT);
     const int cnt = (int)((uint32_t)bend - bstart);
     __syncthreads();
-    stage_batch<NT, true>(rec4, vals, bstart, (uint32_t)bend, sb, sid);
+    stage_batch<NT, true>(rec4, vals, bstart, (uint32_t)bend, sb);
     __syncthreads();
     if (MM ? wlast >= (int32_t)bstart : __ballot(last >= (int32_t)bstart) != 0ull) {
       const int len = build_list<NT>(sb, MM ? min(cnt, wlast - (int32_t)bstart + 1) : cnt, g.ox, g.oy, l2min, list);
@@ -642,16 +655,19 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
       if constexpr (!MM) {
         for (int t = len - 1; t >= 0; --t) {
           const Entry cur = list[t];
-          const int32_t idx = (int32_t)(bstart + cur.k);
+          const uint32_t ck = cur.koff >> 4;
+          const int32_t idx = (int32_t)(bstart + ck);
+          const float4 abc = plane_at<NT>(sb, cur.koff, 4);
           // Every lane evaluates the fragment (the wave executes it anyway when
           // any lane contributes); lanes that do not contribute get zero weight.
-          const float ex = lane_exponent(cur, sb[4 * NT + cur.k], g.L);
+          const float ex = lane_exponent(cur, abc, g.L);
           const bool contrib = idx <= last && ex >= l2min;
           if (__ballot(contrib) == 0ull) continue;
           ++nact;
           const float raw = __builtin_amdgcn_exp2f(ex);
           const float a = __builtin_amdgcn_fmed3f(raw, 0.f, amax);  // min(raw, amax), raw >= 0
-          const float4 r0 = sb[cur.k], r1 = sb[NT + cur.k], r2 = sb[2 * NT + cur.k], r3 = sb[3 * NT + cur.k];
+          const float4 r0 = plane_at<NT>(sb, cur.koff, 0), r1 = plane_at<NT>(sb, cur.koff, 1);
+          const float4 r2 = plane_at<NT>(sb, cur.koff, 2), r3 = plane_at<NT>(sb, cur.koff, 3);
           const float f[7] = {r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
           const float iom = __builtin_amdgcn_rcpf(1.f - a);  // 1 / (1 - alpha), alpha <= 0.99
           const float Tp = Tr * iom;
@@ -687,20 +703,22 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
           const float tot = wave_reduce16(v);
           const int which = (lane >> 2) & 15;
           if ((lane & 3) == 0 && which < 13 && tot != 0.f)
-            add_or_store<DET>(dst + (uint64_t)(DET ? bstart + cur.k : sid[cur.k]) * STRIDE + which, tot);
+            add_or_store<DET>(dst + (uint64_t)(DET ? bstart + ck : __float_as_uint(abc.w)) * STRIDE + which, tot);
         }
       } else {
         // Back to front.  A lane that does not blend the fragment takes alpha
         // = 0: its weight w and its dL/dq entry vanish, its transmittance
         // and suffix sum are unchanged (T / (1 - 0) = T and GS + 0 Gf = GS
         // exactly), so the recurrences need no per-value selects.
+        // the pixel's last blended index as a byte offset into the batch
+        // planes (below 0: none of the batch)
+        const int32_t lastoff = min(max(last - (int32_t)bstart, -1), NT) * 16;
         auto step = [&](const Entry &e, const float4 &abc) {
-          const int32_t idx = (int32_t)(bstart + e.k);
           const float ex = lane_exponent(e, abc, g.L);
-          const bool contrib = idx <= last && ex >= l2min;
+          const bool contrib = (int32_t)e.koff <= lastoff && ex >= l2min;
           if (__ballot(contrib) == 0ull) return;
-          const float4 r0 = sb[e.k], r1 = sb[NT + e.k], r2 = sb[2 * NT + e.k], r3 = sb[3 * NT + e.k];
-          const uint32_t rid = sid[e.k];
+          const float4 r0 = plane_at<NT>(sb, e.koff, 0), r1 = plane_at<NT>(sb, e.koff, 1);
+          const float4 r2 = plane_at<NT>(sb, e.koff, 2), r3 = plane_at<NT>(sb, e.koff, 3);
           const float raw = __builtin_amdgcn_exp2f(ex);
           const float a = contrib ? __builtin_amdgcn_fmed3f(raw, 0.f, amax) : 0.f;  // min(raw, amax), raw >= 0
           const float f[7] = {r1.z, r1.w, r2.x, r2.y, r2.z, r2.w, r3.x};
@@ -723,15 +741,14 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
           // (granule (lane >> 2) of row nb lands at (lane >> 2) ^ nb)
           const int col = lane ^ (nb << 2);
           acc.a[nb][col] = w;
-          acc.a[8 + nb][col] = -0.5f * a * gate;
-          const bool mine = lane == nb;
-          isid = mine ? (DET ? bstart + e.k : rid) : isid;
-          icx = mine ? r0.x : icx;
-          icy = mine ? r0.y : icy;
+          acc.a[8 + nb][col] = a * gate;
+          if (lane == 0)
+            acc.info[nb] = make_float4(__uint_as_float(DET ? bstart + (e.koff >> 4) : __float_as_uint(abc.w)), r0.x,
+                                       r0.y, 0.f);
           if (++nb == 8) {
             nact += 8;
             __builtin_amdgcn_wave_barrier();
-            flush_records<STRIDE, DET>(acc, 8, bf, fields, isid, icx, icy, bcx, bcy, dst);
+            flush_records<STRIDE, DET>(acc, 8, bf, fields, bcx, bcy, dst);
             __builtin_amdgcn_wave_barrier();
             nb = 0;
           }
@@ -740,7 +757,7 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
         // cover their latency, and a prefetch costs register copies)
         for (int t = len - 1; t >= 0; --t) {
           const Entry e = list[t];
-          step(e, sb[4 * NT + e.k]);
+          step(e, plane_at<NT>(sb, e.koff, 4));
         }
       }
     }
@@ -748,7 +765,7 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
   if (MM && nb > 0) {
     nact += (uint32_t)nb;
     __builtin_amdgcn_wave_barrier();
-    flush_records<STRIDE, DET>(acc, nb, bf, fields, isid, icx, icy, bcx, bcy, dst);
+    flush_records<STRIDE, DET>(acc, nb, bf, fields, bcx, bcy, dst);
   }
   if ((threadIdx.x & 63) == 0) {
     work[1] = nev;
@@ -815,7 +832,6 @@ __global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(MM ? 
                                                          const uint32_t *__restrict__ vals) {
   constexpr int NT = bwd_batch_of<T, MM>();
   __shared__ float4 sb[5 * NT];  // field-major staged batch (see forward_kernel)
-  __shared__ uint32_t sid[NT];
   __shared__ Entry lists[T * T / 64][NT];
   __shared__ std::conditional_t<MM, WaveAcc, uint32_t> accs_[T * T / 64];
   WaveAcc *accs = reinterpret_cast<WaveAcc *>(accs_);
@@ -823,7 +839,7 @@ __global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(MM ? 
   __shared__ uint32_t s_item;
   const Header &h = *header(desc);
   if (!h.cfg.persistent) {
-    backward_tile<T, MM, DET>(desc, h, ws, blockIdx.x, sb, sid, lists, accs, &smax, vals);
+    backward_tile<T, MM, DET>(desc, h, ws, blockIdx.x, sb, lists, accs, &smax, vals);
     return;
   }
   uint32_t *ctr = ws_ptr<uint32_t>(ws, h.ws.status) + S_QUEUE_BWD;
@@ -839,7 +855,7 @@ __global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(MM ? 
     const uint32_t stop = min(ntiles, base + chunk);
     for (uint32_t it = base; it < stop; ++it) {
       __syncthreads();
-      backward_tile<T, MM, DET>(desc, h, ws, queue[it], sb, sid, lists, accs, &smax, vals);
+      backward_tile<T, MM, DET>(desc, h, ws, queue[it], sb, lists, accs, &smax, vals);
     }
   }
 }
