@@ -155,9 +155,9 @@ Layout make_layout(const pgsag_config &cfg, const Sizes &z, uint64_t cap, int n_
   L.zero_begin = off;
   const uint64_t status_at = take(S_WORDS * 4);
   L.lb_compact = take((chunks_of(z.n_records) + 1) * 8);
-  L.dhist = take(4 * 256 * 4);
-  L.thist = take(4 * 256 * 4);
-  L.qhist = take(256 * 4);
+  L.dhist = take(kHistCopies * kHistStride * 4);
+  L.thist = take(kHistCopies * kHistStride * 4);
+  L.qhist = take(kHistCopies * kHistStride * 4);
   L.zero_end = off;
   L.chunk_pairs = take(emit_chunks_of(z.n_records) * 4);
   {

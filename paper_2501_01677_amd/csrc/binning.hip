@@ -379,7 +379,7 @@ __global__ void __launch_bounds__(kCompactBlock) compact_kernel(const void *__re
     }
   }
   __syncthreads();
-  uint32_t *dh = ws_ptr<uint32_t>(ws, h.ws.dhist);
+  uint32_t *dh = ws_ptr<uint32_t>(ws, h.ws.dhist) + (vid % kHistCopies) * kHistStride;
   if (threadIdx.x < kRadixBins)
     for (int p = 0; p < kDepthPasses; ++p)
       if (hs[p][threadIdx.x]) atomicAdd(&dh[p * kRadixBins + threadIdx.x], hs[p][threadIdx.x]);
@@ -399,7 +399,12 @@ __global__ void __launch_bounds__(64) depth_plan_kernel(const void *__restrict__
   for (int p = 0; p < kDepthPasses; ++p) {
     bool one = false;
 #pragma unroll
-    for (int q = 0; q < kRadixBins / 64; ++q) one |= dh[p * kRadixBins + q * 64 + lane] == n;
+    for (int q = 0; q < kRadixBins / 64; ++q) {
+      uint32_t v = 0;
+#pragma unroll
+      for (int c = 0; c < kHistCopies; ++c) v += dh[c * kHistStride + p * kRadixBins + q * 64 + lane];
+      one |= v == n;
+    }
     if (n > 0 && __ballot(one)) skip |= 1u << p;
   }
   if (lane == 0) st[S_PLAN_DEPTH] = skip;
@@ -422,7 +427,8 @@ __global__ void __launch_bounds__(256) digit_hist_kernel(const uint32_t *__restr
   }
   __syncthreads();
   for (int p = 0; p < passes; ++p)
-    if (hs[p][threadIdx.x]) atomicAdd(&hist[p * kRadixBins + threadIdx.x], hs[p][threadIdx.x]);
+    if (hs[p][threadIdx.x])
+      atomicAdd(&hist[(blockIdx.x % kHistCopies) * kHistStride + p * kRadixBins + threadIdx.x], hs[p][threadIdx.x]);
 }
 
 // Which passes of a sort are real.  With a plan word (bit p set: pass p is
@@ -496,8 +502,11 @@ __global__ void __launch_bounds__(kDigitScanBlock) chunk_scan_kernel(const uint3
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int d = blockIdx.x;
   const uint32_t *h = hist + pass * kRadixBins;
-  // digit base: sum of the totals of the digits below d
-  uint32_t b = tid < d ? h[tid] : 0u;
+  // digit base: sum of the totals of the digits below d (over the copies)
+  uint32_t b = 0;
+  if (tid < d)
+#pragma unroll
+    for (int c = 0; c < kHistCopies; ++c) b += h[c * kHistStride + tid];
   for (int o = 32; o > 0; o >>= 1) b += __shfl_xor(b, o, 64);
   if (lane == 0) red[wave] = b;
   __syncthreads();
@@ -911,7 +920,7 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict
     }
   }
   __syncthreads();
-  uint32_t *th = ws_ptr<uint32_t>(ws, h.ws.thist);
+  uint32_t *th = ws_ptr<uint32_t>(ws, h.ws.thist) + (vid % kHistCopies) * kHistStride;
   if (threadIdx.x < kRadixBins)
     for (int q = 0; q < passes; ++q)
       if (hs[q][threadIdx.x]) atomicAdd(&th[q * kRadixBins + threadIdx.x], hs[q][threadIdx.x]);

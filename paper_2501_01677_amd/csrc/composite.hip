@@ -456,15 +456,24 @@ template <int STRIDE, bool DET>
 __device__ __forceinline__ void flush_records(WaveAcc &acc, int nb, const float (&bf)[16], uint32_t fields,
                                               float bcx, float bcy, float *__restrict__ dst) {
   const int lane = threadIdx.x & 63, j = lane & 15, kk = lane >> 4;
-  floatx4 c = {0.f, 0.f, 0.f, 0.f};
+  // two independent accumulation chains (pixel halves), interleaved, so
+  // that each MFMA issues while the previous one of the other chain is in
+  // flight
+  floatx4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const float4 av = *reinterpret_cast<const float4 *>(&acc.a[j][((4 * t + kk) ^ (j & 7)) << 2]);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * t + 0], av.x, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * t + 1], av.y, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * t + 2], av.z, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * t + 3], av.w, c, 0, 0, 0);
+  for (int t = 0; t < 2; ++t) {
+    const float4 a0 = *reinterpret_cast<const float4 *>(&acc.a[j][((4 * t + kk) ^ (j & 7)) << 2]);
+    const float4 a1 = *reinterpret_cast<const float4 *>(&acc.a[j][((4 * (t + 2) + kk) ^ (j & 7)) << 2]);
+    c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * t + 0], a0.x, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * (t + 2) + 0], a1.x, c1, 0, 0, 0);
+    c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * t + 1], a0.y, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * (t + 2) + 1], a1.y, c1, 0, 0, 0);
+    c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * t + 2], a0.z, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * (t + 2) + 2], a1.z, c1, 0, 0, 0);
+    c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * t + 3], a0.w, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[4 * (t + 2) + 3], a1.w, c1, 0, 0, 0);
   }
+  const floatx4 c = c0 + c1;
   const int b = j & 7;  // buffered record
   const float4 ib = acc.info[b];
   const float cx = ib.y - bcx, cy = ib.z - bcy;

@@ -20,6 +20,11 @@ constexpr int kRadixItems = 4;            // keys per thread in a radix pass
 constexpr int kRadixChunk = kRadixItems * kScanBlock;  // 1024 keys per radix chunk
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
+// Digit histograms are kept in kHistCopies copies of uint32 [4][256], each
+// producing workgroup adding into copy (workgroup & 7): fewer same-word
+// atomics per copy; the consumers add the copies.
+constexpr int kHistCopies = 8;
+constexpr int kHistStride = 4 * kRadixBins;
 
 // Record layout (floats): projected Gaussian for one (render, Gaussian).
 enum RecField {
@@ -101,8 +106,8 @@ struct Layout {
   // radix look-back words and the queue buckets.
   uint64_t zero_begin;
   uint64_t lb_compact;  // uint64 [blocks] look-back words of the compaction scan
-  uint64_t dhist, thist;         // uint32 [4][256] digit histograms (depth, tile)
-  uint64_t qhist;                // histogram of the queue sort
+  uint64_t dhist, thist;         // uint32 [kHistCopies][4][256] digit histograms (depth, tile)
+  uint64_t qhist;                // the same for the queue sort
   uint64_t zero_end;
   uint64_t chunk_pairs;          // uint32 [records / kEmitChunk] pairs of each chunk of depth-sorted records
   uint64_t rtable;               // uint32 [256][chunks] radix chunk offsets
