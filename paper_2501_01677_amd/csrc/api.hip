@@ -492,7 +492,9 @@ int run_backward(const Header *h, const void *dev_desc, void *workspace, const A
                  void **events) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   StageTimer tm{events, s};
-  launch_fill_u32(ws_ptr<uint32_t>(workspace, h->ws.g2), 0u, h->n_records * kG2, s);
+  // float atomics add into the 2D-gradient slots; the deterministic
+  // reduction stores every slot the backward projection reads
+  if (!h->cfg.deterministic) launch_fill_u32(ws_ptr<uint32_t>(workspace, h->ws.g2), 0u, h->n_records * kG2, s);
   if (h->cfg.persistent) launch_fill_u32(ws_ptr<uint32_t>(workspace, h->ws.status) + S_QUEUE_BWD, 0u, 1, s);
   if (h->cfg.deterministic) launch_det_clear(dev_desc, *h, workspace, s);
   tm.begin(PGSAG_STAGE_BACKWARD_COMPOSITE);

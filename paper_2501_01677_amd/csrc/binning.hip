@@ -38,10 +38,20 @@ __device__ inline uint32_t *status_of(void *ws, const Header &h) {
   return ws_ptr<uint32_t>(ws, h.ws.status);
 }
 
+// n words of p set to value: 16-byte stores over the 16-byte aligned body,
+// single words before and after it.
 __global__ void fill_u32_kernel(uint32_t *p, uint32_t value, uint64_t n) {
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) p[i] = value;
+  const uint64_t lead = (uint64_t)((16u - ((uintptr_t)p & 15u)) & 15u) / 4u;
+  const uint64_t head = lead < n ? lead : n;
+  const uint64_t nv = (n - head) / 4;
+  if (tid < head) p[tid] = value;
+  uint4 *q = reinterpret_cast<uint4 *>(p + head);
+  const uint4 v = make_uint4(value, value, value, value);
+  for (uint64_t i = tid; i < nv; i += stride) q[i] = v;
+  const uint64_t done = head + nv * 4;
+  if (tid < n - done) p[done + tid] = value;
 }
 
 // -------------------------------------------------------------- scans
@@ -996,7 +1006,8 @@ inline unsigned blocks_for(uint64_t n, unsigned bs = 256) { return (unsigned)((n
 
 void launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t s) {
   if (n == 0) return;
-  uint64_t blocks = (n + 255) / 256;
+  uint64_t blocks = (n / 4 + 255) / 256;
+  if (blocks < 1) blocks = 1;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, value, n);
 }

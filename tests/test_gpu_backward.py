@@ -220,9 +220,9 @@ def test_deterministic_backward_bit_reproducible_and_matches_oracle(tile, reduce
 @pytest.mark.parametrize("reduce", [0, 1])
 def test_deterministic_backward_on_the_small_parity_workload(reduce):
     """10k Gaussians, 256x256, 16x16 tiles: repeated backward passes are
-    bit-identical in the deterministic mode and agree with the atomic mode
-    to its addition-order rounding; how many atomic-mode elements change
-    between runs is reported."""
+    bit-identical in the deterministic mode, and every repeated atomic-mode
+    pass agrees with them to its addition-order rounding; how many
+    atomic-mode elements change between runs is reported."""
     print(f"[case] deterministic backward config 1 reduce={reduce}", flush=True)
     sc = DET_SCENES["config1"]()
     rd = sc.renders[0]
@@ -241,9 +241,11 @@ def test_deterministic_backward_on_the_small_parity_workload(reduce):
         assert torch.equal(o, res[True][0])
     changed = sum(int((o != res[False][0]).sum()) for o in res[False][1:])
     print(f"[info] atomic mode: {changed} gradient elements changed between runs", flush=True)
-    a, d = res[False][0], res[True][0]
+    d = res[True][0]
     scale = float(d.abs().max())
-    torch.testing.assert_close(a, d, rtol=1e-5, atol=1e-6 * scale)
+    # every atomic-mode pass (each one starts from cleared 2D-gradient slots)
+    for a in res[False]:
+        torch.testing.assert_close(a, d, rtol=1e-5, atol=1e-6 * scale)
 
 
 def test_empty_mask_gives_zero_gradients():
