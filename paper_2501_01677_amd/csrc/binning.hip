@@ -7,12 +7,15 @@
 //                 of active tiles (one workgroup per tile row), so a support
 //                 rectangle's active-tile count is two loads per tile row
 //   compact       stable compaction of records with >= 1 active tile into
-//                 (depth key, record) lists
-//   radix sort    stable LSD sort of that list by the FP32 depth key; a pass
-//                 whose digit is the same for every key is skipped
-//   pair scan     exclusive scan of active-tile counts in depth order
-//   emit          (global tile, record) pairs, depth order preserved, one
-//                 wave per 64 records emitting 64 pairs at a time
+//                 (depth key, record) lists, with the depth digit histograms
+//   depth plan    one wave decides which depth passes are real (a pass whose
+//                 digit is the same for every key is skipped) -> plan word
+//   radix sort    stable LSD sort of that list by the FP32 depth key
+//   chunk pairs   pair totals of every 1024 depth-sorted records
+//   emit          per 1024 records: the first pair offset from the earlier
+//                 chunks' totals and a workgroup scan of the counts, then
+//                 (global tile, record) pairs in depth order, one wave per
+//                 64 records emitting 64 pairs at a time
 //   radix sort    stable LSD sort of the pairs by tile id -> every tile's list
 //                 is in (depth, record) order
 //   ranges        per tile [start, end) into the sorted pairs
@@ -20,15 +23,16 @@
 //                 log2(length), tiles without masked pixels last, by a stable
 //                 radix pass (tile order kept inside a bucket)
 //
-// The compaction and pair scans are single pass: each workgroup takes the
-// next chunk index from an atomic counter (so every chunk before it belongs
-// to a workgroup that is already running), publishes its chunk total, and
-// looks back 64 predecessors at a time until it meets an inclusive prefix
-// (decoupled look-back).  Waits only ever point backwards, to workgroups
-// that are resident and do not wait on later ones, so they end; a bounded
-// spin sets an error word instead of waiting forever.  Radix passes use
+// The compaction is single pass: each workgroup takes the next chunk index
+// from an atomic counter (so every chunk before it belongs to a workgroup
+// that is already running), publishes its chunk total, and looks back 64
+// predecessors at a time until it meets an inclusive prefix (decoupled
+// look-back).  Waits only ever point backwards, to workgroups that are
+// resident and do not wait on later ones, so they end; a bounded spin sets
+// an error word instead of waiting forever.  Radix passes use
 // reduce-then-scan (chunk digit counts, a per-digit scan, a scatter) with
-// digit histograms accumulated by the kernel that produced the keys.
+// digit histograms accumulated by the kernel that produced the keys, in
+// kHistCopies copies (fewer same-word atomics).
 #include "internal.h"
 
 namespace pgsag {

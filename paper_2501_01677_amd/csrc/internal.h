@@ -125,9 +125,7 @@ enum StatusField {
   S_DEPTH_CUR = 8,   // which vis buffer holds the depth-sorted records
   S_ERROR = 9,       // non-zero if a look-back wait gave up (results invalid)
   S_PLAN_DEPTH = 10, // bit p set: depth-sort pass p is skipped (one digit for every key)
-  S_CTR_COMPACT = 16, S_CTR_EMIT = 17, S_CTR_QUEUE = 18,
-  S_CTR_DEPTH = 24,  // 4 counters, one per depth-sort pass
-  S_CTR_TILE = 28,   // 4 counters, one per tile-sort pass
+  S_CTR_COMPACT = 16,  // chunk tickets of the compaction's look-back scan
   S_WORDS = 64
 };
 

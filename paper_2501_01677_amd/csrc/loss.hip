@@ -469,10 +469,11 @@ void launch_loss(const void *d_desc, const void *h_desc, void *ws, const pgsag_l
   const Header &h = *header(h_desc);
   const DevRender *rd = renders_of(h_desc);
   double *acc = ws_ptr<double>(ws, h.ws.loss);
-  const int n = h.n_renders * kAcc;
-  hipLaunchKernelGGL(fill_f64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, acc, n);
+  // the accumulators and the partial sums (laid out one after the other)
+  // cleared by one launch
   const int np = h.n_renders * kSlots * kPart;
-  hipLaunchKernelGGL(fill_f64_kernel, dim3((np + 255) / 256), dim3(256), 0, s, ws_ptr<double>(ws, h.ws.loss_part), np);
+  const int n = (int)((h.ws.loss_part - h.ws.loss) / sizeof(double)) + np;
+  hipLaunchKernelGGL(fill_f64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, acc, n);
   uint64_t max_tiles = 1;
   for (int r = 0; r < h.n_renders; ++r) {
     const uint64_t t = (uint64_t)rd[r].tiles_x * rd[r].tiles_y;
