@@ -749,6 +749,8 @@ __global__ void __launch_bounds__(kEmitChunk / 4) chunk_pairs_kernel(const void 
 // spread of rectangle sizes.  The digit histograms of the emitted tile ids
 // (for the tile sort) are accumulated on the way.
 constexpr uint32_t kSegRows = 8;  // rectangle rows staged per record in emission
+constexpr uint32_t kRowLaneBits = 12;       // widest row (active tiles) of the row-lane emission
+constexpr uint32_t kRowLaneMinPairs = 256;  // fewest pairs of a wave in the row-lane emission
 // 16 waves per workgroup: the workgroup's digit histogram goes to the global
 // one once per 1024 records (these few hundred words take every workgroup's
 // atomics).
@@ -830,6 +832,7 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict
     // in LDS instead of issuing dependent global loads.
     uint32_t *seg = s_seg[threadIdx.x >> 6][lane];
     const bool staged = own && y1 - y0 <= kSegRows && x1 - x0 <= 32;
+    uint32_t widest = 0;  // most active tiles in one row of this lane's rectangle
     if (staged) {
       const uint32_t wpr = (txn + 31) / 32;
       const uint32_t wd = x1 - x0;
@@ -853,83 +856,133 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict
         if (r < nr) {
           const uint64_t two = (uint64_t)lo[r] | ((uint64_t)hi[r] << 32);
           seg[r] = (uint32_t)(two >> sh) & (wd == 32 ? ~0u : ((1u << wd) - 1u));
+          widest = max(widest, (uint32_t)__popc(seg[r]));
         }
     }
     const uint64_t staged_mask = __ballot(staged);
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t j = 0; j < total; j += 64) {
-      const uint32_t t = j + lane;
-      const bool live = t < total && off0 + t < cap;
-      // owner: the last lane whose exclusive prefix is <= t
-      int owner = 0;
+    if (total >= kRowLaneMinPairs && __ballot(own && cnt > 0 && (!staged || widest > kRowLaneBits)) == 0ull) {
+      // The wave emits at least kRowLaneMinPairs pairs, every record with
+      // pairs is staged and no row has more than kRowLaneBits active tiles:
+      // one lane per (record, row) of 8 records at a time.  The lane takes its row's staged active-tile bits and
+      // writes that row's pairs in column order after the pairs of the
+      // record's earlier rows, so each record's pairs keep their row-major
+      // order; no per-pair search.  (Its eight rounds cost about as much as
+      // four rounds of the balanced form, and wider rows would leave most
+      // lanes idle while a few walk their bits: such waves take the
+      // balanced form.)
+      const uint32_t nrows = own && cnt > 0 ? y1 - y0 : 0u;
+      const uint32_t tile0 = toff + y0 * txn + x0;  // the rectangle's first tile
+      const int gl = lane >> 3, row = lane & 7;
+      for (int rb = 0; rb < 64; rb += 8) {
+        const int src = rb + gl;
+        const uint32_t rn = __shfl(nrows, src, 64);
+        if (__ballot(rn > 0u) == 0ull) continue;
+        const uint32_t bits0 = (uint32_t)row < rn ? s_seg[threadIdx.x >> 6][src][row] : 0u;
+        const uint32_t c = __popc(bits0);
+        // the record's pairs in its rows above this one
+        uint32_t inc = c;
 #pragma unroll
-      for (int step = 32; step > 0; step >>= 1) {
-        const int cand = owner + step;
-        const uint32_t ce = __shfl(excl, cand, 64);
-        if (ce <= t) owner = cand;
-      }
-      uint32_t k = t - __shfl(excl, owner, 64);
-      const uint32_t orec = __shfl(rec, owner, 64);
-      const uint32_t ox0 = __shfl(x0, owner, 64), oy0 = __shfl(y0, owner, 64);
-      const uint32_t ox1 = __shfl(x1, owner, 64), oy1 = __shfl(y1, owner, 64);
-      const uint32_t otoff = __shfl(toff, owner, 64), otxn = __shfl(txn, owner, 64);
-      const uint32_t oam = __shfl(amoff, owner, 64);
-      if (live) {
-        uint32_t gt = otoff + oy0 * otxn + ox0;  // (the k-th active tile always exists)
-        if ((staged_mask >> owner) & 1ull) {
-          const uint32_t *os = s_seg[threadIdx.x >> 6][owner];
-          for (uint32_t r = 0; r < oy1 - oy0; ++r) {
-            uint32_t bits = os[r];
-            const uint32_t c = __popc(bits);
-            if (k < c) {
-              // position of the k-th set bit: halving search on popcounts
-              uint32_t pos = 0;
-#pragma unroll
-              for (uint32_t wdt = 16; wdt > 0; wdt >>= 1) {
-                const uint32_t lo = __popc(bits & ((1u << wdt) - 1u));
-                if (k >= lo) {
-                  k -= lo;
-                  bits >>= wdt;
-                  pos += wdt;
-                }
-              }
-              gt = otoff + (oy0 + r) * otxn + ox0 + pos;
-              break;
+        for (int o = 1; o < 8; o <<= 1) {
+          const uint32_t t = __shfl_up(inc, o, 8);
+          if (row >= o) inc += t;
+        }
+        uint64_t e = off0 + __shfl(excl, src, 64) + (inc - c);
+        const uint32_t rowtile = __shfl(tile0, src, 64) + (uint32_t)row * __shfl(txn, src, 64);
+        const uint32_t orec = __shfl(rec, src, 64);
+        uint32_t bits = bits0;
+        while (bits) {
+          const uint32_t b = (uint32_t)__ffs(bits) - 1u;
+          bits &= bits - 1u;
+          if (e < cap) {
+            const uint32_t gt = rowtile + b;
+            key_out[e] = gt;
+            if (det) {
+              val_out[e] = (uint32_t)e;
+              prec[e] = orec;
+            } else {
+              val_out[e] = orec;
             }
-            k -= c;
+            for (int q = 0; q < passes; ++q) atomicAdd(&hs[q][(gt >> (tdb * q)) & tmask], 1u);
           }
-        } else {
-          const uint32_t wpr = (otxn + 31) / 32;
-          const uint32_t *am = am_all + oam;
-          bool found = false;
-          for (uint32_t ty = oy0; ty < oy1 && !found; ++ty) {
-            for (uint32_t w = ox0 / 32; w * 32 < ox1; ++w) {
-              uint32_t bits = am[ty * wpr + w];
-              const uint32_t lo32 = w * 32;
-              if (ox0 > lo32) bits &= ~0u << (ox0 - lo32);
-              if (ox1 < lo32 + 32) bits &= (1u << (ox1 - lo32)) - 1u;
+          ++e;
+        }
+      }
+    } else {
+      for (uint32_t j = 0; j < total; j += 64) {
+        const uint32_t t = j + lane;
+        const bool live = t < total && off0 + t < cap;
+        // owner: the last lane whose exclusive prefix is <= t
+        int owner = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+          const int cand = owner + step;
+          const uint32_t ce = __shfl(excl, cand, 64);
+          if (ce <= t) owner = cand;
+        }
+        uint32_t k = t - __shfl(excl, owner, 64);
+        const uint32_t orec = __shfl(rec, owner, 64);
+        const uint32_t ox0 = __shfl(x0, owner, 64), oy0 = __shfl(y0, owner, 64);
+        const uint32_t ox1 = __shfl(x1, owner, 64), oy1 = __shfl(y1, owner, 64);
+        const uint32_t otoff = __shfl(toff, owner, 64), otxn = __shfl(txn, owner, 64);
+        const uint32_t oam = __shfl(amoff, owner, 64);
+        if (live) {
+          uint32_t gt = otoff + oy0 * otxn + ox0;  // (the k-th active tile always exists)
+          if ((staged_mask >> owner) & 1ull) {
+            const uint32_t *os = s_seg[threadIdx.x >> 6][owner];
+            for (uint32_t r = 0; r < oy1 - oy0; ++r) {
+              uint32_t bits = os[r];
               const uint32_t c = __popc(bits);
               if (k < c) {
-                for (uint32_t q = 0; q < k; ++q) bits &= bits - 1;
-                gt = otoff + ty * otxn + lo32 + (__ffs(bits) - 1);
-                found = true;
+                // position of the k-th set bit: halving search on popcounts
+                uint32_t pos = 0;
+#pragma unroll
+                for (uint32_t wdt = 16; wdt > 0; wdt >>= 1) {
+                  const uint32_t lo = __popc(bits & ((1u << wdt) - 1u));
+                  if (k >= lo) {
+                    k -= lo;
+                    bits >>= wdt;
+                    pos += wdt;
+                  }
+                }
+                gt = otoff + (oy0 + r) * otxn + ox0 + pos;
                 break;
               }
               k -= c;
             }
+          } else {
+            const uint32_t wpr = (otxn + 31) / 32;
+            const uint32_t *am = am_all + oam;
+            bool found = false;
+            for (uint32_t ty = oy0; ty < oy1 && !found; ++ty) {
+              for (uint32_t w = ox0 / 32; w * 32 < ox1; ++w) {
+                uint32_t bits = am[ty * wpr + w];
+                const uint32_t lo32 = w * 32;
+                if (ox0 > lo32) bits &= ~0u << (ox0 - lo32);
+                if (ox1 < lo32 + 32) bits &= (1u << (ox1 - lo32)) - 1u;
+                const uint32_t c = __popc(bits);
+                if (k < c) {
+                  for (uint32_t q = 0; q < k; ++q) bits &= bits - 1;
+                  gt = otoff + ty * otxn + lo32 + (__ffs(bits) - 1);
+                  found = true;
+                  break;
+                }
+                k -= c;
+              }
+            }
           }
+          const uint64_t e = off0 + t;
+          key_out[e] = gt;
+          if (det) {
+            // the tile sort carries the emission index; the record follows
+            // it through pair_rec (det_fixup_kernel)
+            val_out[e] = (uint32_t)e;
+            prec[e] = orec;
+          } else {
+            val_out[e] = orec;
+          }
+          for (int q = 0; q < passes; ++q) atomicAdd(&hs[q][(gt >> (tdb * q)) & tmask], 1u);
         }
-        const uint64_t e = off0 + t;
-        key_out[e] = gt;
-        if (det) {
-          // the tile sort carries the emission index; the record follows
-          // it through pair_rec (det_fixup_kernel)
-          val_out[e] = (uint32_t)e;
-          prec[e] = orec;
-        } else {
-          val_out[e] = orec;
-        }
-        for (int q = 0; q < passes; ++q) atomicAdd(&hs[q][(gt >> (tdb * q)) & tmask], 1u);
       }
     }
   }
