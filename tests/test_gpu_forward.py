@@ -151,22 +151,31 @@ def _emit_reference_inputs(b, sc, tile):
     return grids, offs, np.concatenate(active)
 
 
-@pytest.mark.parametrize("n,seed,wide,det", [(300, 1, False, False), (40_000, 2, False, False),
-                                             (3_000, 3, True, False), (8_000, 4, True, False),
-                                             (8_000, 4, True, True), (60_000, 5, True, False),
-                                             (60_000, 6, True, True)])
-def test_binning_bit_exact_on_synthetic_rects(n, seed, wide, det):
-    """wide: rectangles up to 48 x 14 tiles, so emission also takes its path
-    for rectangles too large to stage (more than 8 rows or 32 columns).  The
-    pair capacities (64 n or 700 n) select both radix chunk sizes (1024, and
-    2048 from two million keys); the 60000-record cases hold tile lists of
-    several thousand pairs.  det: the deterministic configuration, whose tile
-    sort carries emission indices."""
-    print(f"[case] binning n={n} wide={wide} det={det}", flush=True)
+# rectangle kinds: (image size, largest width - 1 and height - 1 in tiles, pair capacity per record)
+RECT_KINDS = {"small": ((300, 200), (4, 3), 64), "mid": ((600, 400), (11, 8), 200),
+              "wide": ((1100, 300), (48, 14), 700)}
+
+
+@pytest.mark.parametrize("n,seed,kind,det", [(300, 1, "small", False), (40_000, 2, "small", False),
+                                             (20_000, 7, "mid", False), (20_000, 8, "mid", True),
+                                             (3_000, 3, "wide", False), (8_000, 4, "wide", False),
+                                             (8_000, 4, "wide", True), (60_000, 5, "wide", False),
+                                             (60_000, 6, "wide", True)])
+def test_binning_bit_exact_on_synthetic_rects(n, seed, kind, det):
+    """small: waves of fewer than 256 pairs (emission's balanced form).  mid:
+    rectangles up to 8 rows x 11 columns, so waves of several hundred pairs
+    whose rows all hold at most 12 active tiles take the row-lane form.
+    wide: rectangles up to 48 x 14 tiles, so emission also takes its path for
+    rectangles too large to stage (more than 8 rows or 32 columns).  The pair
+    capacities select both radix chunk sizes (1024 keys, and 4096 from 2^19
+    keys); the 60000-record cases hold tile lists of several thousand pairs.
+    det: the deterministic configuration, whose tile sort carries emission
+    indices."""
+    print(f"[case] binning n={n} kind={kind} det={det}", flush=True)
     tile = 16
-    W, H = (1100, 300) if wide else (300, 200)
+    (W, H), (mw, mh), cap = RECT_KINDS[kind]
     sc = scenes.small_scene(50 + seed, n=n, width=W, height=H, sh_degree=0, n_views=2)
-    b = device_scene(sc, RenderConfig(tile=tile, deterministic=det), pair_capacity=(700 if wide else 64) * n)
+    b = device_scene(sc, RenderConfig(tile=tile, deterministic=det), pair_capacity=cap * n)
     rng = np.random.default_rng(seed)
     nrec = int(b.info.n_records)
     grids, offs, active = _emit_reference_inputs(b, sc, tile)
@@ -177,8 +186,8 @@ def test_binning_bit_exact_on_synthetic_rects(n, seed, wide, det):
         k = int(m.sum())
         x0 = rng.integers(0, tx, k)
         y0 = rng.integers(0, ty, k)
-        x1 = np.minimum(tx, x0 + rng.integers(0, 49 if wide else 5, k))
-        y1 = np.minimum(ty, y0 + rng.integers(0, 15 if wide else 4, k))
+        x1 = np.minimum(tx, x0 + rng.integers(0, mw + 1, k))
+        y1 = np.minimum(ty, y0 + rng.integers(0, mh + 1, k))
         rects[m] = np.stack([x0, y0, x1, y1], 1)
     depth = rng.integers(0, 2000, nrec).astype(np.uint32) * np.uint32(1 << 20)  # ties and high bits
     depth[::7] = rng.integers(0, 2 ** 32, len(depth[::7]), dtype=np.uint64).astype(np.uint32)
