@@ -322,6 +322,41 @@ def cpu_baseline(scene, sample=4096, seed=7):
                        f"FP64 forward + gradient, full per-Gaussian preprocessing included; {dt:.1f} s")
 
 
+def cpu_baseline_config1(seed=7, brute_sample=8192):
+    """The FP64 oracle on config 1 (10k Gaussians, 256x256, full frame),
+    forward plus gradient, in its two modes: culled (each pixel's Gaussians
+    from the exact-support grid) over the whole frame, and brute force (every
+    Gaussian at every pixel) on a fixed sample of pixels."""
+    import torch
+    import scenes
+    from oracle import OracleConfig
+    from oracle import composite as oc
+    torch.set_num_threads(os.cpu_count() or 1)
+    cfg = OracleConfig()
+    sc = scenes.config1()
+    rd = sc.renders[0]
+    gs = sc.sets[rd.set_index]
+    H, W = rd.camera.height, rd.camera.width
+    g = scenes.grad_outputs(seed + 1000, rd, scale={"depth": 0.05})
+    out = {}
+    rng = np.random.default_rng(seed)
+    for mode, npx in (("culled", H * W), ("brute", brute_sample)):
+        idx = np.arange(H * W) if npx == H * W else np.sort(rng.choice(H * W, npx, replace=False))
+        pix = np.stack([idx // W, idx % W], 1)
+        sel = np.zeros((H, W), bool)
+        sel[pix[:, 0], pix[:, 1]] = True
+        gg = {k: (v * sel).astype(np.float32) for k, v in g.items()}
+        t0 = time.perf_counter()
+        oc.render(gs, rd.camera, rd.mask, cfg, pixels=pix, mode=mode)
+        oc.render_grad(gs, rd.camera, rd.mask, cfg, gg, pixels=pix, mode=mode)
+        dt = time.perf_counter() - t0
+        out[mode] = dict(value=round(npx / dt / 1e6, 6), unit="Mpixels/s", pixels=int(npx), seconds=round(dt, 2))
+    out.update(cores=torch.get_num_threads(), kind="oracle",
+               workload="config 1: 10k Gaussians SH0, 256x256 full frame, FP64 forward + gradient; brute force on "
+                        f"{brute_sample} sampled pixels (seed {seed})")
+    return out
+
+
 def _graph_time(bb, torch, steps):
     g = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
@@ -720,6 +755,8 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(sc)
+        log("[bench] CPU oracle on config 1 (culled and brute force)")
+        line["cpu_baseline_config1"] = cpu_baseline_config1()
     print(json.dumps(line), flush=True)
 
 
