@@ -762,11 +762,14 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
             nb = 0;
           }
         };
-        // (the entry's loads are not prefetched: the other resident waves
-        // cover their latency, and a prefetch costs register copies)
+        // the next entry is read while this one is evaluated (its
+        // coefficients, read through the entry's slot, are not: a second
+        // prefetched register set would spill)
+        Entry e = list[len > 0 ? len - 1 : 0];
         for (int t = len - 1; t >= 0; --t) {
-          const Entry e = list[t];
+          const Entry en = list[t > 0 ? t - 1 : 0];
           step(e, plane_at<NT>(sb, e.koff, 4));
+          e = en;
         }
       }
     }
