@@ -160,6 +160,7 @@ Layout make_layout(const pgsag_config &cfg, const Sizes &z, uint64_t cap, int n_
   L.qhist = take(kHistCopies * kHistStride * 4);
   L.zero_end = off;
   L.chunk_pairs = take(emit_chunks_of(z.n_records) * 4);
+  L.chunk_off = take(emit_chunks_of(z.n_records) * 8);
   {
     uint64_t big = z.n_records > cap ? z.n_records : cap;
     big = big > z.n_tiles ? big : z.n_tiles;

@@ -736,6 +736,36 @@ __global__ void __launch_bounds__(kEmitChunk / 4) chunk_pairs_kernel(const void 
   if (threadIdx.x == 0) ws_ptr<uint32_t>(ws, h.ws.chunk_pairs)[vid] = tot;
 }
 
+// Exclusive prefix (64-bit) of the per-chunk pair totals in one workgroup,
+// for batches of more than kEmitDirectChunks emission chunks (below that,
+// each emission workgroup adds the earlier chunks' totals itself).
+constexpr uint64_t kEmitDirectChunks = 2048;
+__global__ void __launch_bounds__(1024) chunk_prefix_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+  const Header &h = *header(desc);
+  const uint32_t *st = status_of(ws, h);
+  const uint32_t nb = (uint32_t)emit_chunks_of(st[S_NVIS]);
+  const uint32_t *cp = ws_ptr<const uint32_t>(ws, h.ws.chunk_pairs);
+  uint64_t *co = ws_ptr<uint64_t>(ws, h.ws.chunk_off);
+  const uint32_t per = (nb + 1023u) / 1024u;
+  const uint32_t a = threadIdx.x * per, b = min(nb, a + per);
+  uint64_t sum = 0;
+  for (uint32_t j = a; j < b; ++j) sum += cp[j];
+  __shared__ uint64_t sc[1024];
+  sc[threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint64_t v = (int)threadIdx.x >= o ? sc[threadIdx.x - o] : 0ull;
+    __syncthreads();
+    sc[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint64_t run = sc[threadIdx.x] - sum;
+  for (uint32_t j = a; j < b; ++j) {
+    co[j] = run;
+    run += cp[j];
+  }
+}
+
 // Pair emission: one workgroup per kEmitChunk depth-sorted records, one
 // wave per 64 of them.  The workgroup's first pair is the sum of the pair
 // counts of the earlier chunks (summed by chunk_pairs_kernel), its
@@ -755,7 +785,8 @@ constexpr uint32_t kRowLaneMinPairs = 256;  // fewest pairs of a wave in the row
 // one once per 1024 records (these few hundred words take every workgroup's
 // atomics).
 constexpr int kEmitBlock = kEmitChunk;
-__global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict__ desc, void *__restrict__ ws) {
+__global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict__ desc, void *__restrict__ ws,
+                                                          int scanned) {
   const Header &h = *header(desc);
   uint32_t *st = status_of(ws, h);
   const uint32_t nvis = st[S_NVIS];
@@ -777,9 +808,10 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict
   const bool own = i < nvis;
   const uint32_t rec = own ? ws_ptr<uint32_t>(ws, h.ws.vis_val[st[S_DEPTH_CUR] ? 1 : 0])[i] : 0u;
   const uint32_t cnt = own ? ws_ptr<uint32_t>(ws, h.ws.nact)[rec] : 0u;
-  // pairs of the earlier chunks, and the chunk's exclusive scan of counts
+  // pairs of the earlier chunks (scanned: their prefix, written by
+  // chunk_prefix_kernel), and the chunk's exclusive scan of counts
   __shared__ uint64_t s_pre[kEmitBlock / 64];
-  {
+  if (!scanned) {
     const uint32_t *cp = ws_ptr<const uint32_t>(ws, h.ws.chunk_pairs);
     uint64_t pre = 0;
     for (uint32_t j = threadIdx.x; j < vid; j += kEmitBlock) pre += cp[j];
@@ -789,8 +821,12 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict
   uint32_t chunk_total;
   const uint32_t ex = block_exclusive_scan<kEmitBlock / 64>(cnt, &chunk_total);  // (its barriers publish s_pre)
   uint64_t prefix = 0;
+  if (scanned) {
+    prefix = ws_ptr<const uint64_t>(ws, h.ws.chunk_off)[vid];
+  } else {
 #pragma unroll
-  for (int w = 0; w < kEmitBlock / 64; ++w) prefix += s_pre[w];
+    for (int w = 0; w < kEmitBlock / 64; ++w) prefix += s_pre[w];
+  }
   if (vid == nb - 1 && threadIdx.x == 0) {
     const uint64_t need = prefix + chunk_total;
     st[S_PAIRS_LO] = (uint32_t)need;
@@ -1085,17 +1121,19 @@ void launch_depth_sort(const void *d_desc, const Header &h, void *ws, hipStream_
   hipLaunchKernelGGL(depth_plan_kernel, dim3(1), dim3(64), 0, s, d_desc, ws);
   uint32_t *keys[2] = {ws_ptr<uint32_t>(ws, h.ws.vis_key[0]), ws_ptr<uint32_t>(ws, h.ws.vis_key[1])};
   uint32_t *vals[2] = {ws_ptr<uint32_t>(ws, h.ws.vis_val[0]), ws_ptr<uint32_t>(ws, h.ws.vis_val[1])};
-  // (visible records rarely fill 4096-key chunks on every workgroup of the
-  // chip: the depth sort takes 1024)
+  // (below four million records the visible ones rarely fill 4096-key
+  // chunks on every workgroup of the chip: the depth sort takes 1024 there)
   radix_sort(keys, vals, h.n_records, st + S_NVIS, 32, st + S_PLAN_DEPTH, 1, ws_ptr<uint32_t>(ws, h.ws.dhist),
-             ws_ptr<uint32_t>(ws, h.ws.rtable), st, S_DEPTH_CUR, false, s);
+             ws_ptr<uint32_t>(ws, h.ws.rtable), st, S_DEPTH_CUR, h.n_records >= (1ull << 22), s);
 }
 
 void launch_emit(const void *d_desc, const Header &h, void *ws, hipStream_t s) {
   if (h.n_records == 0) return;
   const dim3 grid((unsigned)emit_chunks_of(h.n_records));
   hipLaunchKernelGGL(chunk_pairs_kernel, grid, dim3(kEmitChunk / 4), 0, s, d_desc, ws);
-  hipLaunchKernelGGL(emit_kernel, grid, dim3(kEmitBlock), 0, s, d_desc, ws);
+  const int scanned = emit_chunks_of(h.n_records) > kEmitDirectChunks ? 1 : 0;
+  if (scanned) hipLaunchKernelGGL(chunk_prefix_kernel, dim3(1), dim3(1024), 0, s, d_desc, ws);
+  hipLaunchKernelGGL(emit_kernel, grid, dim3(kEmitBlock), 0, s, d_desc, ws, scanned);
 }
 
 void launch_tile_sort(const void *d_desc, const Header &h, void *ws, hipStream_t s) {

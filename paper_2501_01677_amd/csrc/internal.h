@@ -110,6 +110,7 @@ struct Layout {
   uint64_t qhist;                // the same for the queue sort
   uint64_t zero_end;
   uint64_t chunk_pairs;          // uint32 [records / kEmitChunk] pairs of each chunk of depth-sorted records
+  uint64_t chunk_off;            // uint64 [records / kEmitChunk] their exclusive prefix (large batches)
   uint64_t rtable;               // uint32 [256][chunks] radix chunk offsets
   uint64_t qkey[2], qval0;       // queue sort buffers (the result lands in `queue`)
   uint64_t stats;

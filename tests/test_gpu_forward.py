@@ -160,7 +160,7 @@ RECT_KINDS = {"small": ((300, 200), (4, 3), 64), "mid": ((600, 400), (11, 8), 20
                                              (20_000, 7, "mid", False), (20_000, 8, "mid", True),
                                              (3_000, 3, "wide", False), (8_000, 4, "wide", False),
                                              (8_000, 4, "wide", True), (60_000, 5, "wide", False),
-                                             (60_000, 6, "wide", True)])
+                                             (60_000, 6, "wide", True), (2_100_000, 9, "small", False)])
 def test_binning_bit_exact_on_synthetic_rects(n, seed, kind, det):
     """small: waves of fewer than 256 pairs (emission's balanced form).  mid:
     rectangles up to 8 rows x 11 columns, so waves of several hundred pairs
@@ -169,8 +169,10 @@ def test_binning_bit_exact_on_synthetic_rects(n, seed, kind, det):
     rectangles too large to stage (more than 8 rows or 32 columns).  The pair
     capacities select both radix chunk sizes (1024 keys, and 4096 from 2^19
     keys); the 60000-record cases hold tile lists of several thousand pairs.
-    det: the deterministic configuration, whose tile sort carries emission
-    indices."""
+    The 4.2M-record case takes the depth sort's 4096-key chunks and the
+    emission's one-workgroup scan of the per-chunk pair totals (more than
+    2048 chunks).  det: the deterministic configuration, whose tile sort
+    carries emission indices."""
     print(f"[case] binning n={n} kind={kind} det={det}", flush=True)
     tile = 16
     (W, H), (mw, mh), cap = RECT_KINDS[kind]
