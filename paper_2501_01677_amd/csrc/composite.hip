@@ -569,10 +569,10 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
   // dL/d(soft count): every blended fragment's alpha enters the pixel's
   // soft count with weight 1 (the count output's gradient)
   float gcount = 0.f;
-  // GS = sum_c g_c S_c, S_c the blended features behind the current fragment
-  // (plus the background term): dL/dalpha only needs this dot product, so it
-  // is kept instead of the seven suffix sums.
-  float GS = 0.f;
+  // H = g_alpha T_final - sum_c g_c S_c, S_c the blended features behind the
+  // current fragment (plus the background term): dL/dalpha only needs this
+  // difference, so it is kept instead of the seven suffix sums.
+  float H = 0.f;
   if (masked) {
     last = ws_ptr<int32_t>(ws, h.ws.pix_last)[rd.pixel_offset + pix];
     Tf = ws_ptr<float>(ws, h.ws.pix_T)[rd.pixel_offset + pix];
@@ -606,9 +606,8 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
         gch[5] += k;
       }
     }
-    GS = Tf * (gch[0] * h.cfg.bg[0] + gch[1] * h.cfg.bg[1] + gch[2] * h.cfg.bg[2]);
+    H = ga * Tf - Tf * (gch[0] * h.cfg.bg[0] + gch[1] * h.cfg.bg[1] + gch[2] * h.cfg.bg[2]);
   }
-  const float gaTf = ga * Tf;  // g_alpha T_final
   // the tile's largest last-blended index (with MM from a wave maximum by
   // lane exchanges and one LDS atomic per wave; the lane-exchange form keeps
   // per-lane atomics, whose registers it cannot spare)
@@ -652,12 +651,25 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
   const float bcx = g.ox + 3.5f, bcy = g.oy + 3.5f;  // block centre
   const uint32_t fields = slot_fields(lane >> 4);
   int nb = 0;  // buffered records (uniform)
+  // Lane b < nb holds the slot (koff) of buffered record b; its id and 2D
+  // mean are copied to acc.info by lanes [ninfo, nb) before a flush or the
+  // next batch's staging (one masked write per group, not per record).
+  uint32_t bkoff = 0u;
+  int ninfo = 0;  // (uniform)
   for (int64_t bend = end; bend > (int64_t)rg.x; bend -= NT) {
     const uint32_t bstart = (uint32_t)max((int64_t)rg.x, bend - NT);
     const int cnt = (int)((uint32_t)bend - bstart);
     __syncthreads();
     stage_batch<NT, true>(rec4, vals, bstart, (uint32_t)bend, sb);
     __syncthreads();
+    const auto copy_info = [&](int upto) {
+      if (lane >= ninfo && lane < upto) {
+        const float4 r0 = plane_at<NT>(sb, bkoff, 0);
+        const uint32_t id = DET ? bstart + (bkoff >> 4) : __float_as_uint(plane_at<NT>(sb, bkoff, 4).w);
+        acc.info[lane] = make_float4(__uint_as_float(id), r0.x, r0.y, 0.f);
+      }
+      ninfo = upto;
+    };
     if (MM ? wlast >= (int32_t)bstart : __ballot(last >= (int32_t)bstart) != 0ull) {
       const int len = build_list<NT>(sb, MM ? min(cnt, wlast - (int32_t)bstart + 1) : cnt, g.ox, g.oy, l2min, list);
       nev += (uint32_t)len;
@@ -690,8 +702,8 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
             Gf = fmaf(gch[c], f[c], Gf);
             v[6 + c] = w * gch[c];
           }
-          const float dLda = Tp * Gf + (gaTf - GS) * iom + gcount;
-          GS = contrib ? fmaf(w, Gf, GS) : GS;
+          const float dLda = fmaf(Tp, Gf, fmaf(H, iom, gcount));
+          H = contrib ? fmaf(-w, Gf, H) : H;
           Tr = contrib ? Tp : Tr;
           // alpha = o G with G = exp(-q/2): dalpha/do = G = alpha / o,
           // dalpha/dq = -alpha / 2 (zero on the clamped side of alpha_max)
@@ -717,7 +729,7 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
       } else {
         // Back to front.  A lane that does not blend the fragment takes alpha
         // = 0: its weight w and its dL/dq entry vanish, its transmittance
-        // and suffix sum are unchanged (T / (1 - 0) = T and GS + 0 Gf = GS
+        // and suffix term are unchanged (T / (1 - 0) = T and H - 0 Gf = H
         // exactly), so the recurrences need no per-value selects.
         // the pixel's last blended index as a byte offset into the batch
         // planes (below 0: none of the batch)
@@ -726,7 +738,7 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
           const float ex = lane_exponent(e, abc, g.L);
           const bool contrib = (int32_t)e.koff <= lastoff && ex >= l2min;
           if (__ballot(contrib) == 0ull) return;
-          const float4 r0 = plane_at<NT>(sb, e.koff, 0), r1 = plane_at<NT>(sb, e.koff, 1);
+          const float4 r1 = plane_at<NT>(sb, e.koff, 1);
           const float4 r2 = plane_at<NT>(sb, e.koff, 2), r3 = plane_at<NT>(sb, e.koff, 3);
           const float raw = __builtin_amdgcn_exp2f(ex);
           const float a = contrib ? __builtin_amdgcn_fmed3f(raw, 0.f, amax) : 0.f;  // min(raw, amax), raw >= 0
@@ -739,8 +751,8 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
           float Gf = 0.f;
 #pragma unroll
           for (int c = 0; c < 7; ++c) Gf = fmaf(gch[c], f[c], Gf);
-          const float dLda = Tp * Gf + (gaTf - GS) * iom + gcount;
-          GS = fmaf(w, Gf, GS);
+          const float dLda = fmaf(Tp, Gf, fmaf(H, iom, gcount));
+          H = fmaf(-w, Gf, H);
           Tr = Tp;
           // alpha = o G with G = exp(-q/2): dalpha/do = G = alpha / o,
           // dalpha/dq = -alpha / 2 (zero on the clamped side of alpha_max)
@@ -751,15 +763,15 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
           const int col = lane ^ (nb << 2);
           acc.a[nb][col] = w;
           acc.a[8 + nb][col] = a * gate;
-          if (lane == 0)
-            acc.info[nb] = make_float4(__uint_as_float(DET ? bstart + (e.koff >> 4) : __float_as_uint(abc.w)), r0.x,
-                                       r0.y, 0.f);
+          bkoff = lane == nb ? e.koff : bkoff;
           if (++nb == 8) {
             nact += 8;
+            copy_info(8);
             __builtin_amdgcn_wave_barrier();
             flush_records<STRIDE, DET>(acc, 8, bf, fields, bcx, bcy, dst);
             __builtin_amdgcn_wave_barrier();
             nb = 0;
+            ninfo = 0;
           }
         };
         // the next entry is read while this one is evaluated (its
@@ -771,6 +783,7 @@ __device__ __forceinline__ void backward_tile(const void *__restrict__ desc, con
           step(e, plane_at<NT>(sb, e.koff, 4));
           e = en;
         }
+        copy_info(nb);  // the batch's slots are restaged next
       }
     }
   }
