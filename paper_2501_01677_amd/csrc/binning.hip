@@ -30,9 +30,10 @@
 // look-back).  Waits only ever point backwards, to workgroups that are
 // resident and do not wait on later ones, so they end; a bounded spin sets
 // an error word instead of waiting forever.  Radix passes use
-// reduce-then-scan (chunk digit counts, a per-digit scan, a scatter) with
-// digit histograms accumulated by the kernel that produced the keys, in
-// kHistCopies copies (fewer same-word atomics).
+// reduce-then-scan (chunk digit counts, a per-digit scan, a scatter).  The
+// digit histograms the scan needs are accumulated by the compaction (depth
+// keys, all passes at once, so the plan can skip passes) or by each pass's
+// count kernel (tile ids), in kHistCopies copies (fewer same-word atomics).
 #include "internal.h"
 
 namespace pgsag {
@@ -461,12 +462,14 @@ __device__ inline PassPlan plan_pass(const uint32_t *plan_word, int pass, int pa
 }
 
 // Pass part 1: digit counts of every chunk -> table[digit][chunk].  NW
-// waves of RI keys per thread: chunks of 64 NW RI keys.
+// waves of RI keys per thread: chunks of 64 NW RI keys.  With `hist`, the
+// chunk's counts are also added to the pass's digit histogram (copy chunk
+// mod kHistCopies), which the digit scan reads next.
 template <int RI, int NW>
 __global__ void __launch_bounds__(64 * NW) chunk_count_kernel(const uint32_t *keys0, const uint32_t *keys1,
                                                               const uint32_t *n_dev, uint64_t n_bound, int pass,
                                                               int passes, int dbits, const uint32_t *plan_word,
-                                                              uint32_t *table, uint32_t nb_bound) {
+                                                              uint32_t *table, uint32_t nb_bound, uint32_t *hist) {
   constexpr int NT = 64 * NW;
   __shared__ uint32_t hs[kRadixBins];
   const PassPlan pp = plan_pass(plan_word, pass, passes);
@@ -491,7 +494,11 @@ __global__ void __launch_bounds__(64 * NW) chunk_count_kernel(const uint32_t *ke
   for (int r = 0; r < RI; ++r)
     if (base + (uint64_t)r * NT + threadIdx.x < n) atomicAdd(&hs[(kk[r] >> shift) & dmask], 1u);
   __syncthreads();
-  if (threadIdx.x <= dmask) table[(uint64_t)threadIdx.x * nb_bound + c] = hs[threadIdx.x];
+  if (threadIdx.x <= dmask) {
+    const uint32_t v = hs[threadIdx.x];
+    table[(uint64_t)threadIdx.x * nb_bound + c] = v;
+    if (hist && v) atomicAdd(&hist[(c % kHistCopies) * kHistStride + pass * kRadixBins + threadIdx.x], v);
+  }
 }
 
 // Pass part 2: per digit, exclusive scan of its chunk counts along the
@@ -671,19 +678,22 @@ __global__ void __launch_bounds__(64 * NW) chunk_scatter_kernel(uint32_t *keys0,
 // Sorts (keys, vals) in buffers [0] by `bits` low key bits, stably.  With a
 // plan word (written on the device before the sort) passes it marks are
 // skipped and the result buffer is published in st[cur_word]; otherwise it
-// is buffer (passes & 1).  With `hist_ready` the digit histograms were
-// accumulated by the kernel that produced the keys.  `table` holds uint32
-// [256][chunks].
+// is buffer (passes & 1).  The digit histograms (`hist`, zeroed before the
+// sort) come from `hist_mode`: kHistByProducer, accumulated by the kernel
+// that produced the keys; kHistByCount, by each pass's count kernel;
+// kHistByPass, by one extra read of the keys before the first pass.
+// `table` holds uint32 [256][chunks].
+enum HistMode { kHistByPass = 0, kHistByProducer = 1, kHistByCount = 2 };
 template <int RI>
 void radix_passes(uint32_t *keys[2], uint32_t *vals[2], uint64_t n_bound, const uint32_t *n_dev, int passes, int dbits,
-                  const uint32_t *plan_word, uint32_t *hist, uint32_t *table, uint32_t *st, int cur_word,
-                  hipStream_t s) {
+                  const uint32_t *plan_word, uint32_t *hist, bool count_hist, uint32_t *table, uint32_t *st,
+                  int cur_word, hipStream_t s) {
   // eight waves per chunk: each ranks 64 RI keys of the chunk
   constexpr uint32_t chunk = RI * 64 * 8;
   const uint32_t nb = (uint32_t)((n_bound + chunk - 1) / chunk);
   for (int p = 0; p < passes; ++p) {
     hipLaunchKernelGGL((chunk_count_kernel<RI, 8>), dim3(nb), dim3(512), 0, s, keys[0], keys[1], n_dev, n_bound, p,
-                       passes, dbits, plan_word, table, nb);
+                       passes, dbits, plan_word, table, nb, count_hist ? hist : nullptr);
     hipLaunchKernelGGL(chunk_scan_kernel, dim3(1u << dbits), dim3(kDigitScanBlock), 0, s, n_dev, n_bound, p, passes,
                        plan_word, (const uint32_t *)hist, table, nb, chunk);
     hipLaunchKernelGGL((chunk_scatter_kernel<RI, 8>), dim3(nb), dim3(512), 0, s, keys[0], vals[0], keys[1], vals[1],
@@ -694,20 +704,21 @@ void radix_passes(uint32_t *keys[2], uint32_t *vals[2], uint64_t n_bound, const 
 // `big`: chunks of 4096 keys (fewer workgroups, longer per-digit runs,
 // better coalesced scatters) rather than 1024 (more workgroups).
 void radix_sort(uint32_t *keys[2], uint32_t *vals[2], uint64_t n_bound, const uint32_t *n_dev, int bits,
-                const uint32_t *plan_word, int hist_ready, uint32_t *hist, uint32_t *table, uint32_t *st,
+                const uint32_t *plan_word, int hist_mode, uint32_t *hist, uint32_t *table, uint32_t *st,
                 int cur_word, bool big, hipStream_t s) {
   const int passes = (bits + kRadixBits - 1) / kRadixBits;
   const int dbits = digit_bits_for((uint32_t)bits);
   if (n_bound == 0 || passes == 0) return;
-  if (!hist_ready) {
+  if (hist_mode == kHistByPass) {
     const uint64_t hb64 = (n_bound + kRadixChunk - 1) / kRadixChunk;
     const unsigned hb = hb64 < 2048 ? (unsigned)hb64 : 2048u;
     hipLaunchKernelGGL(digit_hist_kernel, dim3(hb), dim3(256), 0, s, keys[0], n_dev, n_bound, passes, dbits, hist);
   }
+  const bool count_hist = hist_mode == kHistByCount;
   if (big)
-    radix_passes<8>(keys, vals, n_bound, n_dev, passes, dbits, plan_word, hist, table, st, cur_word, s);
+    radix_passes<8>(keys, vals, n_bound, n_dev, passes, dbits, plan_word, hist, count_hist, table, st, cur_word, s);
   else
-    radix_passes<2>(keys, vals, n_bound, n_dev, passes, dbits, plan_word, hist, table, st, cur_word, s);
+    radix_passes<2>(keys, vals, n_bound, n_dev, passes, dbits, plan_word, hist, count_hist, table, st, cur_word, s);
 }
 
 // -------------------------------------------------------------- emission
@@ -776,14 +787,11 @@ __global__ void __launch_bounds__(1024) chunk_prefix_kernel(const void *__restri
 // of its pair with a six-step search over the lanes' prefix offsets
 // (shuffles) and the k-th active tile of that record's rectangle from the
 // per-row active-tile bit masks.  Work per lane is balanced whatever the
-// spread of rectangle sizes.  The digit histograms of the emitted tile ids
-// (for the tile sort) are accumulated on the way.
+// spread of rectangle sizes.
 constexpr uint32_t kSegRows = 8;  // rectangle rows staged per record in emission
 constexpr uint32_t kRowLaneBits = 12;       // widest row (active tiles) of the row-lane emission
 constexpr uint32_t kRowLaneMinPairs = 256;  // fewest pairs of a wave in the row-lane emission
-// 16 waves per workgroup: the workgroup's digit histogram goes to the global
-// one once per 1024 records (these few hundred words take every workgroup's
-// atomics).
+// 16 waves per workgroup (one workgroup per emission chunk).
 constexpr int kEmitBlock = kEmitChunk;
 __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict__ desc, void *__restrict__ ws,
                                                           int scanned) {
@@ -793,14 +801,7 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict
   const uint32_t nb = (uint32_t)emit_chunks_of(nvis);
   const uint32_t vid = blockIdx.x;
   if (vid >= nb) return;  // (uniform per workgroup)
-  __shared__ uint32_t hs[4][kRadixBins];
   __shared__ uint32_t s_seg[kEmitBlock / 64][64][kSegRows];  // per wave, per owner record: row bits of its rectangle
-  const int passes = tile_passes(h.tile_bits);
-  const int tdb = digit_bits_for(h.tile_bits);
-  const uint32_t tmask = (1u << tdb) - 1u;
-  if (threadIdx.x < kRadixBins)
-    for (int q = 0; q < 4; ++q) hs[q][threadIdx.x] = 0;
-  __syncthreads();
   const int lane = threadIdx.x & 63;
   const uint64_t cap = h.pair_capacity;
   const uint64_t i = (uint64_t)vid * kEmitBlock + threadIdx.x;
@@ -939,7 +940,6 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict
             } else {
               val_out[e] = orec;
             }
-            for (int q = 0; q < passes; ++q) atomicAdd(&hs[q][(gt >> (tdb * q)) & tmask], 1u);
           }
           ++e;
         }
@@ -1017,16 +1017,10 @@ __global__ void __launch_bounds__(kEmitBlock) emit_kernel(const void *__restrict
           } else {
             val_out[e] = orec;
           }
-          for (int q = 0; q < passes; ++q) atomicAdd(&hs[q][(gt >> (tdb * q)) & tmask], 1u);
         }
       }
     }
   }
-  __syncthreads();
-  uint32_t *th = ws_ptr<uint32_t>(ws, h.ws.thist) + (vid % kHistCopies) * kHistStride;
-  if (threadIdx.x < kRadixBins)
-    for (int q = 0; q < passes; ++q)
-      if (hs[q][threadIdx.x]) atomicAdd(&th[q * kRadixBins + threadIdx.x], hs[q][threadIdx.x]);
 }
 
 // Deterministic mode: the tile sort has carried every pair's emission index
@@ -1123,7 +1117,7 @@ void launch_depth_sort(const void *d_desc, const Header &h, void *ws, hipStream_
   uint32_t *vals[2] = {ws_ptr<uint32_t>(ws, h.ws.vis_val[0]), ws_ptr<uint32_t>(ws, h.ws.vis_val[1])};
   // (below four million records the visible ones rarely fill 4096-key
   // chunks on every workgroup of the chip: the depth sort takes 1024 there)
-  radix_sort(keys, vals, h.n_records, st + S_NVIS, 32, st + S_PLAN_DEPTH, 1, ws_ptr<uint32_t>(ws, h.ws.dhist),
+  radix_sort(keys, vals, h.n_records, st + S_NVIS, 32, st + S_PLAN_DEPTH, kHistByProducer, ws_ptr<uint32_t>(ws, h.ws.dhist),
              ws_ptr<uint32_t>(ws, h.ws.rtable), st, S_DEPTH_CUR, h.n_records >= (1ull << 22), s);
 }
 
@@ -1140,7 +1134,7 @@ void launch_tile_sort(const void *d_desc, const Header &h, void *ws, hipStream_t
   uint32_t *st = ws_ptr<uint32_t>(ws, h.ws.status);
   uint32_t *keys[2] = {ws_ptr<uint32_t>(ws, h.ws.pair_key[0]), ws_ptr<uint32_t>(ws, h.ws.pair_key[1])};
   uint32_t *vals[2] = {ws_ptr<uint32_t>(ws, h.ws.pair_val[0]), ws_ptr<uint32_t>(ws, h.ws.pair_val[1])};
-  radix_sort(keys, vals, h.pair_capacity, st + S_NPAIRS, (int)h.tile_bits, nullptr, 1,
+  radix_sort(keys, vals, h.pair_capacity, st + S_NPAIRS, (int)h.tile_bits, nullptr, kHistByCount,
              ws_ptr<uint32_t>(ws, h.ws.thist), ws_ptr<uint32_t>(ws, h.ws.rtable), st, -1,
              h.pair_capacity >= (1ull << 19), s);
   if (h.cfg.deterministic)
@@ -1154,7 +1148,7 @@ void launch_tile_sort(const void *d_desc, const Header &h, void *ws, hipStream_t
     hipLaunchKernelGGL(queue_key_kernel, dim3(blocks_for(h.n_tiles)), dim3(256), 0, s, d_desc, ws);
     uint32_t *qk[2] = {ws_ptr<uint32_t>(ws, h.ws.qkey[0]), ws_ptr<uint32_t>(ws, h.ws.qkey[1])};
     uint32_t *qv[2] = {ws_ptr<uint32_t>(ws, h.ws.qval0), ws_ptr<uint32_t>(ws, h.ws.queue)};
-    radix_sort(qk, qv, h.n_tiles, nullptr, kRadixBits, nullptr, 0, ws_ptr<uint32_t>(ws, h.ws.qhist),
+    radix_sort(qk, qv, h.n_tiles, nullptr, kRadixBits, nullptr, kHistByPass, ws_ptr<uint32_t>(ws, h.ws.qhist),
                ws_ptr<uint32_t>(ws, h.ws.rtable), st, -1, false, s);
   }
 }
