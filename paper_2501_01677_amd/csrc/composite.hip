@@ -266,17 +266,19 @@ __device__ void forward_tile(const void *__restrict__ desc, const Header &h, voi
   const float amax = h.cfg.alpha_max, tmin = h.cfg.t_min;
   const float l2min = __log2f(h.cfg.alpha_min);
   FwdEntry *list = lists[threadIdx.x >> 6];
-  bool done = !masked;
   uint32_t nev = 0;  // list entries this wave evaluated (each for all its 64 lanes)
-  float Tr = 1.f;
+  // The transmittance carries the lane's state in its sign: negative once
+  // the lane has stopped (or for an unmasked pixel), so a stopped lane's
+  // next candidate transmittance is negative too and it never blends again.
+  float Tr = masked ? 1.f : -1.f;
   float F[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   int32_t n = 0, last = -1;
   for (uint32_t b = rg.x; b < rg.y; b += NT) {
-    if (__syncthreads_count(!done) == 0) break;
+    if (__syncthreads_count(Tr > 0.f) == 0) break;
     const uint32_t b1 = min(rg.y, b + NT);
     stage_batch<NT, false>(rec4, vals, b, b1, srec);
     __syncthreads();
-    if (__ballot(!done) == 0ull) continue;
+    if (__ballot(Tr > 0.f) == 0ull) continue;
     const int len = build_list<NT>(srec, (int)(b1 - b), g.ox, g.oy, l2min, list);
     // Branch-free over the lanes (selects, no divergent blocks).  The slot
     // of the last blended record of this batch is kept and turned into the
@@ -284,15 +286,17 @@ __device__ void forward_tile(const void *__restrict__ desc, const Header &h, voi
     int lastk = -1;
     const auto eval = [&](const FwdEntry &e) {
       const float ex = lane_exponent(e, g.L);
-      const bool pass = !done && ex >= l2min;
+      const bool pass = ex >= l2min;
       // exp2 >= 0: the median of (x, 0, amax) is min(x, amax) in one instruction
       const float a = __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(ex), 0.f, amax);
-      const float Tn = Tr * (1.f - a);
-      const bool stop = pass && Tn < tmin;
-      const bool blend = pass && !stop;
+      const float aT = a * Tr;
+      const float Tn = Tr - aT;
+      const bool low = Tn < tmin;
+      const bool stop = pass && low;
+      const bool blend = pass && !low;
       const float4 r1 = field_of<NT>(srec, e, 1), r2 = field_of<NT>(srec, e, 2);
       const float d = field_of<NT>(srec, e, 3).x;
-      const float w = blend ? a * Tr : 0.f;
+      const float w = blend ? aT : 0.f;
       F[0] = fmaf(w, r1.z, F[0]);
       F[1] = fmaf(w, r1.w, F[1]);
       F[2] = fmaf(w, r2.x, F[2]);
@@ -300,10 +304,9 @@ __device__ void forward_tile(const void *__restrict__ desc, const Header &h, voi
       F[4] = fmaf(w, r2.z, F[4]);
       F[5] = fmaf(w, r2.w, F[5]);
       F[6] = fmaf(w, d, F[6]);
-      Tr = blend ? Tn : Tr;
+      Tr = blend ? Tn : (stop ? -fabsf(Tr) : Tr);
       n += blend ? 1 : 0;
       lastk = blend ? (int)e.koff : lastk;
-      done = done || stop;
     };
     // two entries per iteration: `e` is loop-carried and reloaded after
     // its evaluation, `f` is loaded and used within the iteration
@@ -319,7 +322,7 @@ __device__ void forward_tile(const void *__restrict__ desc, const Header &h, voi
       e = list[t + 2 < len ? t + 2 : t + 1];
       eval(f);
       t += 2;
-      if ((t & 7) == 0 && __ballot(!done) == 0ull) break;
+      if ((t & 7) == 0 && __ballot(Tr > 0.f) == 0ull) break;
     }
     nev += (uint32_t)t;
     if (lastk >= 0) last = (int32_t)(b + ((uint32_t)lastk >> 4));
@@ -327,6 +330,7 @@ __device__ void forward_tile(const void *__restrict__ desc, const Header &h, voi
   // work counter of this (tile, wave): [0] forward entries evaluated
   if ((threadIdx.x & 63) == 0)
     ws_ptr<uint32_t>(ws, h.ws.work)[((uint64_t)tile * ((T / 8) * (T / 8)) + (threadIdx.x >> 6)) * 3] = nev;
+  Tr = fabsf(Tr);
   if (!g.inside) return;
   const uint64_t HW = (uint64_t)rd.cam.H * W;
   float rgb0 = 0.f, rgb1 = 0.f, rgb2 = 0.f, alpha = 0.f, depth = 0.f;
