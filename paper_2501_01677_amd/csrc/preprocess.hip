@@ -279,6 +279,11 @@ __global__ void __launch_bounds__(256) preprocess_kernel(const void *__restrict_
   const int64_t n = S.n;
   Raw g;
   load_raw(S, i, g);
+  // The SH coefficients (most of the bytes) are loaded once per Gaussian,
+  // with the other parameters, and serve every view below.
+  float shc[3 * K];
+#pragma unroll
+  for (int j = 0; j < 3 * K; ++j) shc[j] = S.sh[j * n + i];
   float4 *rec4 = ws_ptr<float4>(ws, h.ws.rec);
   uint32_t *dkey = ws_ptr<uint32_t>(ws, h.ws.depth_key);
   uint2 *rect = ws_ptr<uint2>(ws, h.ws.rect);
@@ -295,9 +300,8 @@ __global__ void __launch_bounds__(256) preprocess_kernel(const void *__restrict_
     uint32_t count = 0;
     uint2 rr = make_uint2(0u, 0u);
     if (key > h.cfg.z_near && opaque_enough) {
-      // Colour first: it needs only the view direction, so the SH
-      // coefficient loads (most of the bytes) are in flight while the
-      // projection and the support rectangle are computed.
+      // Colour first: it needs only the view direction, so its arithmetic
+      // overlaps the projection's.
       float col[3];
       {
         const float dx = g.mx - c.centre[0], dy = g.my - c.centre[1], dz = g.mz - c.centre[2];
@@ -308,7 +312,7 @@ __global__ void __launch_bounds__(256) preprocess_kernel(const void *__restrict_
         for (int k = 0; k < 3; ++k) {
           float a = 0.5f;
 #pragma unroll
-          for (int j = 0; j < K; ++j) a += B[j] * S.sh[(3 * j + k) * n + i];
+          for (int j = 0; j < K; ++j) a += B[j] * shc[3 * j + k];
           col[k] = fmaxf(a, 0.f);
         }
       }
