@@ -495,7 +495,11 @@ int run_backward(const Header *h, const void *dev_desc, void *workspace, const A
   StageTimer tm{events, s};
   // float atomics add into the 2D-gradient slots; the deterministic
   // reduction stores every slot the backward projection reads
-  if (!h->cfg.deterministic) launch_fill_u32(ws_ptr<uint32_t>(workspace, h->ws.g2), 0u, h->n_records * kG2, s);
+  // the 2D-gradient slots start at zero; the forward compositing has
+  // usually cleared them already (then this pass writes nothing)
+  if (!h->cfg.deterministic)
+    launch_fill_u32(ws_ptr<uint32_t>(workspace, h->ws.g2), 0u, h->n_records * kG2, s,
+                    ws_ptr<uint32_t>(workspace, h->ws.status) + S_G2_CLEAN);
   if (h->cfg.persistent) launch_fill_u32(ws_ptr<uint32_t>(workspace, h->ws.status) + S_QUEUE_BWD, 0u, 1, s);
   if (h->cfg.deterministic) launch_det_clear(dev_desc, *h, workspace, s);
   tm.begin(PGSAG_STAGE_BACKWARD_COMPOSITE);

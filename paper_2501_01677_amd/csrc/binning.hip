@@ -44,8 +44,10 @@ __device__ inline uint32_t *status_of(void *ws, const Header &h) {
 }
 
 // n words of p set to value: 16-byte stores over the 16-byte aligned body,
-// single words before and after it.
-__global__ void fill_u32_kernel(uint32_t *p, uint32_t value, uint64_t n) {
+// single words before and after it.  Nothing is written when `skip` points
+// to a non-zero word.
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t value, uint64_t n, const uint32_t *skip) {
+  if (skip && *skip) return;
   const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const uint64_t lead = (uint64_t)((16u - ((uintptr_t)p & 15u)) & 15u) / 4u;
@@ -1091,12 +1093,12 @@ inline unsigned blocks_for(uint64_t n, unsigned bs = 256) { return (unsigned)((n
 
 }  // namespace
 
-void launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t s) {
+void launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t s, const uint32_t *skip) {
   if (n == 0) return;
   uint64_t blocks = (n / 4 + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, value, n);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, value, n, skip);
 }
 
 void launch_tile_mask(const void *d_desc, const Header &h, void *ws, hipStream_t s) {

@@ -830,6 +830,16 @@ __global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(8))) 
   FwdEntry (*lists)[NT] = sm.lists;
   uint32_t &s_item = sm.item;
   const Header &h = *header(desc);
+  if (h.any_grads && !h.cfg.deterministic) {
+    // The backward's 2D-gradient slots are cleared here, spread over the
+    // grid: this kernel is bound by its arithmetic, so the stores cost
+    // little, and the backward then skips its own clearing pass.
+    uint4 *g2 = ws_ptr<uint4>(ws, h.ws.g2);
+    const uint64_t nv = h.n_records * (uint64_t)kG2 / 4;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (uint64_t)gridDim.x * blockDim.x)
+      g2[v] = make_uint4(0u, 0u, 0u, 0u);
+    if (blockIdx.x == 0 && threadIdx.x == 0) ws_ptr<uint32_t>(ws, h.ws.status)[S_G2_CLEAN] = 1u;
+  }
   if (!h.cfg.persistent) {
     forward_tile<T>(desc, h, ws, blockIdx.x, sb, lists, vals);
     return;
@@ -867,6 +877,8 @@ __global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(MM ? 
   __shared__ int smax;
   __shared__ uint32_t s_item;
   const Header &h = *header(desc);
+  // the slots this pass accumulates into are no longer clean for the next one
+  if (blockIdx.x == 0 && threadIdx.x == 0) ws_ptr<uint32_t>(ws, h.ws.status)[S_G2_CLEAN] = 0u;
   if (!h.cfg.persistent) {
     backward_tile<T, MM, DET>(desc, h, ws, blockIdx.x, sb, lists, accs, &smax, vals);
     return;

@@ -126,6 +126,7 @@ enum StatusField {
   S_DEPTH_CUR = 8,   // which vis buffer holds the depth-sorted records
   S_ERROR = 9,       // non-zero if a look-back wait gave up (results invalid)
   S_PLAN_DEPTH = 10, // bit p set: depth-sort pass p is skipped (one digit for every key)
+  S_G2_CLEAN = 11,   // non-zero: the forward compositing has cleared the 2D-gradient slots
   S_CTR_COMPACT = 16,  // chunk tickets of the compaction's look-back scan
   S_WORDS = 64
 };
@@ -203,7 +204,8 @@ int hip_status(const char *where);
 
 // ---------------------------------------------------------------- launches
 // Host-side launch helpers, defined in the kernel translation units.
-void launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t s);
+// (skip: a device word; when it is non-zero at run time nothing is written)
+void launch_fill_u32(uint32_t *p, uint32_t value, uint64_t n, hipStream_t s, const uint32_t *skip = nullptr);
 void launch_tile_mask(const void *d_desc, const Header &h, void *ws, hipStream_t s);
 void launch_preprocess(const void *d_desc, const Header &h, void *ws, hipStream_t s);
 void launch_recount(const void *d_desc, const Header &h, void *ws, hipStream_t s);
